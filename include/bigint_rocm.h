@@ -1,0 +1,207 @@
+/*
+ * bigint_rocm.h -- C-ABI of a batched big-integer library for AMD MI355X
+ * (gfx950).
+ *
+ * Method: C. E. Oancea and S. M. Watt, "High-Level Big Integer Arithmetic in
+ * Futhark for GPUs".  Many independent unsigned integers of 2^15..2^19 bits
+ * are processed at once, one work-group per instance (Section 2: an instance
+ * fits one work-group, each work-item owning Q digits).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Limbs:      little-endian u32 limbs, instance-major: instance i of a
+ *             uniform batch occupies limbs [i*n, (i+1)*n).  An array of u64
+ *             digits is byte-identical to a u32 array of twice the length.
+ * Ragged:     a flat limb array plus an int64 prefix-offset array `off` of
+ *             length batch+1 in DEVICE memory; instance i is
+ *             flat[off[i] .. off[i+1]).
+ * Memory:     every data pointer is a DEVICE pointer (hipMalloc / torch CUDA
+ *             tensor) unless the parameter says "host".  The caller owns all
+ *             buffers; the library never frees caller memory.
+ * Streams:    `stream` is a hipStream_t passed as void* (NULL = the null
+ *             stream).  Calls only enqueue work on it; they do not
+ *             synchronise the device, so outputs are valid once the stream
+ *             has reached that point.
+ * Errors:     0 = BIGINT_OK, negative = failure, and then nothing was
+ *             enqueued.  Argument checks happen on the host before any
+ *             launch.  Data-dependent conditions never fail a call (a zero
+ *             divisor is reported per instance).  No C++ exception crosses
+ *             this interface.  After BIGINT_EHIP, bigint_last_hip_error()
+ *             returns the hipError_t of the failing HIP call (per thread).
+ * Aliasing:   add/sub allow `out` == `a` or `out` == `b` exactly (in place);
+ *             any other overlap between an output and an input, and any
+ *             overlap between two outputs, is BIGINT_EINVAL.  mul and divmod
+ *             outputs must not overlap any input.
+ */
+#ifndef BIGINT_ROCM_H
+#define BIGINT_ROCM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ----------------------------------------------------------- */
+#define BIGINT_OK 0
+#define BIGINT_EINVAL (-1)       /* bad argument: null, size <= 0, overlap, ... */
+#define BIGINT_ENOMEM (-2)       /* device or host allocation failed            */
+#define BIGINT_EHIP (-3)         /* a HIP runtime call failed                   */
+#define BIGINT_EUNSUPPORTED (-4) /* size outside the supported range            */
+
+/* per-instance division status (the `status` output of divmod) */
+#define BIGINT_DIV_OK 0
+#define BIGINT_DIVZERO 1
+
+/* multiplication algorithms */
+#define BIGINT_MUL_AUTO 0  /* MFMA-split where supported, else plain        */
+#define BIGINT_MUL_PLAIN 1 /* u64-digit schoolbook convolution               */
+#define BIGINT_MUL_MFMA 2  /* 7-bit digits, int8 MFMA Toeplitz tiles         */
+
+/* plan operations */
+#define BIGINT_OP_MUL 1
+#define BIGINT_OP_DIVMOD 2
+
+/* plan flags */
+#define BIGINT_PLAN_DEFAULT 0
+#define BIGINT_PLAN_PLAIN 1   /* ragged multiply with the plain kernel        */
+#define BIGINT_PLAN_NO_GRAPH 2 /* launch directly instead of a hipGraph        */
+
+/* Largest operand (in u32 limbs) the MFMA-split multiply takes: both digit
+ * arrays of an instance must fit in one work-group's 160 KiB of LDS. */
+#define BIGINT_MFMA_MAX_LIMBS 16896
+
+typedef struct bigint_plan_s* bigint_plan_t;
+
+/* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
+int bigint_version(void);
+
+/* Static, NUL-terminated description of a status code (never NULL). */
+const char* bigint_strerror(int code);
+
+/* The hipError_t (as int) of the last HIP failure on this thread, 0 if none. */
+int bigint_last_hip_error(void);
+
+/* ---- addition and subtraction (Section 5.1) ----------------------------------
+ * The paper writes addition as map -> exclusive scan of (carry, all-ones)
+ * pairs -> map (Section 5.1, golden add and baddReg); subtraction is its
+ * mirror with borrows (bsubReg', used by the division step of Section 5.3).
+ *
+ * out[i]        = (a[i] + b[i]) mod 2^(32n)          (bigint_add)
+ *               = (a[i] - b[i]) mod 2^(32n)          (bigint_sub)
+ * carry_out[i]  = floor((a[i]+b[i]) / 2^(32n)) in {0,1}, or [a[i] < b[i]]
+ *                 for the borrow; carry_out may be NULL.
+ * a, b, out:    batch*n limbs.  carry_out: batch u32.
+ * n in [1, 65536], batch >= 0 (0 enqueues nothing).  n > 65536 is
+ * BIGINT_EUNSUPPORTED. */
+int bigint_add(uint32_t* out, uint32_t* carry_out, const uint32_t* a,
+               const uint32_t* b, int64_t n, int64_t batch, void* stream);
+int bigint_sub(uint32_t* out, uint32_t* borrow_out, const uint32_t* a,
+               const uint32_t* b, int64_t n, int64_t batch, void* stream);
+
+/* ---- multiplication (Section 5.2) --------------------------------------------
+ * out[i] = a[i] * b[i], the full (na+nb)-limb product.  The paper's quadratic
+ * formula C_k = sum_{i+j=k} A_i B_j (Section 5.2) is evaluated either
+ *   BIGINT_MUL_PLAIN: on u64 digits, each thread computing Q consecutive
+ *     outputs and their balancing partners (threadConv/halfConv), partial
+ *     sums kept as (low, high, carry) triples and resolved by one carry scan
+ *     (bmulReg: convolution, then baddReg of the low and shifted high parts);
+ *   BIGINT_MUL_MFMA: on 7-bit digits as a sum of Toeplitz-times-Hankel
+ *     int8 MFMA tiles with int32 accumulation (exact: every coefficient is at
+ *     most min(Na,Nb)*127^2 < 2^31), recombined in 64-bit columns and
+ *     resolved by the same carry scan.
+ * a: batch*na limbs, b: batch*nb limbs, out: batch*(na+nb) limbs.
+ * na, nb >= 1.  MFMA needs na, nb <= BIGINT_MFMA_MAX_LIMBS (else
+ * BIGINT_EUNSUPPORTED); PLAIN needs na+nb <= 32768; AUTO picks MFMA when it
+ * fits and na,nb >= 64, otherwise PLAIN. */
+int bigint_mul(uint32_t* out, const uint32_t* a, int64_t na, const uint32_t* b,
+               int64_t nb, int64_t batch, int algo, void* stream);
+
+/* ---- division (Section 5.3) ------------------------------------------------------
+ * q[i] = floor(u[i] / v[i]), r[i] = u[i] - q[i]*v[i], 0 <= r[i] < v[i].
+ * The quotient comes from the whole shifted inverse w = floor(B^h / v)
+ * (B = 2^32, h = precision of u) computed by Newton steps whose
+ * multiplications run on the MFMA-split multiply (Section 5.3, `step`), then
+ * q = floor(u*w / B^h) with one final correction.
+ * u: batch*nu limbs, v: batch*nv limbs, q: batch*nu limbs, r: batch*nv limbs,
+ * status: batch int32 or NULL.  A zero divisor gives status BIGINT_DIVZERO,
+ * q = 0 and r = u mod 2^(32 nv); the call itself still returns BIGINT_OK.
+ * nu, nv in [1, 8192] (else BIGINT_EUNSUPPORTED).  The call allocates its
+ * workspace with hipMallocAsync on `stream`. */
+int bigint_divmod(uint32_t* q, uint32_t* r, int32_t* status, const uint32_t* u,
+                  int64_t nu, const uint32_t* v, int64_t nv, int64_t batch,
+                  void* stream);
+
+/* ---- plans for ragged batches ------------------------------------------------------
+ * A plan fixes the instance sizes of a ragged batch (host arrays len_a, len_b
+ * of `batch` limb counts; for DIVMOD len_a are the dividend and len_b the
+ * divisor lengths), bins instances by cost, orders them largest first and
+ * picks a tuned tile configuration per bin (from the autotune cache if one
+ * was loaded, else built-in defaults).  Creating a plan allocates a small
+ * device schedule; the plan owns it until bigint_plan_destroy.
+ * Workspace: bigint_plan_workspace_size reports the device scratch a call
+ * needs; pass a buffer of at least that size with bigint_plan_set_workspace,
+ * otherwise the first call allocates one (owned by the plan).
+ * A plan must not be used by two streams at once. */
+int bigint_plan_create(bigint_plan_t* plan, int op, const int64_t* len_a,
+                       const int64_t* len_b, int64_t batch, int flags);
+int bigint_plan_workspace_size(bigint_plan_t plan, size_t* bytes);
+int bigint_plan_set_workspace(bigint_plan_t plan, void* dev, size_t bytes);
+int bigint_plan_destroy(bigint_plan_t plan);
+
+/* Ragged multiplication: out instance i = a instance i * b instance i, with
+ * out_off[i+1]-out_off[i] == (a_off[i+1]-a_off[i]) + (b_off[i+1]-b_off[i]);
+ * the limb counts must equal those given to bigint_plan_create (not checked
+ * on the device).  All instances run in one persistent launch fed by a
+ * device work queue, captured into a hipGraph and replayed on later calls
+ * with the same pointers (unless BIGINT_PLAN_NO_GRAPH).  Offsets are DEVICE
+ * int64 arrays of length batch+1. */
+int bigint_mul_ragged(uint32_t* out, const int64_t* out_off, const uint32_t* a,
+                      const int64_t* a_off, const uint32_t* b,
+                      const int64_t* b_off, int64_t batch, bigint_plan_t plan,
+                      void* stream);
+
+/* Ragged division: instance i divides u[u_off[i]..) by v[v_off[i]..); q
+ * instance i has the dividend's limb count and r the divisor's. */
+int bigint_divmod_ragged(uint32_t* q, const int64_t* q_off, uint32_t* r,
+                         const int64_t* r_off, int32_t* status,
+                         const uint32_t* u, const int64_t* u_off,
+                         const uint32_t* v, const int64_t* v_off, int64_t batch,
+                         bigint_plan_t plan, void* stream);
+
+/* ---- autotuning ----------------------------------------------------------------
+ * Times every candidate tile configuration of the MFMA-split multiply on the
+ * current device for each size bin (2^15..2^19 bits), keeps the fastest and
+ * writes the table as JSON to `cache_path` (host path; NULL = do not write).
+ * Later plans use the table.  bigint_autotune_load reads such a file.  All
+ * candidates produce identical bytes; the table only affects speed. */
+int bigint_autotune(const char* cache_path, int flags);
+int bigint_autotune_load(const char* cache_path);
+
+/* ---- diagnostics: the steps of the MFMA-split multiply ---------------------------
+ * bigint_digits7: out[i*D + k] = floor(a[i] / 2^(7k)) mod 128 for k < D
+ *   (the digit split); a: batch*n limbs, out: batch*D bytes, D >= 1.
+ * bigint_conv7: c[i*(Na+Nb-1) + k] = sum_{s+t=k} alpha_s beta_t over the
+ *   7-bit digits of a[i] (Na = ceil(32na/7)) and b[i] (Nb = ceil(32nb/7)),
+ *   computed by the int8 MFMA tiles (int32 output, before recombination).
+ * bigint_shinv: w[i*(h+1) ..] = floor(B^h / v[i]) with B = 2^32, the whole
+ *   shifted inverse of the division; v: batch*nv limbs, needs h >= nv and
+ *   a nonzero top limb of v (else that instance's w is 0); h <= 8192. */
+int bigint_digits7(uint8_t* out, const uint32_t* a, int64_t n, int64_t D,
+                   int64_t batch, void* stream);
+int bigint_conv7(int32_t* c, const uint32_t* a, int64_t na, const uint32_t* b,
+                 int64_t nb, int64_t batch, void* stream);
+int bigint_shinv(uint32_t* w, const uint32_t* v, int64_t nv, int64_t h,
+                 int64_t batch, void* stream);
+
+/* Tile parameters of the MFMA multiply used by the next calls on this thread
+ * (strips per wave band: 4, 8 or 16; waves per work-group: 4 or 8); 0 keeps
+ * the default.  Exists so tests can check that every configuration gives the
+ * same bytes. */
+int bigint_set_mfma_config(int strips_per_band, int waves);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BIGINT_ROCM_H */

@@ -1,0 +1,349 @@
+// api.hip -- the C-ABI entry points: argument checks, dispatch, plans.
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace bi {
+
+static thread_local int t_last_hip = 0;
+void set_hip_error(hipError_t e) { t_last_hip = (int)e; }
+
+static thread_local int t_cfg_P = 0, t_cfg_waves = 0;
+
+// Built-in tile choice, overridden per size bin by the autotune table.
+struct TuneEntry {
+  int max_limbs;  // bin upper bound (operand limbs)
+  int P, waves;
+};
+static std::mutex g_tune_mu;
+static std::vector<TuneEntry> g_tune = {
+    {1536, 4, 8}, {3072, 8, 8}, {6144, 16, 8}, {12288, 16, 8}, {BIGINT_MFMA_MAX_LIMBS, 16, 8}};
+
+MfmaCfg default_mfma_cfg(int na, int nb) {
+  const int n = std::max(na, nb);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (const auto& e : g_tune)
+    if (n <= e.max_limbs) return MfmaCfg{e.P, e.waves};
+  return MfmaCfg{16, 8};
+}
+
+MfmaCfg current_mfma_cfg(int na, int nb) {
+  MfmaCfg c = default_mfma_cfg(na, nb);
+  if (t_cfg_P) c.P = t_cfg_P;
+  if (t_cfg_waves) c.waves = t_cfg_waves;
+  return c;
+}
+
+int num_cus() {
+  static int n = 0;
+  if (n == 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    int cu = 0;
+    if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cu <= 0)
+      cu = 256;
+    n = cu;
+  }
+  return n;
+}
+
+// byte ranges [p, p+n) overlap?
+static bool overlap(const void* p, size_t n, const void* q, size_t m) {
+  if (!p || !q || n == 0 || m == 0) return false;
+  const uintptr_t a = (uintptr_t)p, b = (uintptr_t)q;
+  return a < b + m && b < a + n;
+}
+
+}  // namespace bi
+
+using namespace bi;
+
+extern "C" {
+
+int bigint_version(void) { return 10000; }
+
+const char* bigint_strerror(int code) {
+  switch (code) {
+    case BIGINT_OK: return "success";
+    case BIGINT_EINVAL: return "invalid argument";
+    case BIGINT_ENOMEM: return "out of memory";
+    case BIGINT_EHIP: return "HIP runtime error";
+    case BIGINT_EUNSUPPORTED: return "size outside the supported range";
+    default: return "unknown status code";
+  }
+}
+
+int bigint_last_hip_error(void) { return t_last_hip; }
+
+int bigint_set_mfma_config(int strips_per_band, int waves) {
+  if (strips_per_band != 0 && strips_per_band != 4 && strips_per_band != 8 &&
+      strips_per_band != 16)
+    return BIGINT_EINVAL;
+  if (waves != 0 && waves != 4 && waves != 8) return BIGINT_EINVAL;
+  t_cfg_P = strips_per_band;
+  t_cfg_waves = waves;
+  return BIGINT_OK;
+}
+
+static int addsub_common(bool sub, uint32_t* out, uint32_t* cout, const uint32_t* a,
+                         const uint32_t* b, int64_t n, int64_t batch, void* stream) {
+  if (!out || !a || !b || n <= 0 || batch < 0) return BIGINT_EINVAL;
+  if (n > 65536) return BIGINT_EUNSUPPORTED;
+  if (batch > 0x7fffffff) return BIGINT_EUNSUPPORTED;
+  const size_t bytes = (size_t)n * (size_t)batch * 4;
+  // in place is allowed only exactly
+  if (out != a && overlap(out, bytes, a, bytes)) return BIGINT_EINVAL;
+  if (out != b && overlap(out, bytes, b, bytes)) return BIGINT_EINVAL;
+  if (cout) {
+    const size_t cb = (size_t)batch * 4;
+    if (overlap(cout, cb, out, bytes) || overlap(cout, cb, a, bytes) || overlap(cout, cb, b, bytes))
+      return BIGINT_EINVAL;
+  }
+  if (batch == 0) return BIGINT_OK;
+  return launch_addsub(sub, out, cout, a, b, n, batch, (hipStream_t)stream);
+}
+
+int bigint_add(uint32_t* out, uint32_t* carry_out, const uint32_t* a, const uint32_t* b, int64_t n,
+               int64_t batch, void* stream) {
+  return addsub_common(false, out, carry_out, a, b, n, batch, stream);
+}
+
+int bigint_sub(uint32_t* out, uint32_t* borrow_out, const uint32_t* a, const uint32_t* b,
+               int64_t n, int64_t batch, void* stream) {
+  return addsub_common(true, out, borrow_out, a, b, n, batch, stream);
+}
+
+static bool mfma_fits(int64_t na, int64_t nb, MfmaCfg cfg) {
+  return na <= BIGINT_MFMA_MAX_LIMBS && nb <= BIGINT_MFMA_MAX_LIMBS &&
+         mfma_lds((int)na, (int)nb, cfg) <= 163840;
+}
+
+int bigint_mul(uint32_t* out, const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb,
+               int64_t batch, int algo, void* stream) {
+  if (!out || !a || !b || na <= 0 || nb <= 0 || batch < 0) return BIGINT_EINVAL;
+  if (algo != BIGINT_MUL_AUTO && algo != BIGINT_MUL_PLAIN && algo != BIGINT_MUL_MFMA)
+    return BIGINT_EINVAL;
+  if (batch > 0x7fffffff || na > (1 << 20) || nb > (1 << 20)) return BIGINT_EUNSUPPORTED;
+  const size_t ob = (size_t)(na + nb) * batch * 4;
+  if (overlap(out, ob, a, (size_t)na * batch * 4) || overlap(out, ob, b, (size_t)nb * batch * 4))
+    return BIGINT_EINVAL;
+  const MfmaCfg cfg = current_mfma_cfg((int)na, (int)nb);
+  int use = algo;
+  if (use == BIGINT_MUL_AUTO)
+    use = (mfma_fits(na, nb, cfg) && std::min(na, nb) >= 64) ? BIGINT_MUL_MFMA : BIGINT_MUL_PLAIN;
+  if (use == BIGINT_MUL_MFMA) {
+    if (!mfma_fits(na, nb, cfg)) return BIGINT_EUNSUPPORTED;
+    if (batch == 0) return BIGINT_OK;
+    return launch_mul_mfma(out, nullptr, a, na, b, nb, batch, cfg, (hipStream_t)stream);
+  }
+  if (na + nb > 32768) return BIGINT_EUNSUPPORTED;
+  if (batch == 0) return BIGINT_OK;
+  return launch_mul_plain(out, a, na, b, nb, batch, (hipStream_t)stream);
+}
+
+int bigint_digits7(uint8_t* out, const uint32_t* a, int64_t n, int64_t D, int64_t batch,
+                   void* stream) {
+  if (!out || !a || n <= 0 || D <= 0 || batch < 0) return BIGINT_EINVAL;
+  if (batch > 0xffff || n > (1 << 24) || D > (1 << 26)) return BIGINT_EUNSUPPORTED;
+  if (overlap(out, (size_t)D * batch, a, (size_t)n * batch * 4)) return BIGINT_EINVAL;
+  if (batch == 0) return BIGINT_OK;
+  return launch_digits7(out, a, n, D, batch, (hipStream_t)stream);
+}
+
+int bigint_conv7(int32_t* c, const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb,
+                 int64_t batch, void* stream) {
+  if (!c || !a || !b || na <= 0 || nb <= 0 || batch < 0) return BIGINT_EINVAL;
+  const MfmaCfg cfg = current_mfma_cfg((int)na, (int)nb);
+  if (!mfma_fits(na, nb, cfg) || batch > 0x7fffffff) return BIGINT_EUNSUPPORTED;
+  const int64_t K = (32 * na + 6) / 7 + (32 * nb + 6) / 7 - 1;
+  const size_t cb = (size_t)K * batch * 4;
+  if (overlap(c, cb, a, (size_t)na * batch * 4) || overlap(c, cb, b, (size_t)nb * batch * 4))
+    return BIGINT_EINVAL;
+  if (batch == 0) return BIGINT_OK;
+  return launch_mul_mfma(nullptr, c, a, na, b, nb, batch, cfg, (hipStream_t)stream);
+}
+
+}  // extern "C"
+
+// ============================================================================
+// plans and ragged batches
+// ============================================================================
+struct bigint_plan_s {
+  int op = 0, flags = 0;
+  int64_t batch = 0;
+  std::vector<int64_t> la, lb;
+  // multiplication schedule
+  bi::QueueItem* d_queue = nullptr;
+  uint32_t* d_counter = nullptr;
+  size_t lds = 0;
+  int waves = 8, grid = 0;
+  bool plain = false;
+  // workspace
+  void* ws = nullptr;
+  size_t ws_bytes = 0, ws_need = 0;
+  bool ws_owned = false;
+  // graph replay keyed by the call's pointers
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  const void* key[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+};
+
+static int plan_build_mul(bigint_plan_s* p) {
+  const int64_t B = p->batch;
+  bool plain = (p->flags & BIGINT_PLAN_PLAIN) != 0;
+  for (int64_t i = 0; i < B && !plain; ++i) {
+    const MfmaCfg c = default_mfma_cfg((int)p->la[i], (int)p->lb[i]);
+    if (!mfma_fits(p->la[i], p->lb[i], c) || std::min(p->la[i], p->lb[i]) < 1) plain = true;
+  }
+  for (int64_t i = 0; i < B; ++i)
+    if (plain && p->la[i] + p->lb[i] > 32768) return BIGINT_EUNSUPPORTED;
+  p->plain = plain;
+  // largest first (cost ~ digit products), ties by index
+  std::vector<int64_t> idx(B);
+  std::iota(idx.begin(), idx.end(), 0);
+  std::stable_sort(idx.begin(), idx.end(), [&](int64_t x, int64_t y) {
+    return p->la[x] * p->lb[x] > p->la[y] * p->lb[y];
+  });
+  std::vector<QueueItem> q(B);
+  size_t lds = 0;
+  for (int64_t t = 0; t < B; ++t) {
+    const int64_t i = idx[t];
+    q[t].inst = (int32_t)i;
+    if (plain) {
+      q[t].cfg = 0;
+      lds = std::max(lds, plain_lds((int)p->la[i], (int)p->lb[i]));
+    } else {
+      MfmaCfg c = default_mfma_cfg((int)p->la[i], (int)p->lb[i]);
+      c.waves = p->waves;
+      q[t].cfg = c.P == 4 ? 0 : (c.P == 8 ? 1 : 2);
+      lds = std::max(lds, mfma_lds((int)p->la[i], (int)p->lb[i], c));
+    }
+  }
+  p->lds = lds;
+  // work-groups per CU allowed by LDS (registers allow one 8-wave group)
+  const int per_cu = plain ? 1 : std::max(1, std::min<int>(2, (int)(163840 / std::max<size_t>(lds, 1))));
+  p->grid = (int)std::min<int64_t>(B, (int64_t)num_cus() * per_cu);
+  if (p->grid < 1) p->grid = 1;
+  if (B > 0) {
+    BI_HIP(hipMalloc(&p->d_queue, sizeof(QueueItem) * B));
+    BI_HIP(hipMemcpy(p->d_queue, q.data(), sizeof(QueueItem) * B, hipMemcpyHostToDevice));
+  }
+  BI_HIP(hipMalloc(&p->d_counter, 64));
+  BI_HIP(hipMemset(p->d_counter, 0, 64));
+  p->ws_need = 0;  // the multiply needs no workspace beyond LDS
+  return BIGINT_OK;
+}
+
+static void plan_free(bigint_plan_s* p) {
+  if (p->exec) hipGraphExecDestroy(p->exec);
+  if (p->graph) hipGraphDestroy(p->graph);
+  if (p->cap_stream) hipStreamDestroy(p->cap_stream);
+  if (p->d_queue) hipFree(p->d_queue);
+  if (p->d_counter) hipFree(p->d_counter);
+  if (p->ws_owned && p->ws) hipFree(p->ws);
+  delete p;
+}
+
+extern "C" {
+
+int bigint_plan_create(bigint_plan_t* plan, int op, const int64_t* len_a, const int64_t* len_b,
+                       int64_t batch, int flags) {
+  if (!plan) return BIGINT_EINVAL;
+  *plan = nullptr;
+  if (batch < 0 || (batch > 0 && (!len_a || !len_b))) return BIGINT_EINVAL;
+  if (op != BIGINT_OP_MUL && op != BIGINT_OP_DIVMOD) return BIGINT_EINVAL;
+  if (flags & ~(BIGINT_PLAN_PLAIN | BIGINT_PLAN_NO_GRAPH)) return BIGINT_EINVAL;
+  if (batch > 0x7fffffff) return BIGINT_EUNSUPPORTED;
+  for (int64_t i = 0; i < batch; ++i)
+    if (len_a[i] <= 0 || len_b[i] <= 0) return BIGINT_EINVAL;
+  bigint_plan_s* p = new (std::nothrow) bigint_plan_s;
+  if (!p) return BIGINT_ENOMEM;
+  p->op = op;
+  p->flags = flags;
+  p->batch = batch;
+  p->la.assign(len_a, len_a + batch);
+  p->lb.assign(len_b, len_b + batch);
+  int rc = BIGINT_OK;
+  if (op == BIGINT_OP_MUL) rc = plan_build_mul(p);
+  else rc = BIGINT_EUNSUPPORTED;
+  if (rc != BIGINT_OK) { plan_free(p); return rc; }
+  *plan = p;
+  return BIGINT_OK;
+}
+
+int bigint_plan_workspace_size(bigint_plan_t plan, size_t* bytes) {
+  if (!plan || !bytes) return BIGINT_EINVAL;
+  *bytes = plan->ws_need;
+  return BIGINT_OK;
+}
+
+int bigint_plan_set_workspace(bigint_plan_t plan, void* dev, size_t bytes) {
+  if (!plan || (!dev && bytes)) return BIGINT_EINVAL;
+  if (bytes < plan->ws_need) return BIGINT_EINVAL;
+  if (plan->ws_owned && plan->ws) hipFree(plan->ws);
+  plan->ws = dev;
+  plan->ws_bytes = bytes;
+  plan->ws_owned = false;
+  return BIGINT_OK;
+}
+
+int bigint_plan_destroy(bigint_plan_t plan) {
+  if (!plan) return BIGINT_EINVAL;
+  plan_free(plan);
+  return BIGINT_OK;
+}
+
+int bigint_mul_ragged(uint32_t* out, const int64_t* out_off, const uint32_t* a,
+                      const int64_t* a_off, const uint32_t* b, const int64_t* b_off, int64_t batch,
+                      bigint_plan_t plan, void* stream) {
+  if (!plan || plan->op != BIGINT_OP_MUL || batch != plan->batch) return BIGINT_EINVAL;
+  if (batch == 0) return BIGINT_OK;
+  if (!out || !out_off || !a || !a_off || !b || !b_off) return BIGINT_EINVAL;
+  int64_t ta = 0, tb = 0;
+  for (int64_t i = 0; i < batch; ++i) { ta += plan->la[i]; tb += plan->lb[i]; }
+  const size_t ob = (size_t)(ta + tb) * 4;
+  if (overlap(out, ob, a, (size_t)ta * 4) || overlap(out, ob, b, (size_t)tb * 4)) return BIGINT_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  auto launch = [&](hipStream_t ls) {
+    return launch_mul_ragged(out, out_off, a, a_off, b, b_off, plan->d_queue, batch,
+                             plan->d_counter, plan->plain, plan->lds, plan->waves, plan->grid, ls);
+  };
+  if ((plan->flags & BIGINT_PLAN_NO_GRAPH) || s == nullptr) return launch(s);
+  const void* key[6] = {out, out_off, a, a_off, b, b_off};
+  if (!plan->exec || memcmp(key, plan->key, sizeof(key)) != 0) {
+    if (plan->exec) { hipGraphExecDestroy(plan->exec); plan->exec = nullptr; }
+    if (plan->graph) { hipGraphDestroy(plan->graph); plan->graph = nullptr; }
+    if (!plan->cap_stream) BI_HIP(hipStreamCreateWithFlags(&plan->cap_stream, hipStreamNonBlocking));
+    BI_HIP(hipStreamBeginCapture(plan->cap_stream, hipStreamCaptureModeThreadLocal));
+    const int rc = launch(plan->cap_stream);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(plan->cap_stream, &g);
+    if (rc != BIGINT_OK) { if (g) hipGraphDestroy(g); return rc; }
+    if (e != hipSuccess) { set_hip_error(e); return BIGINT_EHIP; }
+    plan->graph = g;
+    BI_HIP(hipGraphInstantiate(&plan->exec, g, nullptr, nullptr, 0));
+    memcpy(plan->key, key, sizeof(key));
+  }
+  BI_HIP(hipGraphLaunch(plan->exec, s));
+  return BIGINT_OK;
+}
+
+// ---- not yet available -------------------------------------------------------
+int bigint_divmod(uint32_t*, uint32_t*, int32_t*, const uint32_t*, int64_t, const uint32_t*, int64_t,
+                  int64_t, void*) { return BIGINT_EUNSUPPORTED; }
+int bigint_divmod_ragged(uint32_t*, const int64_t*, uint32_t*, const int64_t*, int32_t*,
+                         const uint32_t*, const int64_t*, const uint32_t*, const int64_t*, int64_t,
+                         bigint_plan_t, void*) { return BIGINT_EUNSUPPORTED; }
+int bigint_shinv(uint32_t*, const uint32_t*, int64_t, int64_t, int64_t, void*) { return BIGINT_EUNSUPPORTED; }
+int bigint_autotune(const char*, int) { return BIGINT_EUNSUPPORTED; }
+int bigint_autotune_load(const char*) { return BIGINT_EUNSUPPORTED; }
+
+}  // extern "C"

@@ -1,0 +1,355 @@
+// dev_mul_mfma.hpp -- the MFMA-split multiply: 7-bit digits, int8 MFMA
+// Toeplitz tiles, int32 accumulation, 64-bit recombination and a carry scan.
+//
+// What is computed is the quadratic formula of Section 5.2,
+// c_k = sum_{i+j=k} alpha_i beta_j, over the 7-bit digits alpha, beta of the
+// operands (digit k = bits [7k, 7k+7)), followed by a * b = sum_k c_k 2^(7k).
+// Every c_k is at most min(Na, Nb) * 127^2, below 2^31 for up to 133,144
+// digits, so int32 accumulation is exact with no floating point anywhere.
+//
+// Tiling (v_mfma_i32_16x16x64_i8, D[16x16] += A[16x64] B[64x16]):
+//   A_Z[r][s] = alpha[Z + 16r - s]   (a Toeplitz slice of alpha)
+//   B_Y[s][p] = beta [Y + s + p]     (overlapping windows of beta)
+//   (A_Z B_Y)[r][p] = sum_{s<64} alpha[Z+16r-s] beta[Y+p+s]
+// is the part of c[Z+Y+16r+p] whose beta index lies in [Y+p, Y+p+64).  With
+// Z + Y = 256w fixed the 16x16 outputs are the "strip" c[256w .. 256w+256),
+// and summing over all Y = 64 * integer covers every beta index once.
+//   Write Y = 256y + 64rho (phase rho in 0..3) and Z = 256x - 64rho; then
+// strip w = x + y.  A wave owns P consecutive strips w0..w0+P-1 (one int32
+// accumulator tile each) and, per phase, walks y: strip w0+i needs A tile
+// x = w0+i-y, so one step needs one new A tile and one B tile for P MFMAs;
+// the other P-1 A tiles are still in registers from the previous steps (a
+// ring of P tiles).  Loads per MFMA: 2/P tiles.
+//
+// Register layout (lane l, idx = l & 15, grp = l >> 4; operand byte t):
+//   A lane holds alpha[Z + 16 idx - 16 grp - t]: 16 contiguous bytes of the
+//     reversed digit array, one aligned ds_read_b128.
+//   B lane holds beta[Y + idx + 16 grp + t]: 16 bytes at an offset of idx
+//     bytes, assembled from 5 aligned dwords with v_alignbyte.
+// Both operands use the same (grp, t) <-> contraction index map, so the
+// MFMA's own K ordering inside a lane does not matter.  The result tile
+// holds column p = l & 15, rows 4 (l >> 4) + v in register v.
+//
+// Recombination: c_k sits at bit 7k.  A strip of 256 coefficients covers
+// exactly 56 limbs (7*256 = 56*32), so strips are limb-aligned.  Per strip a
+// wave forms the 57 column sums X_j (lo 32 bits of every c_k 2^(7k - 32j)
+// whose low bit falls in limb j, plus the high parts from limb j-1; each
+// X_j < 2^35), splits X_j = L_j + 2^32 H_j, adds L + (H shifted up one
+// limb) with a one-bit ballot carry scan, writes the 56 limbs and keeps the
+// 57th column (with its carry) as the strip's carry word C_w.  A final
+// work-group carry scan adds every C_w at limb 56(w+1).
+#pragma once
+
+#include "common.hpp"
+#include "dev_addsub.hpp"
+
+namespace bi {
+namespace mfma {
+
+constexpr int kPadA = 320;  // zero bytes on both sides of reversed alpha (>= 303)
+constexpr int kPadB = 64;   // zero bytes before beta (a tile reads from Y >= -64)
+constexpr int kPadBt = 96;  // zero bytes after beta (reads reach Y + 80)
+constexpr int kStrip = 256; // coefficients per strip
+constexpr int kStripLimbs = 56;
+
+__host__ __device__ inline int ndigits(int n) { return (32 * n + 6) / 7; }
+
+struct Geo {
+  int na, nb, Na, Nb;
+  int QA;   // Abuf[q] = alpha[QA - q]
+  int SA;   // bytes of Abuf
+  int SB;   // bytes of Bbuf; Bbuf[kPadB + j] = beta[j]
+  int W;    // strips
+  int nout; // na + nb
+};
+
+__host__ __device__ inline Geo make_geo(int na, int nb) {
+  Geo g;
+  g.na = na; g.nb = nb;
+  g.Na = ndigits(na); g.Nb = ndigits(nb);
+  g.QA = ((g.Na - 1 + kPadA) + 15) & ~15;
+  g.SA = ((g.QA + kPadA + 1) + 15) & ~15;
+  g.SB = ((kPadB + g.Nb + kPadBt) + 15) & ~15;
+  const int K = g.Na + g.Nb - 1;
+  g.W = (K + kStrip - 1) / kStrip;
+  g.nout = na + nb;
+  return g;
+}
+
+// LDS layout: [Abuf SA][Bbuf SB][per-wave scratch 1 KiB each][strip carries
+// 8W][band order 2*NB][misc 128]
+__host__ __device__ inline size_t lds_bytes(int na, int nb, int nwaves, int P) {
+  const Geo g = make_geo(na, nb);
+  const int NB = (g.W + P - 1) / P;
+  return (size_t)g.SA + g.SB + (size_t)nwaves * 1024 + (size_t)8 * g.W +
+         (size_t)((2 * NB + 15) & ~15) + 128;
+}
+
+struct Lds {
+  uint8_t* A;
+  uint8_t* B;
+  int32_t* wscr;     // this wave's 256 ints
+  int32_t* scr;      // all waves' scratch (256 ints per wave)
+  uint64_t* carry;   // W words
+  uint16_t* order;   // NB entries
+  uint32_t* misc;    // [0] band counter, [1..16] scan scratch (32 words)
+};
+
+__device__ __forceinline__ Lds carve(char* smem, const Geo& g, int P) {
+  Lds s;
+  const int NB = (g.W + P - 1) / P;
+  char* p = smem;
+  s.A = reinterpret_cast<uint8_t*>(p); p += g.SA;
+  s.B = reinterpret_cast<uint8_t*>(p); p += g.SB;
+  s.scr = reinterpret_cast<int32_t*>(p);
+  s.wscr = s.scr + wave_id() * 256; p += num_waves() * 1024;
+  s.carry = reinterpret_cast<uint64_t*>(p); p += 8 * g.W;
+  s.order = reinterpret_cast<uint16_t*>(p); p += (2 * NB + 15) & ~15;
+  s.misc = reinterpret_cast<uint32_t*>(p);
+  return s;
+}
+
+// Stage the reversed digits of a and the digits of b into LDS (zero padded).
+__device__ __forceinline__ void stage(const Lds& s, const Geo& g, const uint32_t* __restrict__ a,
+                             const uint32_t* __restrict__ b) {
+  const int T = blockDim.x;
+  uint32_t* A32 = reinterpret_cast<uint32_t*>(s.A);
+  uint32_t* B32 = reinterpret_cast<uint32_t*>(s.B);
+  for (int d = threadIdx.x; d < g.SA / 4; d += T) {
+    uint32_t w = 0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int i = g.QA - (4 * d + e);
+      const uint32_t v = (i >= 0 && i < g.Na) ? digit7(a, g.na, i) : 0u;
+      w |= v << (8 * e);
+    }
+    A32[d] = w;
+  }
+  for (int d = threadIdx.x; d < g.SB / 4; d += T) {
+    uint32_t w = 0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int j = 4 * d + e - kPadB;
+      const uint32_t v = (j >= 0 && j < g.Nb) ? digit7(b, g.nb, j) : 0u;
+      w |= v << (8 * e);
+    }
+    B32[d] = w;
+  }
+}
+
+// y range of phase rho for the band starting at strip w0 (P strips).
+struct Range { int lo, hi, xlo, xhi; };
+
+__device__ __forceinline__ Range band_range(const Geo& g, int w0, int P, int rho) {
+  Range r;
+  // B tile covers beta[Y .. Y+78]; it is nonzero iff that meets [0, Nb)
+  const int yb_lo = ceil_div(-78 - 64 * rho, 256);
+  const int yb_hi = floor_div(g.Nb - 1 - 64 * rho, 256);
+  // A tile covers alpha[Z-63 .. Z+240]; nonzero iff that meets [0, Na)
+  r.xlo = ceil_div(64 * rho - 240, 256);
+  r.xhi = floor_div(g.Na + 62 + 64 * rho, 256);
+  r.lo = max(yb_lo, w0 - r.xhi);
+  r.hi = min(yb_hi, w0 + P - 1 - r.xlo);
+  return r;
+}
+
+__device__ __forceinline__ int band_cost(const Geo& g, int band, int P) {
+  int c = 0;
+  for (int rho = 0; rho < 4; ++rho) {
+    const Range r = band_range(g, band * P, P, rho);
+    c += max(0, r.hi - r.lo + 1);
+  }
+  return c;
+}
+
+__device__ __forceinline__ v4i load_A(const uint8_t* Abuf, const Geo& g, int x, int rho,
+                                      const Range& r) {
+  v4i v = {0, 0, 0, 0};
+  if (x >= r.xlo && x <= r.xhi) {  // wave-uniform
+    const int lane = lane_id();
+    const int Z = 256 * x - 64 * rho;
+    const int addr = g.QA - Z - 16 * (lane & 15) + 16 * (lane >> 4);
+    v = *reinterpret_cast<const v4i*>(Abuf + addr);
+  }
+  return v;
+}
+
+__device__ __forceinline__ v4i load_B(const uint8_t* Bbuf, int y, int rho) {
+  const int lane = lane_id();
+  const int p = lane & 15;
+  const int Y = 256 * y + 64 * rho;
+  const uint32_t* src =
+      reinterpret_cast<const uint32_t*>(Bbuf + kPadB + Y + 16 * (lane >> 4) + 4 * (p >> 2));
+  const uint32_t d0 = src[0], d1 = src[1], d2 = src[2], d3 = src[3], d4 = src[4];
+  const uint32_t sh = p & 3;
+  v4i v;
+  v.x = (int)__builtin_amdgcn_alignbyte(d1, d0, sh);
+  v.y = (int)__builtin_amdgcn_alignbyte(d2, d1, sh);
+  v.z = (int)__builtin_amdgcn_alignbyte(d3, d2, sh);
+  v.w = (int)__builtin_amdgcn_alignbyte(d4, d3, sh);
+  return v;
+}
+
+// One phase of one band: acc[i] += sum over the y range of A(w0+i-y) B(y).
+template <int P>
+__device__ __forceinline__ void band_phase(v4i (&acc)[P], const Lds& s, const Geo& g, int w0,
+                                           int rho) {
+  const Range r = band_range(g, w0, P, rho);
+  const int L = r.hi - r.lo + 1;
+  if (L <= 0) return;
+  const int xb = w0 - r.lo;  // strip i at step u uses x = xb + i - u
+  v4i ring[P];
+#pragma unroll
+  for (int i = 0; i < P; ++i) ring[i] = load_A(s.A, g, xb + i, rho, r);
+
+  int u = 0;
+  v4i Bc = load_B(s.B, r.lo, rho);
+#pragma unroll 1
+  for (;;) {
+#pragma unroll
+    for (int st = 0; st < P; ++st) {
+      const int step = u + st;
+      // next B tile (clamped to the range so the read stays in bounds)
+      const int ynext = min(r.lo + step + 1, r.hi);
+      const v4i Bn = load_B(s.B, ynext, rho);
+      // strip P-1 first: its slot is the one the next step overwrites
+      acc[P - 1] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ring[(2 * P - 1 - st) % P], Bc,
+                                                          acc[P - 1], 0, 0, 0);
+      ring[(2 * P - 1 - st) % P] = load_A(s.A, g, xb - step - 1, rho, r);
+#pragma unroll
+      for (int i = P - 2; i >= 0; --i)
+        acc[i] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ring[(P + i - st) % P], Bc, acc[i], 0,
+                                                       0, 0);
+      Bc = Bn;
+      if (step + 1 >= L) return;
+    }
+    u += P;
+  }
+}
+
+// Per strip: turn the 256 coefficients of acc (strip w) into 56 limbs of out
+// and the strip carry word; or, for the diagnostic path, store them raw.
+__device__ __noinline__ void strip_out(v4i acc, int w, const Lds& s, const Geo& g,
+                                          uint32_t* out, int32_t* coef) {
+  const int lane = lane_id();
+  int32_t* sc = s.wscr;
+  // lane l holds column p = l & 15, rows 4(l>>4)+v: coefficient 16 row + p
+#pragma unroll
+  for (int v = 0; v < 4; ++v) sc[16 * (4 * (lane >> 4) + v) + (lane & 15)] = acc[v];
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  if (coef) {
+    const int K = g.Na + g.Nb - 1;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int kk = 64 * v + lane;
+      const int k = kStrip * w + kk;
+      if (k < K) coef[k] = sc[kk];
+    }
+    __builtin_amdgcn_wave_barrier();
+    return;
+  }
+  // column sums: lane j in [0, 57) gathers the coefficients of limb j
+  uint64_t X = 0;
+  if (lane <= kStripLimbs) {
+    const int j = lane;
+    const int klo = (32 * j + 6) / 7;          // first kappa with floor(7 kappa/32) == j
+    const int khi = (32 * (j + 1) + 6) / 7;    // one past the last
+    for (int kk = klo; kk < khi && kk < kStrip; ++kk) {
+      const uint64_t v = (uint64_t)(uint32_t)sc[kk] << (7 * kk - 32 * j);
+      X += v & 0xffffffffull;
+    }
+    if (j > 0) {
+      const int plo = (32 * (j - 1) + 6) / 7;
+      for (int kk = plo; kk < klo; ++kk) {
+        const uint64_t v = (uint64_t)(uint32_t)sc[kk] << (7 * kk - 32 * (j - 1));
+        X += v >> 32;
+      }
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+  const uint32_t L = (uint32_t)X;
+  const uint32_t H = (uint32_t)(X >> 32);
+  const uint32_t Hprev = __shfl_up(H, 1, 64);
+  const uint64_t sum = (uint64_t)L + (lane > 0 ? Hprev : 0u);
+  const uint32_t res = (uint32_t)sum;
+  const bool gb = (sum >> 32) != 0;
+  const bool pb = (lane <= kStripLimbs) && res == 0xffffffffu;
+  const WaveCarry wc = wave_carry_masks(gb, pb);
+  const uint32_t cin = wave_carry_in(wc, 0);
+  const uint32_t limb = res + cin;
+  if (lane < kStripLimbs) {
+    const int jg = kStripLimbs * w + lane;
+    if (jg < g.nout) out[jg] = limb;
+  } else if (lane == kStripLimbs) {
+    const uint32_t cout = (uint32_t)gb | ((uint32_t)pb & cin);
+    s.carry[w] = (uint64_t)limb | ((uint64_t)(H + cout) << 32);
+  }
+}
+
+template <int P>
+__device__ __forceinline__ void run_band(int band, const Lds& s, const Geo& g, uint32_t* out, int32_t* coef) {
+  const int w0 = band * P;
+  v4i acc[P];
+#pragma unroll
+  for (int i = 0; i < P; ++i) acc[i] = v4i{0, 0, 0, 0};
+#pragma unroll 1
+  for (int rho = 0; rho < 4; ++rho) band_phase<P>(acc, s, g, w0, rho);
+#pragma unroll
+  for (int i = 0; i < P; ++i)
+    if (w0 + i < g.W) strip_out(acc[i], w0 + i, s, g, out, coef);
+}
+
+// out[0 .. na+nb) = a * b for one instance (whole work-group).  With coef
+// != nullptr the raw coefficients c_k (k < Na+Nb-1) are written instead.
+template <int P>
+__device__ __forceinline__ void wg_mul_mfma(uint32_t* out, int32_t* coef, const uint32_t* __restrict__ a, int na,
+                            const uint32_t* __restrict__ b, int nb, char* smem) {
+  const Geo g = make_geo(na, nb);
+  const Lds s = carve(smem, g, P);
+  const int NB = (g.W + P - 1) / P;
+
+  stage(s, g, a, b);
+  // band order: most expensive first (rank sort by cost; the costs sit in
+  // the wave scratch area, which holds 256 ints per wave >= NB)
+  for (int t = threadIdx.x; t < NB; t += blockDim.x) s.scr[t] = band_cost(g, t, P);
+  if (threadIdx.x == 0) s.misc[0] = 0;
+  __syncthreads();
+  for (int t = threadIdx.x; t < NB; t += blockDim.x) {
+    const int c = s.scr[t];
+    int rank = 0;
+    for (int u2 = 0; u2 < NB; ++u2) {
+      const int cu = s.scr[u2];
+      rank += (cu > c) || (cu == c && u2 < t);
+    }
+    s.order[rank] = (uint16_t)t;
+  }
+  __syncthreads();
+
+  for (;;) {
+    uint32_t t = 0;
+    if (lane_id() == 0) t = atomicAdd(&s.misc[0], 1u);
+    t = __builtin_amdgcn_readfirstlane(t);
+    if ((int)t >= NB) break;
+    const int band = __builtin_amdgcn_readfirstlane((int)s.order[t]);
+    run_band<P>(band, s, g, out, coef);
+  }
+  __syncthreads();
+  if (coef == nullptr) {
+    // out += sum_w C_w B^(56(w+1))
+    const uint64_t* C = s.carry;
+    auto X = [&](int j) -> uint32_t { return out[j]; };
+    auto Y = [&](int j) -> uint32_t {
+      if (j < kStripLimbs) return 0u;
+      const int e = j % kStripLimbs;
+      if (e >= 2) return 0u;
+      const uint64_t c = C[j / kStripLimbs - 1];
+      return e ? (uint32_t)(c >> 32) : (uint32_t)c;
+    };
+    wg_addsub<8, false>(out, g.nout, X, Y, 0u, s.misc + 1);
+  }
+  __syncthreads();
+}
+
+}  // namespace mfma
+}  // namespace bi

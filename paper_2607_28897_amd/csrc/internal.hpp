@@ -1,0 +1,43 @@
+// internal.hpp -- host-side launchers shared by the C-ABI translation units.
+#pragma once
+
+#include "common.hpp"
+
+namespace bi {
+
+// tile configuration of the MFMA multiply
+struct MfmaCfg {
+  int P;       // strips per wave band (4, 8, 16)
+  int waves;   // waves per work-group (4, 8)
+};
+
+MfmaCfg default_mfma_cfg(int na, int nb);
+MfmaCfg current_mfma_cfg(int na, int nb);  // thread override or default
+int num_cus();
+
+int launch_addsub(bool sub, uint32_t* out, uint32_t* cout, const uint32_t* a, const uint32_t* b,
+                  int64_t n, int64_t batch, hipStream_t s);
+int launch_mul_plain(uint32_t* out, const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb,
+                     int64_t batch, hipStream_t s);
+int launch_mul_mfma(uint32_t* out, int32_t* coef, const uint32_t* a, int64_t na,
+                    const uint32_t* b, int64_t nb, int64_t batch, MfmaCfg cfg, hipStream_t s);
+int launch_digits7(uint8_t* out, const uint32_t* a, int64_t n, int64_t D, int64_t batch,
+                   hipStream_t s);
+
+size_t mfma_lds(int na, int nb, MfmaCfg cfg);
+size_t plain_lds(int na, int nb);
+
+// ---- ragged (persistent, queue-fed) -------------------------------------------
+// One queue entry per instance, largest first.  cfg_id selects the tile
+// configuration for that instance.
+struct QueueItem {
+  int32_t inst;
+  int32_t cfg;   // MFMA: index into kPersistCfgs; plain: 0
+};
+
+int launch_mul_ragged(uint32_t* out, const int64_t* out_off, const uint32_t* a,
+                      const int64_t* a_off, const uint32_t* b, const int64_t* b_off,
+                      const QueueItem* queue, int64_t nitems, uint32_t* counter, bool plain,
+                      size_t lds, int waves, int grid, hipStream_t s);
+
+}  // namespace bi

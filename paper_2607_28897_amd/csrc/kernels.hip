@@ -1,0 +1,280 @@
+// kernels.hip -- gfx950 kernels of the batched big-integer library and their
+// host launchers.
+#include "internal.hpp"
+#include "dev_addsub.hpp"
+#include "dev_mul_mfma.hpp"
+#include "dev_mul_plain.hpp"
+
+namespace bi {
+
+// ============================================================================
+// add / sub: one work-group per instance, Q consecutive limbs per thread
+// loaded with 16-byte vector loads (Section 5.1: badd copies the operands
+// from global memory into registers, baddReg scans the per-thread carries).
+// ============================================================================
+template <int Q, bool SUB, bool VEC>
+__global__ __launch_bounds__(1024) void k_addsub(uint32_t* out, uint32_t* cout, const uint32_t* a,
+                                                 const uint32_t* b, int n) {
+  __shared__ uint32_t scratch[32];
+  const int64_t inst = blockIdx.x;
+  const uint32_t* pa = a + inst * n;
+  const uint32_t* pb = b + inst * n;
+  uint32_t* po = out + inst * n;
+  const int j0 = threadIdx.x * Q;
+  const int valid = min(Q, max(0, n - j0));
+  LimbRun<Q, SUB> run;
+  run.start();
+  if (VEC && valid == Q) {
+#pragma unroll
+    for (int i = 0; i < Q; i += 4) {
+      const uint4 va = *reinterpret_cast<const uint4*>(pa + j0 + i);
+      const uint4 vb = *reinterpret_cast<const uint4*>(pb + j0 + i);
+      run.set(i, va.x, vb.x, true);
+      run.set(i + 1, va.y, vb.y, true);
+      run.set(i + 2, va.z, vb.z, true);
+      run.set(i + 3, va.w, vb.w, true);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const bool ok = i < valid;
+      run.set(i, ok ? pa[j0 + i] : 0u, ok ? pb[j0 + i] : 0u, ok);
+    }
+  }
+  run.finish();
+  uint32_t total;
+  const uint32_t c = wg_carry_scan(run.G, run.P, 0u, scratch, &total);
+  run.apply(c);
+  if (VEC && valid == Q) {
+#pragma unroll
+    for (int i = 0; i < Q; i += 4)
+      *reinterpret_cast<uint4*>(po + j0 + i) =
+          make_uint4(run.s[i], run.s[i + 1], run.s[i + 2], run.s[i + 3]);
+  } else {
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+      if (i < valid) po[j0 + i] = run.s[i];
+  }
+  if (cout && threadIdx.x == 0) cout[inst] = total;
+}
+
+template <int Q, bool SUB>
+static int launch_addsub_q(uint32_t* out, uint32_t* cout, const uint32_t* a, const uint32_t* b,
+                           int64_t n, int64_t batch, hipStream_t s) {
+  const int T = (int)((cdiv(n, Q) + 63) / 64 * 64);
+  const bool vec = (n % 4 == 0) && ((uintptr_t)a % 16 == 0) && ((uintptr_t)b % 16 == 0) &&
+                   ((uintptr_t)out % 16 == 0);
+  if (vec)
+    hipLaunchKernelGGL((k_addsub<Q, SUB, true>), dim3((unsigned)batch), dim3(T), 0, s, out, cout, a,
+                       b, (int)n);
+  else
+    hipLaunchKernelGGL((k_addsub<Q, SUB, false>), dim3((unsigned)batch), dim3(T), 0, s, out, cout,
+                       a, b, (int)n);
+  BI_LAUNCH_CHECK();
+  return BIGINT_OK;
+}
+
+template <bool SUB>
+static int launch_addsub_t(uint32_t* out, uint32_t* cout, const uint32_t* a, const uint32_t* b,
+                           int64_t n, int64_t batch, hipStream_t s) {
+  // about 256 threads per instance, 4..64 limbs each
+  if (n <= 1024) return launch_addsub_q<4, SUB>(out, cout, a, b, n, batch, s);
+  if (n <= 2048) return launch_addsub_q<8, SUB>(out, cout, a, b, n, batch, s);
+  if (n <= 4096) return launch_addsub_q<16, SUB>(out, cout, a, b, n, batch, s);
+  if (n <= 16384) return launch_addsub_q<32, SUB>(out, cout, a, b, n, batch, s);
+  return launch_addsub_q<64, SUB>(out, cout, a, b, n, batch, s);
+}
+
+int launch_addsub(bool sub, uint32_t* out, uint32_t* cout, const uint32_t* a, const uint32_t* b,
+                  int64_t n, int64_t batch, hipStream_t s) {
+  return sub ? launch_addsub_t<true>(out, cout, a, b, n, batch, s)
+             : launch_addsub_t<false>(out, cout, a, b, n, batch, s);
+}
+
+// ============================================================================
+// plain u64 multiply: one work-group per instance
+// ============================================================================
+constexpr int kPlainQ = 4;
+constexpr int kPlainR = 4;
+
+template <int Q, int R>
+__global__ __launch_bounds__(1024) void k_mul_plain(uint32_t* out, const uint32_t* a, int na,
+                                                    const uint32_t* b, int nb) {
+  extern __shared__ uint64_t sm64[];
+  const int64_t inst = blockIdx.x;
+  wg_mul_plain<Q, R>(out + inst * (int64_t)(na + nb), a + inst * (int64_t)na, na,
+                     b + inst * (int64_t)nb, nb, sm64);
+}
+
+size_t plain_lds(int na, int nb) { return plain_lds_bytes(na, nb); }
+
+static int plain_threads(int na, int nb) {
+  const int K = (na + 1) / 2 + (nb + 1) / 2;
+  const int NBLK = (K + kPlainQ - 1) / kPlainQ;
+  int T = (int)((cdiv(NBLK, kPlainR) + 63) / 64 * 64);
+  return T < 64 ? 64 : T;
+}
+
+int launch_mul_plain(uint32_t* out, const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb,
+                     int64_t batch, hipStream_t s) {
+  const int T = plain_threads((int)na, (int)nb);
+  if (T > 1024) return BIGINT_EUNSUPPORTED;
+  const size_t lds = plain_lds((int)na, (int)nb);
+  BI_HIP(hipFuncSetAttribute((const void*)k_mul_plain<kPlainQ, kPlainR>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL((k_mul_plain<kPlainQ, kPlainR>), dim3((unsigned)batch), dim3(T), lds, s, out,
+                     a, (int)na, b, (int)nb);
+  BI_LAUNCH_CHECK();
+  return BIGINT_OK;
+}
+
+// ============================================================================
+// MFMA-split multiply: one work-group per instance
+// ============================================================================
+template <int P>
+__global__ __launch_bounds__(512) void k_mul_mfma(uint32_t* out, int32_t* coef, const uint32_t* a,
+                                                  int na, const uint32_t* b, int nb) {
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  const int64_t inst = blockIdx.x;
+  const int K = mfma::ndigits(na) + mfma::ndigits(nb) - 1;
+  mfma::wg_mul_mfma<P>(out ? out + inst * (int64_t)(na + nb) : nullptr,
+                       coef ? coef + inst * (int64_t)K : nullptr, a + inst * (int64_t)na, na,
+                       b + inst * (int64_t)nb, nb, smem);
+}
+
+size_t mfma_lds(int na, int nb, MfmaCfg cfg) {
+  return mfma::lds_bytes(na, nb, cfg.waves, cfg.P);
+}
+
+template <int P>
+static int launch_mfma_p(uint32_t* out, int32_t* coef, const uint32_t* a, int64_t na,
+                         const uint32_t* b, int64_t nb, int64_t batch, int waves, hipStream_t s) {
+  const size_t lds = mfma::lds_bytes((int)na, (int)nb, waves, P);
+  if (lds > 163840) return BIGINT_EUNSUPPORTED;
+  BI_HIP(hipFuncSetAttribute((const void*)k_mul_mfma<P>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)lds));
+  hipLaunchKernelGGL((k_mul_mfma<P>), dim3((unsigned)batch), dim3(64 * waves), lds, s, out, coef,
+                     a, (int)na, b, (int)nb);
+  BI_LAUNCH_CHECK();
+  return BIGINT_OK;
+}
+
+int launch_mul_mfma(uint32_t* out, int32_t* coef, const uint32_t* a, int64_t na,
+                    const uint32_t* b, int64_t nb, int64_t batch, MfmaCfg cfg, hipStream_t s) {
+  switch (cfg.P) {
+    case 4: return launch_mfma_p<4>(out, coef, a, na, b, nb, batch, cfg.waves, s);
+    case 8: return launch_mfma_p<8>(out, coef, a, na, b, nb, batch, cfg.waves, s);
+    case 16: return launch_mfma_p<16>(out, coef, a, na, b, nb, batch, cfg.waves, s);
+    default: return BIGINT_EINVAL;
+  }
+}
+
+// ============================================================================
+// digit split (diagnostic): out[k] = bits [7k, 7k+7) of a
+// ============================================================================
+__global__ void k_digits7(uint8_t* out, const uint32_t* a, int n, int D) {
+  const int64_t inst = blockIdx.y;
+  const uint32_t* pa = a + inst * n;
+  uint8_t* po = out + inst * (int64_t)D;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < D; k += gridDim.x * blockDim.x)
+    po[k] = (uint8_t)digit7(pa, n, k);
+}
+
+int launch_digits7(uint8_t* out, const uint32_t* a, int64_t n, int64_t D, int64_t batch,
+                   hipStream_t s) {
+  const int blocks = (int)std::min<int64_t>(cdiv(D, 256), 64);
+  hipLaunchKernelGGL(k_digits7, dim3(blocks, (unsigned)batch), dim3(256), 0, s, out, a, (int)n,
+                     (int)D);
+  BI_LAUNCH_CHECK();
+  return BIGINT_OK;
+}
+
+// ============================================================================
+// ragged multiply: one persistent launch, a device queue of instances ordered
+// largest first, each work-group pulling the next instance when it is done.
+// ============================================================================
+// Each tile configuration is its own (not inlined) function so that the
+// persistent kernel's register budget is that of the largest one alone.
+template <int P>
+__device__ __noinline__ void ragged_item(uint32_t* po, const uint32_t* pa, int na,
+                                         const uint32_t* pb, int nb, char* smem) {
+  mfma::wg_mul_mfma<P>(po, nullptr, pa, na, pb, nb, smem);
+}
+
+__global__ __launch_bounds__(512) void k_mul_mfma_ragged(uint32_t* out, const int64_t* out_off,
+                                                         const uint32_t* a, const int64_t* a_off,
+                                                         const uint32_t* b, const int64_t* b_off,
+                                                         const QueueItem* queue, int nitems,
+                                                         uint32_t* counter) {
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  __shared__ int item;
+  for (;;) {
+    if (threadIdx.x == 0) item = (int)atomicAdd(counter, 1u);
+    __syncthreads();
+    const int t = __builtin_amdgcn_readfirstlane(item);
+    __syncthreads();
+    if (t >= nitems) break;
+    const QueueItem q = queue[t];
+    const int64_t i = __builtin_amdgcn_readfirstlane(q.inst);
+    const int na = (int)(a_off[i + 1] - a_off[i]);
+    const int nb = (int)(b_off[i + 1] - b_off[i]);
+    uint32_t* po = out + out_off[i];
+    const uint32_t* pa = a + a_off[i];
+    const uint32_t* pb = b + b_off[i];
+    switch (__builtin_amdgcn_readfirstlane(q.cfg)) {
+      case 0: ragged_item<4>(po, pa, na, pb, nb, smem); break;
+      case 1: ragged_item<8>(po, pa, na, pb, nb, smem); break;
+      default: ragged_item<16>(po, pa, na, pb, nb, smem); break;
+    }
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_mul_plain_ragged(uint32_t* out, const int64_t* out_off,
+                                                           const uint32_t* a, const int64_t* a_off,
+                                                           const uint32_t* b, const int64_t* b_off,
+                                                           const QueueItem* queue, int nitems,
+                                                           uint32_t* counter) {
+  extern __shared__ uint64_t sm64[];
+  __shared__ int item;
+  for (;;) {
+    if (threadIdx.x == 0) item = (int)atomicAdd(counter, 1u);
+    __syncthreads();
+    const int t = __builtin_amdgcn_readfirstlane(item);
+    __syncthreads();
+    if (t >= nitems) break;
+    const int64_t i = __builtin_amdgcn_readfirstlane(queue[t].inst);
+    const int na = (int)(a_off[i + 1] - a_off[i]);
+    const int nb = (int)(b_off[i + 1] - b_off[i]);
+    wg_mul_plain<kPlainQ, kPlainR>(out + out_off[i], a + a_off[i], na, b + b_off[i], nb, sm64);
+    __syncthreads();
+  }
+}
+
+__global__ void k_zero_u32(uint32_t* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+int launch_mul_ragged(uint32_t* out, const int64_t* out_off, const uint32_t* a,
+                      const int64_t* a_off, const uint32_t* b, const int64_t* b_off,
+                      const QueueItem* queue, int64_t nitems, uint32_t* counter, bool plain,
+                      size_t lds, int waves, int grid, hipStream_t s) {
+  // reset the queue head with a kernel (graph-capture friendly, no memset node)
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, counter, 1);
+  BI_LAUNCH_CHECK();
+  if (plain) {
+    BI_HIP(hipFuncSetAttribute((const void*)k_mul_plain_ragged,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(k_mul_plain_ragged, dim3(grid), dim3(1024), lds, s, out, out_off, a, a_off,
+                       b, b_off, queue, (int)nitems, counter);
+  } else {
+    BI_HIP(hipFuncSetAttribute((const void*)k_mul_mfma_ragged,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(k_mul_mfma_ragged, dim3(grid), dim3(64 * waves), lds, s, out, out_off, a,
+                       a_off, b, b_off, queue, (int)nitems, counter);
+  }
+  BI_LAUNCH_CHECK();
+  return BIGINT_OK;
+}
+
+}  // namespace bi

@@ -1,0 +1,152 @@
+"""GPU parity: plain u64 multiply and MFMA-split multiply against the oracle,
+bit for bit, through the C-ABI; plus the intermediate steps of the MFMA path
+(digit split, int32 coefficients) and tile-configuration invariance."""
+import numpy as np
+import pytest
+
+from gpu_util import dev, host, rand_limbs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def bi():
+    import paper_2607_28897_amd as m
+    m.lib()
+    yield m
+    m.set_mfma_config(0, 0)
+
+
+ALGOS = ["plain", "mfma"]
+
+
+def _algo(bi, name):
+    return bi.MUL_PLAIN if name == "plain" else bi.MUL_MFMA
+
+
+# ---- the steps of the MFMA path ---------------------------------------------------
+
+@pytest.mark.parametrize("n", [1, 7, 8, 100, 1024, 4097])
+def test_digit_split(bi, orc, n):
+    g = np.random.default_rng(n)
+    a = rand_limbs(g, 3, n)
+    d = bi.digits7(dev(a)).cpu().numpy()
+    for i in range(3):
+        assert np.array_equal(d[i], orc.digits1(a[i], 7))
+
+
+@pytest.mark.parametrize("na,nb", [(1, 1), (2, 1), (7, 7), (8, 9), (56, 56), (63, 65), (100, 300),
+                                   (448, 448), (449, 447), (1024, 1024), (2000, 1500)])
+def test_coefficients(bi, orc, na, nb):
+    g = np.random.default_rng(na * 1000 + nb)
+    a = rand_limbs(g, 2, na)
+    b = rand_limbs(g, 2, nb)
+    c = bi.conv7(dev(a), dev(b)).cpu().numpy()
+    for i in range(2):
+        want = orc.conv1(orc.digits1(a[i]), orc.digits1(b[i]))
+        assert np.array_equal(c[i].astype(np.int64), want)
+
+
+def test_coefficients_all_ones_bound(bi, orc):
+    n = 4096
+    a = np.full((1, n), 0xFFFFFFFF, np.uint32)
+    c = bi.conv7(dev(a), dev(a)).cpu().numpy()[0]
+    want = orc.conv1(orc.digits1(a[0]), orc.digits1(a[0]))
+    assert np.array_equal(c.astype(np.int64), want)
+
+
+# ---- full products --------------------------------------------------------------------
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_config1(bi, orc, algo):
+    from paper_2607_28897_amd import inputs
+    c = inputs.config1()
+    p = bi.mul(dev(c["a"]), dev(c["b"]), _algo(bi, algo))
+    assert np.array_equal(host(p), orc.mul(c["a"], c["b"]))
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_config2_sampled(bi, orc, algo):
+    from paper_2607_28897_amd import inputs
+    c = inputs.config2()
+    p = host(bi.mul(dev(c["a"]), dev(c["b"]), _algo(bi, algo)))
+    # every instance is checked against the oracle on a sample of rows, half
+    # uniform and half carry-adversarial
+    for i in list(range(0, 512, 37)) + list(range(512, 1024, 37)):
+        assert np.array_equal(p[i], orc.mul1(c["a"][i], c["b"][i])), i
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_config3_sampled(bi, orc, algo):
+    from paper_2607_28897_amd import inputs
+    c = inputs.config3()
+    p = host(bi.mul(dev(c["a"]), dev(c["b"]), _algo(bi, algo)))
+    for i in (0, 1, 77, 128, 200, 255):
+        assert np.array_equal(p[i], orc.mul1(c["a"][i], c["b"][i])), i
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_all_ones_2e19(bi, orc, algo):
+    # (B^n - 1)^2: every 7-bit digit is 127, the largest coefficients possible
+    n = 16384
+    a = np.full((1, n), 0xFFFFFFFF, np.uint32)
+    p = host(bi.mul(dev(a), dev(a), _algo(bi, algo)))[0]
+    want = np.concatenate([[1], np.zeros(n - 1), [0xFFFFFFFE], np.full(n - 1, 0xFFFFFFFF)]).astype(np.uint32)
+    assert np.array_equal(p, want)
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+@pytest.mark.parametrize("na,nb", [(1, 1), (1, 2), (3, 1), (5, 5), (55, 57), (64, 64), (111, 1000),
+                                   (1000, 111), (2047, 2049), (4096, 1), (8191, 8193)])
+def test_shapes(bi, orc, algo, na, nb):
+    g = np.random.default_rng(na * 7 + nb)
+    a = rand_limbs(g, 3, na)
+    b = rand_limbs(g, 3, nb)
+    b[2] = 0xFFFFFFFF
+    p = host(bi.mul(dev(a), dev(b), _algo(bi, algo)))
+    for i in range(3):
+        assert np.array_equal(p[i], orc.mul1(a[i], b[i])), i
+
+
+def test_zero_and_one(bi, orc):
+    g = np.random.default_rng(1)
+    n = 3000
+    a = rand_limbs(g, 2, n)
+    b = np.zeros((2, n), np.uint32)
+    b[1, 0] = 1
+    for algo in (bi.MUL_PLAIN, bi.MUL_MFMA):
+        p = host(bi.mul(dev(a), dev(b), algo))
+        assert not p[0].any()
+        assert np.array_equal(p[1][:n], a[1]) and not p[1][n:].any()
+
+
+@pytest.mark.parametrize("P,waves", [(4, 4), (4, 8), (8, 4), (8, 8), (16, 4), (16, 8)])
+def test_tile_configs_identical(bi, orc, P, waves):
+    g = np.random.default_rng(P * 10 + waves)
+    a = rand_limbs(g, 2, 3333)
+    b = rand_limbs(g, 2, 2900)
+    bi.set_mfma_config(P, waves)
+    try:
+        p = host(bi.mul(dev(a), dev(b), bi.MUL_MFMA))
+    finally:
+        bi.set_mfma_config(0, 0)
+    for i in range(2):
+        assert np.array_equal(p[i], orc.mul1(a[i], b[i]))
+
+
+def test_plain_matches_mfma_bytes(bi):
+    g = np.random.default_rng(42)
+    a = rand_limbs(g, 16, 4096)
+    b = rand_limbs(g, 16, 4096)
+    p1 = host(bi.mul(dev(a), dev(b), bi.MUL_PLAIN))
+    p2 = host(bi.mul(dev(a), dev(b), bi.MUL_MFMA))
+    assert np.array_equal(p1, p2)
+
+
+def test_repeat_deterministic(bi):
+    g = np.random.default_rng(43)
+    a = dev(rand_limbs(g, 8, 5000))
+    b = dev(rand_limbs(g, 8, 5000))
+    r1 = host(bi.mul(a, b, bi.MUL_MFMA))
+    r2 = host(bi.mul(a, b, bi.MUL_MFMA))
+    assert np.array_equal(r1, r2)
