@@ -1,0 +1,212 @@
+#!/usr/bin/env python3
+"""Benchmark: 2^19-bit multiplications per second on one MI355X.
+
+One step = one batched MFMA-split multiplication of 256 independent pairs of
+2^19-bit integers (16384 u32 limbs each, uniform random limbs from seed 1002)
+into their full 2^20-bit products: digit split, int8 MFMA Toeplitz
+contraction with int32 accumulation, 64-bit recombination and the carry
+scan, all in one kernel launch with the operands already resident in HBM.
+The plain u64 schoolbook kernel is timed beside it on the same inputs and
+both outputs are compared byte for byte.
+
+Output: one JSON line (see the fields below).  ``--gpus N`` with N > 1 exits:
+this benchmark runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "2^19-bit muls/s on 1 GPU, MFMA-split vs plain u64 kernel, bit-exact"
+INT8_PEAK_TOPS = 5000.0      # MI355X dense int8 MFMA, TOP/s (2 ops per MAC)
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=50)
+    p.add_argument("--warmup", type=int, default=5)
+    p.add_argument("--batch", type=int, default=256)
+    p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    p.add_argument("--cpu-seconds", type=float, default=15.0,
+                   help="target CPU work (core-seconds) of the oracle sample")
+    p.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "mfma_mul_2e19_traffic.json"),
+                   help="HBM traffic per launch from rocprofv3 counters, if measured")
+    return p.parse_args()
+
+
+def time_launches(fn, steps, warmup, torch):
+    """Run fn (one kernel launch on torch's current stream) warmup + steps
+    times; returns (total_ms over the timed steps, mean per-launch ms from
+    per-launch event pairs)."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_start.record()
+    for e0, e1 in ev:
+        e0.record()
+        fn()
+        e1.record()
+    t_end.record()
+    torch.cuda.synchronize()
+    total = t_start.elapsed_time(t_end)
+    per = [e0.elapsed_time(e1) for e0, e1 in ev]
+    return total, float(np.mean(per))
+
+
+def cpu_baseline(a_np, b_np, gpu_out, target_s):
+    """The oracle (plain C schoolbook on u64 digits, as it stands) on a
+    bounded sample of the same pairs, one pair per host thread; also checks
+    the GPU products of the sampled pairs byte for byte."""
+    import concurrent.futures as cf
+    import oracle
+    oracle.build()
+    t0 = time.perf_counter()
+    first = oracle.mul1(a_np[0], b_np[0])
+    one = time.perf_counter() - t0
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    cores = max(1, min(cores, 64))
+    n = int(max(cores, min(a_np.shape[0], target_s / max(one, 1e-3))))
+    n = min(n, a_np.shape[0])
+    idx = list(range(1, n))
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(max_workers=cores) as ex:
+        outs = list(ex.map(lambda i: oracle.mul1(a_np[i], b_np[i]), idx))
+    wall = time.perf_counter() - t0
+    exact = bool(np.array_equal(first, gpu_out[0]) and
+                 all(np.array_equal(o, gpu_out[i]) for o, i in zip(outs, idx)))
+    return {
+        "value": round(len(idx) / wall, 3),
+        "unit": "muls/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": f"{len(idx)} of the {a_np.shape[0]} pairs (2^19 x 2^19 bits), one pair per thread",
+    }, exact, n
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on exactly one GPU: the batched big-integer path has no "
+              "multi-GPU step (instances are independent; see the sharding notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2607_28897_amd as bi
+    from paper_2607_28897_amd import inputs
+
+    cfg = inputs.config3(args.batch)
+    a_np, b_np, n = cfg["a"], cfg["b"], cfg["n"]
+    a = torch.from_numpy(a_np.view(np.int32)).cuda()
+    b = torch.from_numpy(b_np.view(np.int32)).cuda()
+    batch = a.shape[0]
+    out_m = torch.empty((batch, 2 * n), dtype=torch.int32, device="cuda")
+    out_p = torch.empty_like(out_m)
+    L = bi.lib()
+    import ctypes
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    pa, pb = ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr())
+    pm, pp = ctypes.c_void_p(out_m.data_ptr()), ctypes.c_void_p(out_p.data_ptr())
+
+    def run_mfma():
+        rc = L.bigint_mul(pm, pa, n, pb, n, batch, bi.MUL_MFMA, stream)
+        if rc:
+            raise bi.BigIntError(rc, "bigint_mul")
+
+    def run_plain():
+        rc = L.bigint_mul(pp, pa, n, pb, n, batch, bi.MUL_PLAIN, stream)
+        if rc:
+            raise bi.BigIntError(rc, "bigint_mul")
+
+    torch.cuda.synchronize()
+    total_ms, kernel_ms = time_launches(run_mfma, args.steps, args.warmup, torch)
+    print(f"# mfma: {total_ms / args.steps:.4f} ms/step", file=sys.stderr, flush=True)
+    p_steps = max(3, args.steps // 10)
+    p_total, p_kernel = time_launches(run_plain, p_steps, 1, torch)
+    print(f"# plain: {p_total / p_steps:.4f} ms/step", file=sys.stderr, flush=True)
+    same = bool(torch.equal(out_m, out_p))
+
+    ms = total_ms / args.steps
+    value = batch / (ms * 1e-3)
+    Na = (32 * n + 6) // 7
+    ops = 2.0 * batch * Na * Na                     # int8 multiply-accumulates x 2
+    achieved = ops / (kernel_ms * 1e-3) / 1e12      # TOP/s
+    traffic = None
+    if os.path.exists(args.traffic_json):
+        with open(args.traffic_json) as f:
+            t = json.load(f)
+        if t.get("kernel_sha") == kernel_sha():
+            traffic = t.get("bytes_per_launch")
+
+    line = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "muls/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int8",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{batch} pairs of 2^19-bit integers ({n} u32 limbs), uniform random limbs "
+                        f"(seed 1002), full 2^20-bit products, MFMA-split multiply",
+            "batch": batch,
+            "operand_bits": 32 * n,
+            "digits_per_operand": Na,
+        },
+        "roofline": {
+            "bound": "mfma",
+            "achieved": round(achieved, 1),
+            "peak": INT8_PEAK_TOPS,
+            "unit": "TOP/s",
+            "frac": round(achieved / INT8_PEAK_TOPS, 4),
+            "traffic": traffic,
+            "kernel_ms": round(kernel_ms, 4),
+        },
+        "plain": {
+            "value": round(batch / (p_total / p_steps * 1e-3), 1),
+            "unit": "muls/s",
+            "ms_per_step": round(p_total / p_steps, 4),
+            "steps": p_steps,
+        },
+        "mfma_equals_plain": same,
+    }
+    if not args.no_cpu:
+        cpu, exact, _ = cpu_baseline(a_np, b_np, out_m.cpu().numpy().view(np.uint32), args.cpu_seconds)
+        line["cpu_baseline"] = cpu
+        line["bit_exact_sample"] = exact
+    print(json.dumps(line), flush=True)
+
+
+def kernel_sha():
+    """Hash of the sources of the MFMA multiply (to know whether counters
+    taken earlier still describe the current kernel)."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2607_28897_amd", "csrc")
+    for f in ("common.hpp", "dev_addsub.hpp", "dev_mul_mfma.hpp", "kernels.hip"):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+if __name__ == "__main__":
+    main()

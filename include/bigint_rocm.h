@@ -53,6 +53,8 @@ extern "C" {
 /* per-instance division status (the `status` output of divmod) */
 #define BIGINT_DIV_OK 0
 #define BIGINT_DIVZERO 1
+#define BIGINT_DIV_FAILED 2 /* an internal correction loop hit its bound; the
+                               result is not valid (not expected to occur) */
 
 /* multiplication algorithms */
 #define BIGINT_MUL_AUTO 0  /* MFMA-split where supported, else plain        */

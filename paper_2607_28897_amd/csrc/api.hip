@@ -185,6 +185,7 @@ struct bigint_plan_s {
   size_t lds = 0;
   int waves = 8, grid = 0;
   bool plain = false;
+  int cap_u = 0, cap_v = 0;   // division: largest dividend / divisor
   // workspace
   void* ws = nullptr;
   size_t ws_bytes = 0, ws_need = 0;
@@ -242,6 +243,36 @@ static int plan_build_mul(bigint_plan_s* p) {
   return BIGINT_OK;
 }
 
+static int plan_build_div(bigint_plan_s* p) {
+  const int64_t B = p->batch;
+  int64_t cu = 1, cv = 1;
+  for (int64_t i = 0; i < B; ++i) {
+    if (p->la[i] > 8192 || p->lb[i] > 8192) return BIGINT_EUNSUPPORTED;
+    cu = std::max(cu, p->la[i]);
+    cv = std::max(cv, p->lb[i]);
+  }
+  p->cap_u = (int)cu;
+  p->cap_v = (int)cv;
+  // largest first: the cost grows like (nu - nv) (nu + 4 nv) limb products
+  std::vector<int64_t> idx(B);
+  std::iota(idx.begin(), idx.end(), 0);
+  auto cost = [&](int64_t i) {
+    const int64_t d = std::max<int64_t>(p->la[i] - p->lb[i] + 1, 1);
+    return d * (p->la[i] + 4 * p->lb[i]);
+  };
+  std::stable_sort(idx.begin(), idx.end(), [&](int64_t x, int64_t y) { return cost(x) > cost(y); });
+  std::vector<int32_t> q(B);
+  for (int64_t t = 0; t < B; ++t) q[t] = (int32_t)idx[t];
+  p->grid = (int)std::max<int64_t>(1, std::min<int64_t>(B, num_cus()));
+  if (B > 0) {
+    BI_HIP(hipMalloc(&p->d_queue, sizeof(int32_t) * B));
+    BI_HIP(hipMemcpy(p->d_queue, q.data(), sizeof(int32_t) * B, hipMemcpyHostToDevice));
+  }
+  p->ws_need = div_ws_bytes(p->cap_u, p->cap_v, p->grid);
+  if (div_lds_bytes(p->cap_u, p->cap_v) > 163840 - 256) return BIGINT_EUNSUPPORTED;
+  return BIGINT_OK;
+}
+
 static void plan_free(bigint_plan_s* p) {
   if (p->exec) hipGraphExecDestroy(p->exec);
   if (p->graph) hipGraphDestroy(p->graph);
@@ -273,7 +304,7 @@ int bigint_plan_create(bigint_plan_t* plan, int op, const int64_t* len_a, const 
   p->lb.assign(len_b, len_b + batch);
   int rc = BIGINT_OK;
   if (op == BIGINT_OP_MUL) rc = plan_build_mul(p);
-  else rc = BIGINT_EUNSUPPORTED;
+  else rc = plan_build_div(p);
   if (rc != BIGINT_OK) { plan_free(p); return rc; }
   *plan = p;
   return BIGINT_OK;
@@ -336,13 +367,75 @@ int bigint_mul_ragged(uint32_t* out, const int64_t* out_off, const uint32_t* a,
   return BIGINT_OK;
 }
 
-// ---- not yet available -------------------------------------------------------
-int bigint_divmod(uint32_t*, uint32_t*, int32_t*, const uint32_t*, int64_t, const uint32_t*, int64_t,
-                  int64_t, void*) { return BIGINT_EUNSUPPORTED; }
-int bigint_divmod_ragged(uint32_t*, const int64_t*, uint32_t*, const int64_t*, int32_t*,
-                         const uint32_t*, const int64_t*, const uint32_t*, const int64_t*, int64_t,
-                         bigint_plan_t, void*) { return BIGINT_EUNSUPPORTED; }
-int bigint_shinv(uint32_t*, const uint32_t*, int64_t, int64_t, int64_t, void*) { return BIGINT_EUNSUPPORTED; }
+// ---- division ------------------------------------------------------------------
+
+static int divmod_launch_alloc(uint32_t* q, uint32_t* r, int32_t* status, const uint32_t* u,
+                               int64_t nu, const uint32_t* v, int64_t nv, int64_t batch, int h_inv,
+                               hipStream_t s) {
+  const int cap_u = h_inv >= 0 ? h_inv + 2 : (int)nu;
+  const int cap_v = (int)nv;
+  const int grid = (int)std::min<int64_t>(batch, num_cus());
+  const size_t bytes = div_ws_bytes(cap_u, cap_v, grid);
+  void* ws = nullptr;
+  hipError_t e = hipMallocAsync(&ws, bytes, s);
+  if (e != hipSuccess) { set_hip_error(e); return BIGINT_ENOMEM; }
+  const int rc = launch_divmod(q, nullptr, r, nullptr, status, u, nullptr, (int)nu, v, nullptr,
+                               (int)nv, nullptr, batch, ws, cap_u, cap_v, grid, h_inv, nullptr, s);
+  e = hipFreeAsync(ws, s);
+  if (rc != BIGINT_OK) return rc;
+  if (e != hipSuccess) { set_hip_error(e); return BIGINT_EHIP; }
+  return BIGINT_OK;
+}
+
+int bigint_divmod(uint32_t* q, uint32_t* r, int32_t* status, const uint32_t* u, int64_t nu,
+                  const uint32_t* v, int64_t nv, int64_t batch, void* stream) {
+  if (!q || !r || !u || !v || nu <= 0 || nv <= 0 || batch < 0) return BIGINT_EINVAL;
+  if (nu > 8192 || nv > 8192 || batch > 0x7fffffff) return BIGINT_EUNSUPPORTED;
+  const size_t qb = (size_t)nu * batch * 4, rb = (size_t)nv * batch * 4;
+  const size_t ub = (size_t)nu * batch * 4, vb = (size_t)nv * batch * 4, sb = (size_t)batch * 4;
+  if (overlap(q, qb, u, ub) || overlap(q, qb, v, vb) || overlap(r, rb, u, ub) ||
+      overlap(r, rb, v, vb) || overlap(q, qb, r, rb))
+    return BIGINT_EINVAL;
+  if (status && (overlap(status, sb, q, qb) || overlap(status, sb, r, rb) ||
+                 overlap(status, sb, u, ub) || overlap(status, sb, v, vb)))
+    return BIGINT_EINVAL;
+  if (batch == 0) return BIGINT_OK;
+  return divmod_launch_alloc(q, r, status, u, nu, v, nv, batch, -1, (hipStream_t)stream);
+}
+
+int bigint_shinv(uint32_t* w, const uint32_t* v, int64_t nv, int64_t h, int64_t batch,
+                 void* stream) {
+  if (!w || !v || nv <= 0 || batch < 0 || h < nv) return BIGINT_EINVAL;
+  if (h > 8192 || batch > 0x7fffffff) return BIGINT_EUNSUPPORTED;
+  if (overlap(w, (size_t)(h + 1) * batch * 4, v, (size_t)nv * batch * 4)) return BIGINT_EINVAL;
+  if (batch == 0) return BIGINT_OK;
+  return divmod_launch_alloc(w, nullptr, nullptr, nullptr, nv, v, nv, batch, (int)h,
+                             (hipStream_t)stream);
+}
+
+int bigint_divmod_ragged(uint32_t* q, const int64_t* q_off, uint32_t* r, const int64_t* r_off,
+                         int32_t* status, const uint32_t* u, const int64_t* u_off,
+                         const uint32_t* v, const int64_t* v_off, int64_t batch,
+                         bigint_plan_t plan, void* stream) {
+  if (!plan || plan->op != BIGINT_OP_DIVMOD || batch != plan->batch) return BIGINT_EINVAL;
+  if (batch == 0) return BIGINT_OK;
+  if (!q || !q_off || !r || !r_off || !u || !u_off || !v || !v_off) return BIGINT_EINVAL;
+  int64_t tu = 0, tv = 0;
+  for (int64_t i = 0; i < batch; ++i) { tu += plan->la[i]; tv += plan->lb[i]; }
+  if (overlap(q, tu * 4, u, tu * 4) || overlap(q, tu * 4, v, tv * 4) || overlap(r, tv * 4, u, tu * 4) ||
+      overlap(r, tv * 4, v, tv * 4) || overlap(q, tu * 4, r, tv * 4))
+    return BIGINT_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  if (!plan->ws) {
+    BI_HIP(hipMalloc(&plan->ws, plan->ws_need));
+    plan->ws_bytes = plan->ws_need;
+    plan->ws_owned = true;
+  }
+  return launch_divmod(q, q_off, r, r_off, status, u, u_off, 0, v, v_off, 0,
+                       reinterpret_cast<const int32_t*>(plan->d_queue), batch, plan->ws,
+                       plan->cap_u, plan->cap_v, plan->grid, -1, nullptr, s);
+}
+
 int bigint_autotune(const char*, int) { return BIGINT_EUNSUPPORTED; }
 int bigint_autotune_load(const char*) { return BIGINT_EUNSUPPORTED; }
 

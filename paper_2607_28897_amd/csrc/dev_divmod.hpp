@@ -1,0 +1,362 @@
+// dev_divmod.hpp -- division through the whole shifted inverse (Section 5.3).
+//
+// For a divisor v with k+1 significant limbs (B = 2^32) and a dividend u with
+// h significant limbs, the quotient is read off w = floor(B^h / v):
+// q = floor(u w / B^h) is floor(u/v) or one less, fixed by one comparison of
+// r = u - q v with v.  w itself is grown by Newton steps in the integral
+// domain, in the form of the paper's `step` (Section 5.3, Fig. "step"):
+//     w' = w B^m + floor(w (B^cur - v w) / B^(cur-m))
+// which turns w = floor(B^cur / v) into an approximation of
+// floor(B^(cur+m) / v) from below; with m <= cur - k - 1 its error is a few
+// units.  Each step is preceded by an exact fix-up at scale cur (the signed
+// difference e = B^cur - v w -- the paper's powDiff -- is brought into
+// [0, v) by adding or subtracting v), so e >= 0 and only the positive
+// branch of `step` occurs.  The starting value comes from the top three limbs
+// of v.  All multiplications are full products on the MFMA-split multiply;
+// linear operations (precision, shifts, additions, comparisons) run on the
+// whole work-group.  Division by a one-limb divisor is a short division.
+#pragma once
+
+#include "common.hpp"
+#include "dev_addsub.hpp"
+#include "dev_mul_mfma.hpp"
+
+namespace bi {
+namespace div {
+
+constexpr int kP = 16;  // strips per band of the multiplications
+constexpr int kMaxAdjust = 64;  // cap on fix-up rounds per scale
+
+// LDS words used by the division itself (besides the multiply's area)
+struct Shared {
+  uint32_t red[4];      // reductions
+  uint32_t scan[32];    // carry-scan scratch
+  uint32_t w0[4];       // initial estimate (one thread)
+  uint32_t failed;      // a fix-up hit its cap (never expected)
+};
+
+// ---- work-group linear operations on global limb arrays ------------------------
+
+__device__ __forceinline__ void wg_fill(uint32_t* x, int n, uint32_t v) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) x[i] = v;
+  __syncthreads();
+}
+
+__device__ __forceinline__ void wg_copy(uint32_t* dst, const uint32_t* src, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+  __syncthreads();
+}
+
+// dst[0..n) = src[s .. s+n) (limbs past ns read as 0); dst must not overlap src
+__device__ __forceinline__ void wg_shr_copy(uint32_t* dst, int n, const uint32_t* src, int ns, int s) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = (i + s < ns) ? src[i + s] : 0u;
+  __syncthreads();
+}
+
+// number of significant limbs of x[0..n)
+__device__ __forceinline__ int wg_prec(const uint32_t* x, int n, Shared* sh) {
+  if (threadIdx.x == 0) sh->red[0] = 0;
+  __syncthreads();
+  int m = 0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x)
+    if (x[i] != 0u) m = i + 1;
+  if (m) atomicMax(&sh->red[0], (uint32_t)m);
+  __syncthreads();
+  const int r = (int)sh->red[0];
+  __syncthreads();
+  return r;
+}
+
+// sign of x - y over n limbs (both zero-extended to n)
+__device__ __forceinline__ int wg_cmp(const uint32_t* x, int nx, const uint32_t* y, int ny, int n,
+                                      Shared* sh) {
+  if (threadIdx.x == 0) sh->red[1] = 0;
+  __syncthreads();
+  int m = 0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const uint32_t a = i < nx ? x[i] : 0u, b = i < ny ? y[i] : 0u;
+    if (a != b) m = i + 1;
+  }
+  if (m) atomicMax(&sh->red[1], (uint32_t)m);
+  __syncthreads();
+  const int top = (int)sh->red[1];
+  int r = 0;
+  if (top) {
+    const uint32_t a = top - 1 < nx ? x[top - 1] : 0u, b = top - 1 < ny ? y[top - 1] : 0u;
+    r = a > b ? 1 : -1;
+  }
+  __syncthreads();
+  return r;
+}
+
+// dst[0..n) = x + y (or x - y), operands zero-extended; returns carry/borrow
+template <bool SUB>
+__device__ __forceinline__ uint32_t wg_arith(uint32_t* dst, int n, const uint32_t* x, int nx,
+                                             const uint32_t* y, int ny, Shared* sh) {
+  auto X = [&](int j) -> uint32_t { return j < nx ? x[j] : 0u; };
+  auto Y = [&](int j) -> uint32_t { return j < ny ? y[j] : 0u; };
+  const uint32_t c = wg_addsub<4, SUB>(dst, n, X, Y, 0u, sh->scan);
+  return c;
+}
+
+// dst[0..n) = x +/- small (a one-limb value), x zero-extended
+template <bool SUB>
+__device__ __forceinline__ uint32_t wg_arith1(uint32_t* dst, int n, const uint32_t* x, int nx,
+                                              uint32_t small, Shared* sh) {
+  auto X = [&](int j) -> uint32_t { return j < nx ? x[j] : 0u; };
+  auto Y = [&](int j) -> uint32_t { return j == 0 ? small : 0u; };
+  return wg_addsub<4, SUB>(dst, n, X, Y, 0u, sh->scan);
+}
+
+// dst[0 .. na+nb) = a * b (MFMA-split multiply; dst must not overlap a, b)
+__device__ __forceinline__ void wg_mul(uint32_t* dst, const uint32_t* a, int na, const uint32_t* b,
+                                       int nb, char* smem) {
+  mfma::wg_mul_mfma<kP>(dst, nullptr, a, na, b, nb, smem);
+}
+
+// ---- one-lane helpers for the starting value ------------------------------------
+
+// floor(N / D) for a 128-bit N and a divisor D < 2^97 given as (hi, lo), by
+// restoring long division bit by bit (no division instruction needed).
+__device__ inline unsigned __int128 udiv128(unsigned __int128 N, unsigned __int128 D) {
+  unsigned __int128 q = 0, r = 0;
+  for (int i = 127; i >= 0; --i) {
+    r = (r << 1) | ((N >> i) & 1);
+    if (r >= D) { r -= D; q |= (unsigned __int128)1 << i; }
+  }
+  return q;
+}
+
+// ---- the division of one instance ----------------------------------------------
+
+struct Bufs {
+  uint32_t* W;   // w, capacity cw
+  uint32_t* E;   // e, capacity ce
+  uint32_t* T;   // products, capacity ct
+  uint32_t* U2;  // second temporary (new w, remainder), capacity cw
+  int cw, ce, ct;
+};
+
+__host__ __device__ inline size_t div_ws_limbs(int nu, int nv) {
+  const int cw = nu + 8, ce = nv + 8, ct = 2 * nu + nv + 16;
+  return (size_t)2 * cw + ce + ct;
+}
+
+__host__ __device__ inline Bufs carve_bufs(uint32_t* ws, int nu, int nv) {
+  Bufs b;
+  b.cw = nu + 8; b.ce = nv + 8; b.ct = 2 * nu + nv + 16;
+  b.W = ws; b.U2 = b.W + b.cw; b.E = b.U2 + b.cw; b.T = b.E + b.ce;
+  return b;
+}
+
+// Exact fix-up at scale c: given w (lw limbs, approximately floor(B^c / v)),
+// make w = floor(B^c / v) and E = B^c - v w in [0, v).  Returns the new lw.
+__device__ inline int fixup(const uint32_t* v, int k1, int c, Bufs& bf, int lw, Shared* sh,
+                            char* smem, int* adjust) {
+  // P = v * w
+  const int lp = k1 + lw;
+  wg_mul(bf.T, v, k1, bf.W, lw, smem);
+  // sign: P >= B^c  <=>  some limb at index >= c is nonzero
+  const int pp = wg_prec(bf.T, lp, sh);
+  const int le = max(k1 + 2, 2);
+  bool neg;
+  if (pp <= c) {
+    // e = B^c - P (P < B^c): the low c limbs of 0 - P; it is < few v
+    neg = false;
+    auto X = [&](int) -> uint32_t { return 0u; };
+    auto Y = [&](int j) -> uint32_t { return j < lp ? bf.T[j] : 0u; };
+    wg_addsub<4, true>(bf.T, min(c, lp), X, Y, 0u, sh->scan);  // in place
+    // limbs [min(c,lp), c) of 0 - P are all ones only if P == 0, which w >= 1 rules out
+    wg_shr_copy(bf.E, le, bf.T, min(c, lp), 0);
+    if (c > lp) {
+      // B^c - P with P < B^lp <= B^(c-1): e would be >= B^(c-1) -- far from w
+      // exact; keep it exact anyway by filling the all-ones limbs
+      for (int i = threadIdx.x; i < le; i += blockDim.x)
+        if (i >= lp && i < c) bf.E[i] = 0xffffffffu;
+      __syncthreads();
+    }
+  } else {
+    // e = -(P - B^c)
+    neg = true;
+    wg_arith1<true>(bf.T + c, lp - c, bf.T + c, lp - c, 1u, sh);
+    wg_shr_copy(bf.E, le, bf.T, lp, 0);
+  }
+  int adj = 0;
+  // while e < 0: w -= 1, e += v   (a correct estimate needs at most a few
+  // rounds; the cap only guarantees that every wave terminates)
+  while (neg && adj < kMaxAdjust) {
+    wg_arith1<true>(bf.W, lw, bf.W, lw, 1u, sh);
+    // |e| vs v
+    const int s = wg_cmp(bf.E, le, v, k1, le, sh);
+    if (s > 0) {
+      wg_arith<true>(bf.E, le, bf.E, le, v, k1, sh);   // |e| - v, still negative
+    } else {
+      wg_arith<true>(bf.E, le, v, k1, bf.E, le, sh);   // v - |e| >= 0
+      neg = false;
+    }
+    ++adj;
+  }
+  // while e >= v: w += 1, e -= v
+  while (adj < kMaxAdjust) {
+    const int s = wg_cmp(bf.E, le, v, k1, le, sh);
+    if (s < 0) break;
+    wg_arith<true>(bf.E, le, bf.E, le, v, k1, sh);
+    const uint32_t c2 = wg_arith1<false>(bf.W, lw, bf.W, lw, 1u, sh);
+    if (c2) {  // w grew by one limb
+      if (threadIdx.x == 0) bf.W[lw] = 1u;
+      __syncthreads();
+      ++lw;
+    }
+    ++adj;
+  }
+  if (adjust) *adjust += adj;
+  if (adj >= kMaxAdjust) sh->failed = 1u;
+  return wg_prec(bf.W, lw, sh) > 0 ? wg_prec(bf.W, lw, sh) : 1;
+}
+
+// w = floor(B^h / v) for a divisor with k1 >= 2 significant limbs and h >= k1.
+// Leaves w in bf.W and returns its limb count; E = B^h - v w.
+__device__ inline int shifted_inverse(const uint32_t* v, int k1, int h, Bufs& bf, Shared* sh,
+                                      char* smem, int* adjust) {
+  const int k = k1 - 1;
+  // starting value: floor(B^(k+2) / v) from below, using the top three limbs
+  if (threadIdx.x == 0) {
+    typedef unsigned __int128 u128;
+    u128 w0;
+    if (k1 == 2) {
+      // exact: floor(B^3 / (v1 B + v0))
+      const u128 V = ((u128)v[1] << 32) | v[0];
+      w0 = udiv128((u128)1 << 96, V);
+    } else {
+      const u128 V3 = ((u128)v[k] << 64) | ((u128)v[k - 1] << 32) | v[k - 2];
+      w0 = udiv128(~(u128)0, V3 + 1);
+    }
+    sh->w0[0] = (uint32_t)w0;
+    sh->w0[1] = (uint32_t)(w0 >> 32);
+    sh->w0[2] = (uint32_t)(w0 >> 64);
+    sh->w0[3] = (uint32_t)(w0 >> 96);
+  }
+  __syncthreads();
+  int cur = k + 2;
+  int lw;
+  if (h < cur) {
+    // h == k1: w = floor(B^h / v) < B; start from w0 / B
+    cur = h;
+    for (int i = threadIdx.x; i < 4; i += blockDim.x) bf.W[i] = (i < 3) ? sh->w0[i + 1] : 0u;
+    __syncthreads();
+    lw = 3;
+  } else {
+    for (int i = threadIdx.x; i < 4; i += blockDim.x) bf.W[i] = sh->w0[i];
+    __syncthreads();
+    lw = 4;
+  }
+  lw = wg_prec(bf.W, lw, sh);
+  if (lw == 0) {  // estimate 0: start from 1 (the fix-up walks up)
+    if (threadIdx.x == 0) bf.W[0] = 1u;
+    __syncthreads();
+    lw = 1;
+  }
+  lw = fixup(v, k1, cur, bf, lw, sh, smem, adjust);
+  while (cur < h) {
+    const int m = min(h - cur, cur - k1);
+    // Y = w * e (e < v has at most k1 limbs)
+    const int le = wg_prec(bf.E, k1 + 2, sh);
+    int lnew;
+    if (le == 0) {
+      // e = 0: v divides B^cur, so w' = w B^m exactly
+      lnew = lw + m;
+      wg_fill(bf.U2, lnew + 1, 0u);
+      for (int i = threadIdx.x; i < lw; i += blockDim.x) bf.U2[i + m] = bf.W[i];
+      __syncthreads();
+    } else {
+      wg_mul(bf.T, bf.W, lw, bf.E, le, smem);
+      const int ly = lw + le;
+      // w' = w B^m + floor(Y / B^(cur - m))
+      lnew = lw + m + 1;
+      auto X = [&](int j) -> uint32_t { return (j >= m && j - m < lw) ? bf.W[j - m] : 0u; };
+      auto Y = [&](int j) -> uint32_t {
+        const int s = j + cur - m;
+        return s < ly ? bf.T[s] : 0u;
+      };
+      wg_addsub<4, false>(bf.U2, lnew, X, Y, 0u, sh->scan);
+    }
+    wg_copy(bf.W, bf.U2, lnew);
+    lw = wg_prec(bf.W, lnew, sh);
+    cur += m;
+    lw = fixup(v, k1, cur, bf, lw, sh, smem, adjust);
+  }
+  return lw;
+}
+
+// q[0..nq), r[0..nr) = divmod(u[0..nu), v[0..nv)); returns the status.
+// With inverse_only, writes floor(B^h_inv / v) into q[0..nq) instead.
+__device__ inline int wg_divmod(uint32_t* q, int nq, uint32_t* r, int nr, const uint32_t* u, int nu,
+                                const uint32_t* v, int nv, Bufs bf, Shared* sh, char* smem,
+                                bool inverse_only, int h_inv, int* adjust) {
+  if (threadIdx.x == 0) sh->failed = 0u;
+  __syncthreads();
+  const int k1 = wg_prec(v, nv, sh);
+  if (k1 == 0) {
+    if (!inverse_only) {
+      wg_fill(q, nq, 0u);
+      wg_shr_copy(r, nr, u, nu, 0);
+    } else {
+      wg_fill(q, nq, 0u);
+    }
+    return BIGINT_DIVZERO;
+  }
+  const int h = inverse_only ? h_inv : wg_prec(u, nu, sh);
+  if (!inverse_only && h < k1) {  // u < v
+    wg_fill(q, nq, 0u);
+    wg_shr_copy(r, nr, u, nu, 0);
+    return BIGINT_DIV_OK;
+  }
+  if (k1 == 1) {
+    // short division by one limb (one lane walks the limbs top down)
+    const uint32_t d = v[0];
+    if (!inverse_only) wg_fill(q, nq, 0u);
+    else wg_fill(q, nq, 0u);
+    if (threadIdx.x == 0) {
+      uint64_t rem = 0;
+      for (int i = h - (inverse_only ? 0 : 1); i >= 0; --i) {
+        const uint32_t limb = inverse_only ? (i == h ? 1u : 0u) : u[i];
+        const uint64_t t = (rem << 32) | limb;
+        const uint64_t qq = t / d;
+        rem = t - qq * d;
+        if (i < nq) q[i] = (uint32_t)qq;
+      }
+      if (!inverse_only) {
+        for (int i = 0; i < nr; ++i) r[i] = i == 0 ? (uint32_t)rem : 0u;
+      }
+    }
+    __syncthreads();
+    return BIGINT_DIV_OK;
+  }
+  int lw = shifted_inverse(v, k1, h, bf, sh, smem, adjust);
+  if (inverse_only) {
+    wg_shr_copy(q, nq, bf.W, lw, 0);
+    return sh->failed ? BIGINT_DIV_FAILED : BIGINT_DIV_OK;
+  }
+  // q = floor(u w / B^h)
+  wg_mul(bf.T, u, h, bf.W, lw, smem);
+  const int lz = h + lw;
+  const int lq = max(lz - h, 1);
+  wg_shr_copy(bf.U2, lq + 1, bf.T, lz, h);
+  // r = u - q v
+  const int lq2 = max(wg_prec(bf.U2, lq + 1, sh), 1);
+  wg_mul(bf.T, bf.U2, lq2, v, k1, smem);
+  const int lqv = lq2 + k1;
+  wg_arith<true>(bf.E, k1 + 2, u, h, bf.T, lqv, sh);   // fits: 0 <= r < 2v
+  // one correction: r >= v  ->  q += 1, r -= v
+  if (wg_cmp(bf.E, k1 + 2, v, k1, k1 + 2, sh) >= 0) {
+    wg_arith<true>(bf.E, k1 + 2, bf.E, k1 + 2, v, k1, sh);
+    wg_arith1<false>(bf.U2, lq2 + 1, bf.U2, lq2, 1u, sh);
+    if (adjust) *adjust += 1;
+  }
+  wg_shr_copy(q, nq, bf.U2, lq2 + 1, 0);
+  wg_shr_copy(r, nr, bf.E, k1 + 2, 0);
+  return sh->failed ? BIGINT_DIV_FAILED : BIGINT_DIV_OK;
+}
+
+}  // namespace div
+}  // namespace bi

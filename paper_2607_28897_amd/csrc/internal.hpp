@@ -40,4 +40,13 @@ int launch_mul_ragged(uint32_t* out, const int64_t* out_off, const uint32_t* a,
                       const QueueItem* queue, int64_t nitems, uint32_t* counter, bool plain,
                       size_t lds, int waves, int grid, hipStream_t s);
 
+// ---- division -------------------------------------------------------------------
+size_t div_ws_bytes(int cap_u, int cap_v, int grid);
+size_t div_lds_bytes(int cap_u, int cap_v);
+int launch_divmod(uint32_t* q, const int64_t* q_off, uint32_t* r, const int64_t* r_off,
+                  int32_t* status, const uint32_t* u, const int64_t* u_off, int nu,
+                  const uint32_t* v, const int64_t* v_off, int nv, const int32_t* queue,
+                  int64_t nitems, void* ws, int cap_u, int cap_v, int grid, int h_inv,
+                  int32_t* adjust, hipStream_t s);
+
 }  // namespace bi

@@ -1,0 +1,108 @@
+"""GPU parity: division through the whole shifted inverse (Newton steps on the
+MFMA-split multiply) against the oracle's Knuth division, and the shifted
+inverse itself against floor(B^h / v)."""
+import numpy as np
+import pytest
+
+from gpu_util import dev, host, rand_limbs
+
+pytestmark = pytest.mark.gpu
+
+EDGE = np.array([0, 1, 2, 0x7FFFFFFF, 0x80000000, 0xFFFFFFFE, 0xFFFFFFFF], np.uint32)
+
+
+@pytest.fixture(scope="module")
+def bi():
+    import paper_2607_28897_amd as m
+    m.lib()
+    return m
+
+
+def _check_batch(bi, orc, u, v):
+    q, r, st = bi.divmod(dev(u), dev(v))
+    q, r, st = host(q), host(r), st.cpu().numpy()
+    for i in range(u.shape[0]):
+        wq, wr, ws = orc.divmod1(u[i], v[i])
+        assert st[i] == ws, i
+        assert np.array_equal(q[i], wq), i
+        assert np.array_equal(r[i], wr), i
+
+
+@pytest.mark.parametrize("nu,nv", [(1, 1), (2, 1), (5, 1), (2, 2), (3, 2), (4, 3), (7, 3), (8, 4),
+                                   (20, 10), (64, 3), (100, 99), (257, 128), (1000, 500), (2048, 1024),
+                                   (3000, 7), (9, 20)])
+def test_shapes_random(bi, orc, nu, nv):
+    g = np.random.default_rng(nu * 131 + nv)
+    B = 6
+    u = rand_limbs(g, B, nu)
+    v = rand_limbs(g, B, nv)
+    v[1, -1] = 1                           # small top limb
+    v[2] = 0xFFFFFFFF                       # all ones
+    v[3, nv // 2:] = 0                      # leading zero limbs: precision below nv
+    if nv > 1:
+        v[3, 0] = max(v[3, 0], 1)
+    u[4] = 0xFFFFFFFF
+    u[5, :] = 0
+    _check_batch(bi, orc, u, v)
+
+
+def test_special_values(bi, orc):
+    n = 40
+    rows_u, rows_v = [], []
+    g = np.random.default_rng(3)
+    base = rand_limbs(g, 1, n)[0]
+    one = np.zeros(n, np.uint32); one[0] = 1
+    rows_u.append(base); rows_v.append(one)                        # v = 1
+    rows_u.append(base); rows_v.append(base.copy())                # u = v
+    small = base.copy(); small[-1] = 0
+    rows_u.append(small); rows_v.append(base.copy())               # u < v
+    rows_u.append(base); rows_v.append(np.zeros(n, np.uint32))     # v = 0
+    half = np.zeros(n, np.uint32); half[: n // 2] = 0xFFFFFFFF     # (B^2m - 1) / (B^m - 1)
+    rows_u.append(np.full(n, 0xFFFFFFFF, np.uint32)); rows_v.append(half)
+    pw = np.zeros(n, np.uint32); pw[n // 2] = 1                     # v = B^m
+    rows_u.append(base); rows_v.append(pw)
+    u = np.stack(rows_u); v = np.stack(rows_v)
+    _check_batch(bi, orc, u, v)
+
+
+def test_edge_alphabet(bi, orc):
+    g = np.random.default_rng(11)
+    for nu, nv in ((3, 2), (4, 3), (6, 4), (9, 5)):
+        u = g.choice(EDGE, size=(64, nu))
+        v = g.choice(EDGE, size=(64, nv))
+        _check_batch(bi, orc, u, v)
+
+
+def test_config5_sampled(bi, orc):
+    import torch
+    from paper_2607_28897_amd import inputs
+    c = inputs.config5()
+    nu, nv = c["nu"], c["nv"]
+    plan = bi.DivPlan(nu, nv)
+    q, r, st = plan(dev(c["u"]), torch.from_numpy(c["u_off"]).cuda(), dev(c["v"]),
+                    torch.from_numpy(c["v_off"]).cuda())
+    q, r, st = host(q), host(r), st.cpu().numpy()
+    assert not st.any()
+    order = np.argsort(-nu)
+    sample = list(order[:3]) + list(order[-3:]) + list(range(0, 512, 61))
+    u_off, v_off = c["u_off"], c["v_off"]
+    for i in sample:
+        u = c["u"][u_off[i]:u_off[i + 1]]
+        v = c["v"][v_off[i]:v_off[i + 1]]
+        wq, wr, _ = orc.divmod1(u, v)
+        assert np.array_equal(q[u_off[i]:u_off[i + 1]], wq), i
+        assert np.array_equal(r[v_off[i]:v_off[i + 1]], wr), i
+    plan.close()
+
+
+@pytest.mark.parametrize("nv,h", [(1, 1), (1, 9), (2, 2), (2, 7), (3, 3), (5, 40), (64, 130), (500, 2000)])
+def test_shifted_inverse(bi, orc, nv, h):
+    g = np.random.default_rng(nv * 7 + h)
+    v = rand_limbs(g, 4, nv)
+    v[:, -1] |= 1
+    v[1, -1] = 1
+    v[2] = 0xFFFFFFFF
+    w = host(bi.shinv(dev(v), h))
+    for i in range(4):
+        want, _ = orc.shinv1(v[i], h)
+        assert np.array_equal(w[i], want), i
