@@ -39,6 +39,9 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--cpu-seconds", type=float, default=15.0,
                    help="target CPU work (core-seconds) of the oracle sample")
+    p.add_argument("--mode", default="bench", choices=["bench", "copy", "mfma-peak"],
+                   help="copy: a plain copy kernel of known size (counter calibration); "
+                        "mfma-peak: register-only int8 MFMA rate probe")
     p.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "mfma_mul_2e19_traffic.json"),
                    help="HBM traffic per launch from rocprofv3 counters, if measured")
     return p.parse_args()
@@ -108,6 +111,11 @@ def main():
     import torch
     import paper_2607_28897_amd as bi
     from paper_2607_28897_amd import inputs
+
+    if args.mode == "copy":
+        return copy_mode(torch)
+    if args.mode == "mfma-peak":
+        return peak_mode(torch, bi)
 
     cfg = inputs.config3(args.batch)
     a_np, b_np, n = cfg["a"], cfg["b"], cfg["n"]
@@ -194,6 +202,45 @@ def main():
         line["cpu_baseline"] = cpu
         line["bit_exact_sample"] = exact
     print(json.dumps(line), flush=True)
+
+
+def copy_mode(torch):
+    """y = -x over 256 MiB of int32: 256 MiB read + 256 MiB written per launch,
+    the reference for scaling the FETCH_SIZE / WRITE_SIZE counters."""
+    n = 64 * 1024 * 1024
+    x = torch.arange(n, dtype=torch.int32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        torch.neg(x, out=y)
+    torch.cuda.synchronize()
+    print(json.dumps({"mode": "copy", "bytes_read_per_launch": 4 * n, "bytes_written_per_launch": 4 * n,
+                      "launches": 3}))
+
+
+def peak_mode(torch, bi):
+    """Achievable int8 MFMA rate with no memory traffic (v_mfma_i32_16x16x64_i8,
+    8 independent accumulators per wave), for 4..64 waves per CU."""
+    import ctypes
+    L = bi.lib()
+    out = torch.empty(8192 * 256, dtype=torch.int32, device="cuda")
+    s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    ncu = torch.cuda.get_device_properties(0).multi_processor_count
+    res = {}
+    for per_cu in (1, 2, 4, 8, 16):
+        blocks, iters = ncu * per_cu, 4000
+        L.bigint_diag_mfma_rate(ctypes.c_void_p(out.data_ptr()), blocks, 100, s)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        rc = L.bigint_diag_mfma_rate(ctypes.c_void_p(out.data_ptr()), blocks, iters, s)
+        e1.record()
+        torch.cuda.synchronize()
+        if rc:
+            raise bi.BigIntError(rc, "bigint_diag_mfma_rate")
+        ms = e0.elapsed_time(e1)
+        macs = blocks * 4 * iters * 8 * 16384
+        res[f"{4 * per_cu}_waves_per_cu_TOPs"] = round(2 * macs / ms / 1e9, 1)
+    print(json.dumps({"mode": "mfma-peak", "cus": ncu, **res}))
 
 
 def kernel_sha():

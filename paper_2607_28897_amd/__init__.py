@@ -82,6 +82,7 @@ def lib() -> ctypes.CDLL:
             "bigint_conv7": ([_vp, _vp, _i64, _vp, _i64, _i64, _vp], _int),
             "bigint_shinv": ([_vp, _vp, _i64, _i64, _i64, _vp], _int),
             "bigint_set_mfma_config": ([_int, _int], _int),
+            "bigint_diag_mfma_rate": ([_vp, _i64, _i64, _vp], _int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)

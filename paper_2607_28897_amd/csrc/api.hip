@@ -436,7 +436,148 @@ int bigint_divmod_ragged(uint32_t* q, const int64_t* q_off, uint32_t* r, const i
                        plan->cap_u, plan->cap_v, plan->grid, -1, nullptr, s);
 }
 
-int bigint_autotune(const char*, int) { return BIGINT_EUNSUPPORTED; }
-int bigint_autotune_load(const char*) { return BIGINT_EUNSUPPORTED; }
+int bigint_diag_mfma_rate(int32_t* scratch, int64_t blocks, int64_t iters, void* stream) {
+  if (!scratch || blocks <= 0 || iters <= 0) return BIGINT_EINVAL;
+  if (blocks > (1 << 20) || iters > (1 << 24)) return BIGINT_EUNSUPPORTED;
+  return launch_mfma_rate(scratch, (int)blocks, (int)iters, (hipStream_t)stream);
+}
+
+// ---- autotuning ------------------------------------------------------------------
+// For each size bin, every tile configuration (strips per band P, waves per
+// work-group) multiplies the same random batch; the fastest is kept.  All
+// candidates must give identical bytes (checked on the first instance).
+
+int bigint_autotune(const char* cache_path, int flags) {
+  (void)flags;
+  static const int kBins[] = {1024, 2048, 4096, 8192, 16384};
+  static const int kP[] = {4, 8, 16};
+  static const int kW[] = {4, 8};
+  std::vector<TuneEntry> table;
+  hipStream_t s = nullptr;
+  BI_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  BI_HIP(hipEventCreate(&e0));
+  BI_HIP(hipEventCreate(&e1));
+  int rc = BIGINT_OK;
+  for (size_t bi_ = 0; bi_ < sizeof(kBins) / sizeof(kBins[0]) && rc == BIGINT_OK; ++bi_) {
+    const int n = kBins[bi_];
+    const int batch = std::max(64, (int)(num_cus() * 2 * (16384.0 / n) * (16384.0 / n) / 16));
+    const int nb = std::min(batch, 4096);
+    const size_t in_bytes = (size_t)nb * n * 4, out_bytes = (size_t)nb * 2 * n * 4;
+    uint32_t *a = nullptr, *b = nullptr, *out = nullptr;
+    if (hipMalloc(&a, in_bytes) != hipSuccess || hipMalloc(&b, in_bytes) != hipSuccess ||
+        hipMalloc(&out, out_bytes) != hipSuccess) {
+      rc = BIGINT_ENOMEM;
+    }
+    std::vector<uint32_t> host((size_t)nb * n), first, cur(2 * (size_t)n);
+    if (rc == BIGINT_OK) {
+      uint64_t x = 0x9e3779b97f4a7c15ull ^ (uint64_t)n;  // splitmix64 stream
+      auto next = [&]() {
+        uint64_t z = (x += 0x9e3779b97f4a7c15ull);
+        z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+        z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+        return z ^ (z >> 31);
+      };
+      for (auto& v : host) v = (uint32_t)next();
+      if (hipMemcpy(a, host.data(), in_bytes, hipMemcpyHostToDevice) != hipSuccess) rc = BIGINT_EHIP;
+      for (auto& v : host) v = (uint32_t)next();
+      if (rc == BIGINT_OK && hipMemcpy(b, host.data(), in_bytes, hipMemcpyHostToDevice) != hipSuccess)
+        rc = BIGINT_EHIP;
+    }
+    float best = 1e30f;
+    TuneEntry pick{n, 16, 8};
+    for (int P : kP)
+      for (int W : kW) {
+        if (rc != BIGINT_OK) break;
+        const MfmaCfg cfg{P, W};
+        if (mfma_lds(n, n, cfg) > 163840) continue;
+        rc = launch_mul_mfma(out, nullptr, a, n, b, n, nb, cfg, s);  // warm-up
+        if (rc != BIGINT_OK) break;
+        if (hipEventRecord(e0, s) != hipSuccess) { rc = BIGINT_EHIP; break; }
+        for (int rep = 0; rep < 3 && rc == BIGINT_OK; ++rep)
+          rc = launch_mul_mfma(out, nullptr, a, n, b, n, nb, cfg, s);
+        if (rc != BIGINT_OK) break;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+          rc = BIGINT_EHIP;
+          break;
+        }
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rc = BIGINT_EHIP; break; }
+        if (hipMemcpy(cur.data(), out, cur.size() * 4, hipMemcpyDeviceToHost) != hipSuccess) {
+          rc = BIGINT_EHIP;
+          break;
+        }
+        if (first.empty()) first = cur;
+        else if (first != cur) { rc = BIGINT_EHIP; set_hip_error(hipErrorUnknown); break; }
+        if (ms < best) { best = ms; pick = TuneEntry{n, P, W}; }
+      }
+    if (a) (void)hipFree(a);
+    if (b) (void)hipFree(b);
+    if (out) (void)hipFree(out);
+    table.push_back(pick);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipStreamDestroy(s);
+  if (rc != BIGINT_OK) return rc;
+  // bins switch at the geometric midpoints between the tuned sizes
+  for (size_t i = 0; i + 1 < table.size(); ++i)
+    table[i].max_limbs = (int)(table[i].max_limbs * 1.41421356);
+  table.back().max_limbs = BIGINT_MFMA_MAX_LIMBS;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune = table;
+  }
+  if (cache_path) {
+    FILE* f = fopen(cache_path, "w");
+    if (!f) return BIGINT_EINVAL;
+    int dev = 0;
+    hipDeviceProp_t prop;
+    (void)hipGetDevice(&dev);
+    const bool have = hipGetDeviceProperties(&prop, dev) == hipSuccess;
+    fprintf(f, "{\"arch\": \"%s\", \"op\": \"mul_mfma\", \"bins\": [", have ? prop.gcnArchName : "?");
+    for (size_t i = 0; i < table.size(); ++i)
+      fprintf(f, "%s{\"max_limbs\": %d, \"strips_per_band\": %d, \"waves\": %d}", i ? ", " : "",
+              table[i].max_limbs, table[i].P, table[i].waves);
+    fprintf(f, "]}\n");
+    fclose(f);
+  }
+  return BIGINT_OK;
+}
+
+// Reads a table written by bigint_autotune (the fields are read in order).
+int bigint_autotune_load(const char* cache_path) {
+  if (!cache_path) return BIGINT_EINVAL;
+  FILE* f = fopen(cache_path, "r");
+  if (!f) return BIGINT_EINVAL;
+  std::string txt;
+  char buf[4096];
+  size_t k;
+  while ((k = fread(buf, 1, sizeof(buf), f)) > 0) txt.append(buf, k);
+  fclose(f);
+  std::vector<TuneEntry> table;
+  size_t pos = 0;
+  auto field = [&](const char* name, int* v) {
+    const size_t q = txt.find(name, pos);
+    if (q == std::string::npos) return false;
+    const size_t c = txt.find(':', q);
+    if (c == std::string::npos) return false;
+    *v = atoi(txt.c_str() + c + 1);
+    pos = c + 1;
+    return true;
+  };
+  for (;;) {
+    TuneEntry e;
+    if (!field("\"max_limbs\"", &e.max_limbs)) break;
+    if (!field("\"strips_per_band\"", &e.P) || !field("\"waves\"", &e.waves)) return BIGINT_EINVAL;
+    if ((e.P != 4 && e.P != 8 && e.P != 16) || (e.waves != 4 && e.waves != 8) || e.max_limbs <= 0)
+      return BIGINT_EINVAL;
+    table.push_back(e);
+  }
+  if (table.empty()) return BIGINT_EINVAL;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune = table;
+  return BIGINT_OK;
+}
 
 }  // extern "C"

@@ -65,8 +65,12 @@ struct LimbRun {
 // blockDim*Q limbs, carry chained between rounds).  Returns the carry
 // (borrow) out of limb n-1 in every thread.  out may alias the storage that
 // X or Y read, limb for limb.
-template <int Q, bool SUB, class FX, class FY>
+//
+// SPARSE: out aliases X's storage and most Y limbs are zero; a limb is only
+// stored when its value changes (saves rewriting the whole array).
+template <int Q, bool SUB, class FX, class FY, bool SPARSE = false>
 __device__ __forceinline__ uint32_t wg_addsub(uint32_t* out, int n, FX X, FY Y, uint32_t cin, uint32_t* scratch) {
+  constexpr bool out_differs = false;
   const int T = blockDim.x;
   uint32_t carry = cin;
   for (int base = 0; base < n; base += T * Q) {
@@ -85,7 +89,7 @@ __device__ __forceinline__ uint32_t wg_addsub(uint32_t* out, int n, FX X, FY Y, 
     run.apply(c);
 #pragma unroll
     for (int i = 0; i < Q; ++i)
-      if (i < valid) out[j0 + i] = run.s[i];
+      if (i < valid && (!SPARSE || run.s[i] != x[i] || out_differs)) out[j0 + i] = run.s[i];
     carry = cout;
     __syncthreads();
   }

@@ -108,8 +108,10 @@ __device__ __forceinline__ uint32_t wg_arith1(uint32_t* dst, int n, const uint32
   return wg_addsub<4, SUB>(dst, n, X, Y, 0u, sh->scan);
 }
 
-// dst[0 .. na+nb) = a * b (MFMA-split multiply; dst must not overlap a, b)
-__device__ __forceinline__ void wg_mul(uint32_t* dst, const uint32_t* a, int na, const uint32_t* b,
+// dst[0 .. na+nb) = a * b (MFMA-split multiply; dst must not overlap a, b).
+// One out-of-line copy serves every call site of the division, so the
+// kernel's code stays small enough for the instruction cache.
+__device__ __noinline__ void wg_mul(uint32_t* dst, const uint32_t* a, int na, const uint32_t* b,
                                        int nb, char* smem) {
   mfma::wg_mul_mfma<kP>(dst, nullptr, a, na, b, nb, smem);
 }

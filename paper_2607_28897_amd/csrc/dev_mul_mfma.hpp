@@ -162,35 +162,50 @@ __device__ __forceinline__ int band_cost(const Geo& g, int band, int P) {
   return c;
 }
 
+// A tile x of phase rho.  Tiles entirely outside alpha read the zero padding
+// at the start of Abuf (every lane the same 16 bytes), so no branch is needed.
 __device__ __forceinline__ v4i load_A(const uint8_t* Abuf, const Geo& g, int x, int rho,
                                       const Range& r) {
-  v4i v = {0, 0, 0, 0};
-  if (x >= r.xlo && x <= r.xhi) {  // wave-uniform
-    const int lane = lane_id();
-    const int Z = 256 * x - 64 * rho;
-    const int addr = g.QA - Z - 16 * (lane & 15) + 16 * (lane >> 4);
-    v = *reinterpret_cast<const v4i*>(Abuf + addr);
-  }
-  return v;
+  const int lane = lane_id();
+  const int Z = 256 * x - 64 * rho;
+  const bool ok = x >= r.xlo && x <= r.xhi;  // wave-uniform
+  const int addr = ok ? g.QA - Z - 16 * (lane & 15) + 16 * (lane >> 4) : 0;
+  return *reinterpret_cast<const v4i*>(Abuf + addr);
 }
 
-__device__ __forceinline__ v4i load_B(const uint8_t* Bbuf, int y, int rho) {
+// B tile y of phase rho in two halves: the five aligned dwords a lane needs
+// (issued early) and their byte alignment into the operand (done late).
+struct BRaw {
+  uint32_t d[5];
+};
+
+__device__ __forceinline__ BRaw load_B_raw(const uint8_t* Bbuf, int y, int rho) {
   const int lane = lane_id();
   const int p = lane & 15;
   const int Y = 256 * y + 64 * rho;
   const uint32_t* src =
       reinterpret_cast<const uint32_t*>(Bbuf + kPadB + Y + 16 * (lane >> 4) + 4 * (p >> 2));
-  const uint32_t d0 = src[0], d1 = src[1], d2 = src[2], d3 = src[3], d4 = src[4];
-  const uint32_t sh = p & 3;
+  BRaw b;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) b.d[i] = src[i];
+  return b;
+}
+
+__device__ __forceinline__ v4i align_B(const BRaw& b) {
+  const uint32_t sh = lane_id() & 3;
   v4i v;
-  v.x = (int)__builtin_amdgcn_alignbyte(d1, d0, sh);
-  v.y = (int)__builtin_amdgcn_alignbyte(d2, d1, sh);
-  v.z = (int)__builtin_amdgcn_alignbyte(d3, d2, sh);
-  v.w = (int)__builtin_amdgcn_alignbyte(d4, d3, sh);
+  v.x = (int)__builtin_amdgcn_alignbyte(b.d[1], b.d[0], sh);
+  v.y = (int)__builtin_amdgcn_alignbyte(b.d[2], b.d[1], sh);
+  v.z = (int)__builtin_amdgcn_alignbyte(b.d[3], b.d[2], sh);
+  v.w = (int)__builtin_amdgcn_alignbyte(b.d[4], b.d[3], sh);
   return v;
 }
 
 // One phase of one band: acc[i] += sum over the y range of A(w0+i-y) B(y).
+// Software pipeline per step: the step's P MFMAs run on the B tile aligned at
+// the end of the previous step; the raw dwords of the next B tile were loaded
+// one step earlier, and the one new A tile goes into the ring slot that the
+// first MFMA of the step has just read.
 template <int P>
 __device__ __forceinline__ void band_phase(v4i (&acc)[P], const Lds& s, const Geo& g, int w0,
                                            int rho) {
@@ -201,35 +216,50 @@ __device__ __forceinline__ void band_phase(v4i (&acc)[P], const Lds& s, const Ge
   v4i ring[P];
 #pragma unroll
   for (int i = 0; i < P; ++i) ring[i] = load_A(s.A, g, xb + i, rho, r);
+  v4i Bc = align_B(load_B_raw(s.B, r.lo, rho));
+  BRaw raw = load_B_raw(s.B, min(r.lo + 1, r.hi), rho);
 
-  int u = 0;
-  v4i Bc = load_B(s.B, r.lo, rho);
+  // one step of the pipeline (st = step mod P, known at compile time).  The
+  // next B tile is aligned into a second register set half-way through the
+  // step, so the step boundary carries no VALU -> MFMA dependency.
+  auto step_fn = [&](const int step, const int st) __attribute__((always_inline)) {
+    // strip P-1 first: its slot is the one the next step's new tile takes
+    acc[P - 1] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ring[(2 * P - 1 - st) % P], Bc,
+                                                        acc[P - 1], 0, 0, 0);
+    ring[(2 * P - 1 - st) % P] = load_A(s.A, g, xb - step - 1, rho, r);
+#pragma unroll
+    for (int i = P - 2; i >= P / 2; --i)
+      acc[i] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ring[(P + i - st) % P], Bc, acc[i], 0, 0, 0);
+    __builtin_amdgcn_sched_barrier(0);
+    const v4i Bn = align_B(raw);
+    raw = load_B_raw(s.B, min(r.lo + step + 2, r.hi), rho);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int i = P / 2 - 1; i >= 0; --i)
+      acc[i] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ring[(P + i - st) % P], Bc, acc[i], 0, 0, 0);
+    __builtin_amdgcn_sched_barrier(0);
+    Bc = Bn;
+  };
+  // full blocks of P steps: no exit inside, the ring returns to its layout
+  const int nfull = L / P;
 #pragma unroll 1
-  for (;;) {
+  for (int blk = 0; blk < nfull; ++blk) {
 #pragma unroll
-    for (int st = 0; st < P; ++st) {
-      const int step = u + st;
-      // next B tile (clamped to the range so the read stays in bounds)
-      const int ynext = min(r.lo + step + 1, r.hi);
-      const v4i Bn = load_B(s.B, ynext, rho);
-      // strip P-1 first: its slot is the one the next step overwrites
-      acc[P - 1] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ring[(2 * P - 1 - st) % P], Bc,
-                                                          acc[P - 1], 0, 0, 0);
-      ring[(2 * P - 1 - st) % P] = load_A(s.A, g, xb - step - 1, rho, r);
+    for (int st = 0; st < P; ++st) step_fn(blk * P + st, st);
+  }
+  // the remaining L mod P steps
+  const int rem = L - nfull * P;
+  if (rem > 0) {
+    // a guarded, fully unrolled block keeps every ring index a constant
 #pragma unroll
-      for (int i = P - 2; i >= 0; --i)
-        acc[i] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ring[(P + i - st) % P], Bc, acc[i], 0,
-                                                       0, 0);
-      Bc = Bn;
-      if (step + 1 >= L) return;
-    }
-    u += P;
+    for (int st = 0; st < P - 1; ++st)
+      if (st < rem) step_fn(nfull * P + st, st);
   }
 }
 
 // Per strip: turn the 256 coefficients of acc (strip w) into 56 limbs of out
 // and the strip carry word; or, for the diagnostic path, store them raw.
-__device__ __noinline__ void strip_out(v4i acc, int w, const Lds& s, const Geo& g,
+__device__ __forceinline__ void strip_out(v4i acc, int w, const Lds& s, const Geo& g,
                                           uint32_t* out, int32_t* coef) {
   const int lane = lane_id();
   int32_t* sc = s.wscr;
@@ -346,7 +376,7 @@ __device__ __forceinline__ void wg_mul_mfma(uint32_t* out, int32_t* coef, const 
       const uint64_t c = C[j / kStripLimbs - 1];
       return e ? (uint32_t)(c >> 32) : (uint32_t)c;
     };
-    wg_addsub<8, false>(out, g.nout, X, Y, 0u, s.misc + 1);
+    wg_addsub<8, false, decltype(X), decltype(Y), true>(out, g.nout, X, Y, 0u, s.misc + 1);
   }
   __syncthreads();
 }

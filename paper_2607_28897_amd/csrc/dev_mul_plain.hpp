@@ -156,7 +156,7 @@ __device__ __forceinline__ void wg_mul_plain(uint32_t* out, const uint32_t* __re
     const uint64_t d = Sp[2 * (pd / Q - 1) + e];
     return (j & 1) ? (uint32_t)(d >> 32) : (uint32_t)d;
   };
-  wg_addsub<8, false>(out, nout, X, Y, 0u, scratch);
+  wg_addsub<8, false, decltype(X), decltype(Y), true>(out, nout, X, Y, 0u, scratch);
 }
 
 }  // namespace bi

@@ -250,6 +250,33 @@ __global__ __launch_bounds__(1024) void k_mul_plain_ragged(uint32_t* out, const 
   }
 }
 
+// ============================================================================
+// register-only MFMA rate probe (diagnostic): every wave keeps 8 independent
+// accumulators busy with v_mfma_i32_16x16x64_i8; no memory traffic inside.
+// ============================================================================
+__global__ __launch_bounds__(256) void k_mfma_rate(int32_t* out, int iters) {
+  const int lane = lane_id();
+  v4i a = {lane, lane * 3, lane * 5, lane * 7};
+  v4i b = {lane * 11, lane * 13, lane, 1};
+  v4i acc[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) acc[j] = v4i{j, 0, 0, 0};
+  for (int i = 0; i < iters; ++i) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc[j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, acc[j], 0, 0, 0);
+  }
+  int32_t t = 0;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) t += acc[j].x + acc[j].y + acc[j].z + acc[j].w;
+  out[blockIdx.x * blockDim.x + threadIdx.x] = t;
+}
+
+int launch_mfma_rate(int32_t* out, int blocks, int iters, hipStream_t s) {
+  hipLaunchKernelGGL(k_mfma_rate, dim3(blocks), dim3(256), 0, s, out, iters);
+  BI_LAUNCH_CHECK();
+  return BIGINT_OK;
+}
+
 __global__ void k_zero_u32(uint32_t* p, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0u;

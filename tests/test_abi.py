@@ -1,0 +1,94 @@
+"""CPU-only checks of the C-ABI library: it loads, exports every function the
+header declares, and rejects bad arguments on the host before any launch."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bigint_rocm.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(bigint_\w+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def bi():
+    import paper_2607_28897_amd as m
+    if not os.path.exists(m.LIB_PATH):
+        pytest.skip("library not built")
+    m.lib()
+    return m
+
+
+def test_every_declared_symbol_is_exported(bi):
+    names = declared_functions()
+    assert len(names) >= 20
+    L = ctypes.CDLL(bi.LIB_PATH)
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_version_and_strerror(bi):
+    L = bi.lib()
+    assert L.bigint_version() >= 10000
+    for code in (0, -1, -2, -3, -4, 12345):
+        assert isinstance(L.bigint_strerror(code), bytes)
+    assert L.bigint_strerror(-1) == b"invalid argument"
+
+
+def test_host_side_argument_checks(bi):
+    L = bi.lib()
+    p = ctypes.c_void_p(0x10000)           # never dereferenced: checks fail first
+    q = ctypes.c_void_p(0x20000)
+    EINVAL, EUNS = bi.EINVAL, bi.EUNSUPPORTED
+    assert L.bigint_add(None, None, p, p, 8, 1, None) == EINVAL
+    assert L.bigint_sub(p, None, None, p, 8, 1, None) == EINVAL
+    assert L.bigint_add(p, None, p, p, 0, 1, None) == EINVAL
+    assert L.bigint_add(p, None, p, p, 8, -1, None) == EINVAL
+    assert L.bigint_add(p, None, p, p, 70000, 1, None) == EUNS
+    # partial overlap of out with an input
+    assert L.bigint_add(ctypes.c_void_p(0x10004), None, p, q, 4, 1, None) == EINVAL
+    assert L.bigint_mul(None, p, 4, p, 4, 1, 0, None) == EINVAL
+    assert L.bigint_mul(q, p, 0, p, 4, 1, 0, None) == EINVAL
+    assert L.bigint_mul(q, p, 4, p, 4, 1, 7, None) == EINVAL
+    assert L.bigint_mul(p, p, 4, q, 4, 1, 1, None) == EINVAL          # out overlaps a
+    assert L.bigint_mul(ctypes.c_void_p(0x100000), p, 20000, q, 20000, 1,
+                        bi.MUL_MFMA, None) == EUNS
+    assert L.bigint_divmod(None, q, None, p, 4, p, 4, 1, None) == EINVAL
+    assert L.bigint_divmod(ctypes.c_void_p(0x100000), ctypes.c_void_p(0x200000), None, p, 9000,
+                           q, 4, 1, None) == EUNS
+    assert L.bigint_shinv(ctypes.c_void_p(0x100000), p, 5, 4, 1, None) == EINVAL   # h < nv
+    assert L.bigint_set_mfma_config(5, 0) == EINVAL
+    assert L.bigint_set_mfma_config(0, 3) == EINVAL
+    assert L.bigint_digits7(None, p, 4, 5, 1, None) == EINVAL
+    assert L.bigint_diag_mfma_rate(None, 1, 1, None) == EINVAL
+
+
+def test_plan_argument_checks(bi):
+    L = bi.lib()
+    h = ctypes.c_void_p()
+    la = np.array([5, 0], np.int64)
+    assert L.bigint_plan_create(None, bi.OP_MUL, None, None, 0, 0) == bi.EINVAL
+    assert L.bigint_plan_create(ctypes.byref(h), 99, None, None, 0, 0) == bi.EINVAL
+    assert L.bigint_plan_create(ctypes.byref(h), bi.OP_MUL, la.ctypes.data_as(ctypes.c_void_p),
+                                la.ctypes.data_as(ctypes.c_void_p), 2, 0) == bi.EINVAL
+    assert L.bigint_plan_create(ctypes.byref(h), bi.OP_MUL, None, None, 1, 0) == bi.EINVAL
+    assert L.bigint_plan_create(ctypes.byref(h), bi.OP_MUL, None, None, 0, 64) == bi.EINVAL
+    assert L.bigint_plan_destroy(None) == bi.EINVAL
+    n = ctypes.c_size_t()
+    assert L.bigint_plan_workspace_size(None, ctypes.byref(n)) == bi.EINVAL
+    assert L.bigint_mul_ragged(None, None, None, None, None, None, 0, None, None) == bi.EINVAL
+
+
+def test_binding_fails_loudly_without_library(monkeypatch):
+    import paper_2607_28897_amd as m
+    monkeypatch.setattr(m, "_lib", None)
+    monkeypatch.setattr(m, "LIB_PATH", "/nonexistent/libbigint_rocm.so")
+    with pytest.raises(RuntimeError):
+        m.lib()
