@@ -39,9 +39,10 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--cpu-seconds", type=float, default=15.0,
                    help="target CPU work (core-seconds) of the oracle sample")
-    p.add_argument("--mode", default="bench", choices=["bench", "copy", "mfma-peak"],
+    p.add_argument("--mode", default="bench", choices=["bench", "copy", "mfma-peak", "ragged", "divmod"],
                    help="copy: a plain copy kernel of known size (counter calibration); "
-                        "mfma-peak: register-only int8 MFMA rate probe")
+                        "mfma-peak: register-only int8 MFMA rate probe; ragged / divmod: the "
+                        "4096-product ragged batch and the 512-division batch (extra lines)")
     p.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "mfma_mul_2e19_traffic.json"),
                    help="HBM traffic per launch from rocprofv3 counters, if measured")
     return p.parse_args()
@@ -116,6 +117,10 @@ def main():
         return copy_mode(torch)
     if args.mode == "mfma-peak":
         return peak_mode(torch, bi)
+    if args.mode == "ragged":
+        return ragged_mode(torch, bi, inputs, args)
+    if args.mode == "divmod":
+        return divmod_mode(torch, bi, inputs, args)
 
     cfg = inputs.config3(args.batch)
     a_np, b_np, n = cfg["a"], cfg["b"], cfg["n"]
@@ -241,6 +246,61 @@ def peak_mode(torch, bi):
         macs = blocks * 4 * iters * 8 * 16384
         res[f"{4 * per_cu}_waves_per_cu_TOPs"] = round(2 * macs / ms / 1e9, 1)
     print(json.dumps({"mode": "mfma-peak", "cus": ncu, **res}))
+
+
+def ragged_mode(torch, bi, inputs, args):
+    """4096 products, bit lengths log-uniform in [2^15, 2^19] (seed 1003), one
+    persistent launch replayed from a hipGraph; the plain kernel beside it."""
+    c = inputs.config4()
+    lens = c["lens"]
+    ta = torch.from_numpy(c["a"].view(np.int32)).cuda()
+    tb = torch.from_numpy(c["b"].view(np.int32)).cuda()
+    tao, tbo = torch.from_numpy(c["a_off"]).cuda(), torch.from_numpy(c["b_off"]).cuda()
+    Nd = (32 * lens.astype(np.float64) + 6) // 7
+    ops = 2.0 * float((Nd * Nd).sum())
+    res = {"mode": "ragged", "workload": "4096 products, operand bits log-uniform in [2^15, 2^19]",
+           "int8_ops_per_launch": ops}
+    for flags, name in ((0, "mfma_graph"), (2, "mfma_direct"), (1, "plain")):
+        plan = bi.MulPlan(lens, lens, flags)
+        out, oo = plan(ta, tao, tb, tbo)
+        steps = max(2, args.steps // (10 if flags == 1 else 2))
+        total, per = time_launches(lambda: plan(ta, tao, tb, tbo, out=out, out_off=oo), steps,
+                                   args.warmup, torch)
+        ms = total / steps
+        res[name] = {"ms": round(ms, 4), "muls_per_s": round(4096 / ms * 1e3, 1),
+                     "TOPs": round(ops / ms / 1e9, 1)}
+        if flags == 0:
+            ref = out.clone()
+        else:
+            res[name]["equals_mfma_graph"] = bool(torch.equal(out, ref))
+        plan.close()
+    print(json.dumps(res))
+
+
+def divmod_mode(torch, bi, inputs, args):
+    """512 divisions (dividend log-uniform in [2^16, 2^18] bits, divisor half
+    as many limbs), and the same-size products for the Div/Mul ratio."""
+    c = inputs.config5()
+    nu, nv = c["nu"], c["nv"]
+    tu = torch.from_numpy(c["u"].view(np.int32)).cuda()
+    tv = torch.from_numpy(c["v"].view(np.int32)).cuda()
+    tuo, tvo = torch.from_numpy(c["u_off"]).cuda(), torch.from_numpy(c["v_off"]).cuda()
+    plan = bi.DivPlan(nu, nv)
+    steps = max(3, args.steps // 5)
+    total, _ = time_launches(lambda: plan(tu, tuo, tv, tvo), steps, args.warmup, torch)
+    ms = total / steps
+    # one full product of each dividend with itself, the Div/Mul reference
+    mplan = bi.MulPlan(nu, nu)
+    out, oo = mplan(tu, tuo, tu, tuo)
+    mtotal, _ = time_launches(lambda: mplan(tu, tuo, tu, tuo, out=out, out_off=oo), steps,
+                              args.warmup, torch)
+    mms = mtotal / steps
+    print(json.dumps({"mode": "divmod", "workload": "512 divisions, dividend bits log-uniform in "
+                      "[2^16, 2^18], divisor half the limbs", "ms": round(ms, 4),
+                      "divs_per_s": round(512 / ms * 1e3, 1),
+                      "same_size_products_ms": round(mms, 4), "div_over_mul": round(ms / mms, 3)}))
+    plan.close()
+    mplan.close()
 
 
 def kernel_sha():

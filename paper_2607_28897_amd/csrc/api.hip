@@ -16,14 +16,16 @@ void set_hip_error(hipError_t e) { t_last_hip = (int)e; }
 
 static thread_local int t_cfg_P = 0, t_cfg_waves = 0;
 
-// Built-in tile choice, overridden per size bin by the autotune table.
+// Tile choice per size bin.  The built-in table is what bigint_autotune
+// picked on an MI355X; a table loaded with bigint_autotune_load (or produced
+// by bigint_autotune) replaces it.
 struct TuneEntry {
   int max_limbs;  // bin upper bound (operand limbs)
   int P, waves;
 };
 static std::mutex g_tune_mu;
 static std::vector<TuneEntry> g_tune = {
-    {1536, 4, 8}, {3072, 8, 8}, {6144, 16, 8}, {12288, 16, 8}, {BIGINT_MFMA_MAX_LIMBS, 16, 8}};
+    {1448, 4, 4}, {2896, 8, 8}, {5792, 8, 8}, {11585, 16, 8}, {BIGINT_MFMA_MAX_LIMBS, 16, 8}};
 
 MfmaCfg default_mfma_cfg(int na, int nb) {
   const int n = std::max(na, nb);
@@ -461,8 +463,9 @@ int bigint_autotune(const char* cache_path, int flags) {
   int rc = BIGINT_OK;
   for (size_t bi_ = 0; bi_ < sizeof(kBins) / sizeof(kBins[0]) && rc == BIGINT_OK; ++bi_) {
     const int n = kBins[bi_];
-    const int batch = std::max(64, (int)(num_cus() * 2 * (16384.0 / n) * (16384.0 / n) / 16));
-    const int nb = std::min(batch, 4096);
+    // enough instances to fill every CU several times at the small sizes
+    const double r = 16384.0 / n;
+    const int nb = num_cus() * std::max(1, (int)(r * r / 8));
     const size_t in_bytes = (size_t)nb * n * 4, out_bytes = (size_t)nb * 2 * n * 4;
     uint32_t *a = nullptr, *b = nullptr, *out = nullptr;
     if (hipMalloc(&a, in_bytes) != hipSuccess || hipMalloc(&b, in_bytes) != hipSuccess ||

@@ -150,3 +150,20 @@ def test_repeat_deterministic(bi):
     r1 = host(bi.mul(a, b, bi.MUL_MFMA))
     r2 = host(bi.mul(a, b, bi.MUL_MFMA))
     assert np.array_equal(r1, r2)
+
+
+def test_autotune_table_roundtrip(bi, orc, tmp_path):
+    import json
+    path = str(tmp_path / "tune.json")
+    bi.autotune(path)
+    t = json.load(open(path))
+    assert t["op"] == "mul_mfma" and len(t["bins"]) == 5
+    for e in t["bins"]:
+        assert e["strips_per_band"] in (4, 8, 16) and e["waves"] in (4, 8)
+    bi.autotune_load(path)
+    g = np.random.default_rng(9)
+    a = rand_limbs(g, 3, 5000)
+    b = rand_limbs(g, 3, 5000)
+    p = host(bi.mul(dev(a), dev(b), bi.MUL_MFMA))
+    for i in range(3):
+        assert np.array_equal(p[i], orc.mul1(a[i], b[i]))
