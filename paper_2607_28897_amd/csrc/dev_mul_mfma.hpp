@@ -109,32 +109,40 @@ __device__ __forceinline__ Lds carve(char* smem, const Geo& g, int P) {
   return s;
 }
 
+// Four consecutive 7-bit digits k0..k0+3 of the n-limb integer a (0 outside
+// [0, 32n) bits), packed low digit first: a 28-bit window of at most two
+// adjacent limbs.
+__device__ __forceinline__ uint32_t digits4(const uint32_t* __restrict__ a, int n, int k0) {
+  if (k0 < 0) {  // only in the zero padding in front of the digits
+    uint32_t w = 0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) w |= digit7(a, n, k0 + e) << (8 * e);
+    return w;
+  }
+  const int bit = 7 * k0;
+  const int l = bit >> 5, sft = bit & 31;
+  const uint64_t lo = l < n ? a[l] : 0u;
+  const uint64_t hi = l + 1 < n ? a[l + 1] : 0u;
+  const uint32_t v = (uint32_t)((lo | (hi << 32)) >> sft);
+  return (v & 0x7fu) | ((v << 1) & 0x7f00u) | ((v << 2) & 0x7f0000u) | ((v << 3) & 0x7f000000u);
+}
+
 // Stage the reversed digits of a and the digits of b into LDS (zero padded).
+// Abuf[q] = alpha[QA - q]: dword d holds digits QA-4d-3 .. QA-4d, byte-reversed.
 __device__ __forceinline__ void stage(const Lds& s, const Geo& g, const uint32_t* __restrict__ a,
-                             const uint32_t* __restrict__ b) {
+                                      const uint32_t* __restrict__ b) {
   const int T = blockDim.x;
   uint32_t* A32 = reinterpret_cast<uint32_t*>(s.A);
   uint32_t* B32 = reinterpret_cast<uint32_t*>(s.B);
-  for (int d = threadIdx.x; d < g.SA / 4; d += T) {
-    uint32_t w = 0;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int i = g.QA - (4 * d + e);
-      const uint32_t v = (i >= 0 && i < g.Na) ? digit7(a, g.na, i) : 0u;
-      w |= v << (8 * e);
-    }
-    A32[d] = w;
+  const int nA = g.SA / 4, nB = g.SB / 4;
+#pragma unroll 4
+  for (int d = threadIdx.x; d < nA; d += T) {
+    const int k0 = g.QA - 4 * d - 3;
+    // digits at index >= Na come out 0 because the bits past the top limb are 0
+    A32[d] = __builtin_bswap32(digits4(a, g.na, k0));
   }
-  for (int d = threadIdx.x; d < g.SB / 4; d += T) {
-    uint32_t w = 0;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int j = 4 * d + e - kPadB;
-      const uint32_t v = (j >= 0 && j < g.Nb) ? digit7(b, g.nb, j) : 0u;
-      w |= v << (8 * e);
-    }
-    B32[d] = w;
-  }
+#pragma unroll 4
+  for (int d = threadIdx.x; d < nB; d += T) B32[d] = digits4(b, g.nb, 4 * d - kPadB);
 }
 
 // y range of phase rho for the band starting at strip w0 (P strips).
