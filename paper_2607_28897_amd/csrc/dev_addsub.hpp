@@ -77,10 +77,13 @@ __device__ __forceinline__ uint32_t wg_addsub(uint32_t* out, int n, FX X, FY Y, 
     const int j0 = base + threadIdx.x * Q;
     const int valid = min(Q, max(0, n - j0));
     uint32_t x[Q], y[Q];
+    // limb indices clamped, values masked: no branch around the loads
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      x[i] = (i < valid) ? X(j0 + i) : 0u;
-      y[i] = (i < valid) ? Y(j0 + i) : 0u;
+      const int jj = min(j0 + i, n - 1);
+      const uint32_t xv = X(jj), yv = Y(jj);
+      x[i] = (i < valid) ? xv : 0u;
+      y[i] = (i < valid) ? yv : 0u;
     }
     LimbRun<Q, SUB> run;
     run.build(x, y, valid);

@@ -113,18 +113,18 @@ __device__ __forceinline__ Lds carve(char* smem, const Geo& g, int P) {
 // [0, 32n) bits), packed low digit first: a 28-bit window of at most two
 // adjacent limbs.
 __device__ __forceinline__ uint32_t digits4(const uint32_t* __restrict__ a, int n, int k0) {
-  if (k0 < 0) {  // only in the zero padding in front of the digits
-    uint32_t w = 0;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) w |= digit7(a, n, k0 + e) << (8 * e);
-    return w;
-  }
-  const int bit = 7 * k0;
+  // branch-free so that the loads of consecutive calls can be batched: the
+  // limb indices are clamped and the values masked instead
+  const int kc = max(k0, 0);
+  const int bit = 7 * kc;
   const int l = bit >> 5, sft = bit & 31;
-  const uint64_t lo = l < n ? a[l] : 0u;
-  const uint64_t hi = l + 1 < n ? a[l + 1] : 0u;
-  const uint32_t v = (uint32_t)((lo | (hi << 32)) >> sft);
-  return (v & 0x7fu) | ((v << 1) & 0x7f00u) | ((v << 2) & 0x7f0000u) | ((v << 3) & 0x7f000000u);
+  const uint32_t lo = a[min(l, n - 1)] & (l < n ? 0xffffffffu : 0u);
+  const uint32_t hi = a[min(l + 1, n - 1)] & (l + 1 < n ? 0xffffffffu : 0u);
+  const uint32_t v = (uint32_t)((((uint64_t)hi << 32) | lo) >> sft);
+  const uint32_t w =
+      (v & 0x7fu) | ((v << 1) & 0x7f00u) | ((v << 2) & 0x7f0000u) | ((v << 3) & 0x7f000000u);
+  // k0 < 0: digits k0..-1 are padding zeros, the window at 0 moves up
+  return k0 >= 0 ? w : (k0 <= -4 ? 0u : w << (8 * -k0));
 }
 
 // Stage the reversed digits of a and the digits of b into LDS (zero padded).
@@ -135,13 +135,13 @@ __device__ __forceinline__ void stage(const Lds& s, const Geo& g, const uint32_t
   uint32_t* A32 = reinterpret_cast<uint32_t*>(s.A);
   uint32_t* B32 = reinterpret_cast<uint32_t*>(s.B);
   const int nA = g.SA / 4, nB = g.SB / 4;
-#pragma unroll 4
+#pragma unroll 8
   for (int d = threadIdx.x; d < nA; d += T) {
     const int k0 = g.QA - 4 * d - 3;
     // digits at index >= Na come out 0 because the bits past the top limb are 0
     A32[d] = __builtin_bswap32(digits4(a, g.na, k0));
   }
-#pragma unroll 4
+#pragma unroll 8
   for (int d = threadIdx.x; d < nB; d += T) B32[d] = digits4(b, g.nb, 4 * d - kPadB);
 }
 
@@ -287,23 +287,26 @@ __device__ __forceinline__ void strip_out(v4i acc, int w, const Lds& s, const Ge
     __builtin_amdgcn_wave_barrier();
     return;
   }
-  // column sums: lane j in [0, 57) gathers the coefficients of limb j
+  // column sums: lane j in [0, 57) gathers the coefficients of limb j (at
+  // most 5 whose low bits start in limb j, at most 5 spilling from limb j-1);
+  // fixed trip counts with masks keep the LDS reads unconditional
   uint64_t X = 0;
-  if (lane <= kStripLimbs) {
-    const int j = lane;
+  {
+    const int j = min(lane, kStripLimbs);
     const int klo = (32 * j + 6) / 7;          // first kappa with floor(7 kappa/32) == j
     const int khi = (32 * (j + 1) + 6) / 7;    // one past the last
-    for (int kk = klo; kk < khi && kk < kStrip; ++kk) {
-      const uint64_t v = (uint64_t)(uint32_t)sc[kk] << (7 * kk - 32 * j);
-      X += v & 0xffffffffull;
+    const int plo = (32 * (j - 1) + 6) / 7;    // first kappa of limb j-1 (j > 0)
+#pragma unroll
+    for (int e = 0; e < 5; ++e) {
+      const int kk = klo + e;
+      const uint64_t v = (uint64_t)(uint32_t)sc[min(kk, kStrip - 1)] << ((7 * kk - 32 * j) & 63);
+      X += (kk < khi && kk < kStrip) ? (v & 0xffffffffull) : 0ull;
+      const int pk = plo + e;
+      const uint64_t u = (uint64_t)(uint32_t)sc[max(min(pk, kStrip - 1), 0)]
+                         << ((7 * pk - 32 * (j - 1)) & 63);
+      X += (j > 0 && pk < klo) ? (u >> 32) : 0ull;
     }
-    if (j > 0) {
-      const int plo = (32 * (j - 1) + 6) / 7;
-      for (int kk = plo; kk < klo; ++kk) {
-        const uint64_t v = (uint64_t)(uint32_t)sc[kk] << (7 * kk - 32 * (j - 1));
-        X += v >> 32;
-      }
-    }
+    if (lane > kStripLimbs) X = 0;
   }
   __builtin_amdgcn_wave_barrier();
   const uint32_t L = (uint32_t)X;

@@ -58,6 +58,19 @@ __global__ __launch_bounds__(1024) void k_addsub(uint32_t* out, uint32_t* cout, 
   if (cout && threadIdx.x == 0) cout[inst] = total;
 }
 
+template <bool SUB>
+__global__ __launch_bounds__(1024) void k_addsub_rounds(uint32_t* out, uint32_t* cout,
+                                                        const uint32_t* a, const uint32_t* b, int n) {
+  __shared__ uint32_t scratch[32];
+  const int64_t inst = blockIdx.x;
+  const uint32_t* pa = a + inst * n;
+  const uint32_t* pb = b + inst * n;
+  auto X = [&](int j) -> uint32_t { return pa[j]; };
+  auto Y = [&](int j) -> uint32_t { return pb[j]; };
+  const uint32_t c = wg_addsub<16, SUB>(out + inst * n, n, X, Y, 0u, scratch);
+  if (cout && threadIdx.x == 0) cout[inst] = c;
+}
+
 template <int Q, bool SUB>
 static int launch_addsub_q(uint32_t* out, uint32_t* cout, const uint32_t* a, const uint32_t* b,
                            int64_t n, int64_t batch, hipStream_t s) {
@@ -81,8 +94,12 @@ static int launch_addsub_t(uint32_t* out, uint32_t* cout, const uint32_t* a, con
   if (n <= 1024) return launch_addsub_q<4, SUB>(out, cout, a, b, n, batch, s);
   if (n <= 2048) return launch_addsub_q<8, SUB>(out, cout, a, b, n, batch, s);
   if (n <= 4096) return launch_addsub_q<16, SUB>(out, cout, a, b, n, batch, s);
-  if (n <= 16384) return launch_addsub_q<32, SUB>(out, cout, a, b, n, batch, s);
-  return launch_addsub_q<64, SUB>(out, cout, a, b, n, batch, s);
+  if (n <= 32768) return launch_addsub_q<32, SUB>(out, cout, a, b, n, batch, s);
+  // beyond 1024 threads x 32 limbs: rounds of the work-group add, carry chained
+  hipLaunchKernelGGL((k_addsub_rounds<SUB>), dim3((unsigned)batch), dim3(1024), 0, s, out, cout, a,
+                     b, (int)n);
+  BI_LAUNCH_CHECK();
+  return BIGINT_OK;
 }
 
 int launch_addsub(bool sub, uint32_t* out, uint32_t* cout, const uint32_t* a, const uint32_t* b,
