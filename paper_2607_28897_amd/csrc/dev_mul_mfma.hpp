@@ -319,12 +319,17 @@ __device__ __forceinline__ void strip_out(v4i acc, int w, const Lds& s, const Ge
   const WaveCarry wc = wave_carry_masks(gb, pb);
   const uint32_t cin = wave_carry_in(wc, 0);
   const uint32_t limb = res + cin;
+  const int jg = kStripLimbs * w + lane;
+  // limbs 2..55 all ones (limbs past the product count as ones): a carry
+  // entering limb 2 then runs through the whole strip
+  const uint64_t tail = ((1ull << kStripLimbs) - 1) & ~3ull;
+  const uint64_t ones = __ballot(jg >= g.nout || limb == 0xffffffffu);
   if (lane < kStripLimbs) {
-    const int jg = kStripLimbs * w + lane;
     if (jg < g.nout) out[jg] = limb;
   } else if (lane == kStripLimbs) {
     const uint32_t cout = (uint32_t)gb | ((uint32_t)pb & cin);
-    s.carry[w] = (uint64_t)limb | ((uint64_t)(H + cout) << 32);
+    s.carry[w] = (uint64_t)limb | ((uint64_t)(H + cout) << 32) |
+                 ((uint64_t)((ones & tail) == tail) << 63);
   }
 }
 
@@ -377,17 +382,46 @@ __device__ __forceinline__ void wg_mul_mfma(uint32_t* out, int32_t* coef, const 
   }
   __syncthreads();
   if (coef == nullptr) {
-    // out += sum_w C_w B^(56(w+1))
-    const uint64_t* C = s.carry;
-    auto X = [&](int j) -> uint32_t { return out[j]; };
-    auto Y = [&](int j) -> uint32_t {
-      if (j < kStripLimbs) return 0u;
-      const int e = j % kStripLimbs;
-      if (e >= 2) return 0u;
-      const uint64_t c = C[j / kStripLimbs - 1];
-      return e ? (uint32_t)(c >> 32) : (uint32_t)c;
-    };
-    wg_addsub<8, false, decltype(X), decltype(Y), true>(out, g.nout, X, Y, 0u, s.misc + 1);
+    // out += sum_w C_w B^(56(w+1)).  Strip w' receives C_{w'-1} (< 2^35) on its
+    // limbs 0 and 1; a carry out of limb 1 runs on only through a tail of
+    // all-ones limbs.  So an exclusive carry scan over strips, one strip per
+    // thread, resolves everything: strip w' generates when limbs 0..1 plus
+    // C_{w'-1} overflow and its tail is all ones, and propagates when limbs
+    // 0..1 plus C_{w'-1} are all ones and so is its tail.
+    const uint64_t kC = (1ull << 63) - 1;
+    uint32_t carry = 0u;
+    for (int base = 0; base < g.W; base += blockDim.x) {
+      const int w = base + threadIdx.x;
+      const bool valid = w < g.W;
+      const int j0 = kStripLimbs * (valid ? w : 0);
+      const uint32_t l0 = (valid && j0 < g.nout) ? out[j0] : 0u;
+      const uint32_t l1 = (valid && j0 + 1 < g.nout) ? out[j0 + 1] : 0u;
+      const uint64_t d = (valid && w > 0) ? (s.carry[w - 1] & kC) : 0ull;
+      const bool ones = valid && (s.carry[w] >> 63);
+      const uint64_t x0 = ((uint64_t)l1 << 32) | l0;
+      const uint64_t x = x0 + d;
+      const bool xh = x < x0;  // carry out of limb 1
+      const bool gen = valid && xh && ones;
+      const bool prop = valid && !xh && x == ~0ull && ones;
+      uint32_t cout;
+      const uint32_t c = wg_carry_scan(gen, prop, carry, s.misc + 1, &cout);
+      carry = cout;
+      if (valid) {
+        const uint64_t y = x + c;
+        const bool yh = xh || (y < x);
+        if (y != x0) {
+          if (j0 < g.nout) out[j0] = (uint32_t)y;
+          if (j0 + 1 < g.nout) out[j0 + 1] = (uint32_t)(y >> 32);
+        }
+        if (yh) {  // ripple into the tail (stops at its first limb that is not all ones)
+          for (int j = j0 + 2; j < min(j0 + kStripLimbs, g.nout); ++j) {
+            const uint32_t v = out[j];
+            out[j] = v + 1u;
+            if (v != 0xffffffffu) break;
+          }
+        }
+      }
+    }
   }
   __syncthreads();
 }

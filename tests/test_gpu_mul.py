@@ -167,3 +167,18 @@ def test_autotune_table_roundtrip(bi, orc, tmp_path):
     p = host(bi.mul(dev(a), dev(b), bi.MUL_MFMA))
     for i in range(3):
         assert np.array_equal(p[i], orc.mul1(a[i], b[i]))
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+@pytest.mark.parametrize("n,m", [(16384, 1), (16384, 3), (4096, 2), (1000, 7), (57, 1), (113, 2)])
+def test_products_with_long_all_ones_runs(bi, orc, algo, n, m):
+    # (B^n - 1) * b = b B^n - b: the low n limbs are B^n - b, all ones above
+    # the lowest limbs, so carries between strips run through whole strips
+    g = np.random.default_rng(n + m)
+    a = np.full((2, n), 0xFFFFFFFF, np.uint32)
+    b = rand_limbs(g, 2, m)
+    b[1, 0] = 1
+    b[1, 1:] = 0
+    p = host(bi.mul(dev(a), dev(b), _algo(bi, algo)))
+    for i in range(2):
+        assert np.array_equal(p[i], orc.mul1(a[i], b[i])), i
