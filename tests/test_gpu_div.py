@@ -106,3 +106,12 @@ def test_shifted_inverse(bi, orc, nv, h):
     for i in range(4):
         want, _ = orc.shinv1(v[i], h)
         assert np.array_equal(w[i], want), i
+
+
+def test_knuth_add_back_inputs(bi, orc):
+    # inputs on which schoolbook division needs its rarest correction step
+    from conftest import from_int
+    from test_oracle_pins import ADD_BACK_CASES
+    for u, v in ADD_BACK_CASES:
+        nu, nv = -(-u.bit_length() // 32), -(-v.bit_length() // 32)
+        _check_batch(bi, orc, from_int(u, nu)[None], from_int(v, nv)[None])

@@ -17,6 +17,21 @@ from conftest import from_int, to_int
 B = 1 << 32
 EDGE = [0, 1, 2, 0x7FFFFFFF, 0x80000000, 0xFFFFFFFE, 0xFFFFFFFF]
 
+ADD_BACK_CASES = [
+    # (u, v) pairs on which Knuth's Algorithm D (64-bit digits) needs the
+    # add-back step (D6): q-hat survives the two-digit test of D3 and is still
+    # one too large.  Found by a plain-Python search of Algorithm D over
+    # structured digits; the expected results come from Python's divmod.
+    (0x7fffffffffffffff000000000000000100000000000000028000000000000001,
+     0x7fffffffffffffff00000000000000017fffffffffffffff),
+    (0x8000000000000000ffffffffffffffff00000000ffffffff7fffffffffffffff8000000000000000,
+     0x10000000000000001ffffffffffffffff),
+    (0x80000000000000007fffffffffffffff00000000000000010000000100000000,
+     0xffffffffffffffff00000000000000008000000000000000),
+    (0xffffffffffffffffffffffffffffffff00000001000000007fffffffffffffff,
+     0x800000000000000080000000000000000000000100000000),
+]
+
 
 def edge_values(n):
     for limbs in itertools.product(EDGE, repeat=n):
@@ -248,6 +263,13 @@ def test_divmod_knuth_add_back_cases(orc):
         if to_int(v) == 0:
             continue
         _check_divmod(orc, u, v)
+
+
+def test_divmod_add_back_step(orc):
+    for u, v in ADD_BACK_CASES:
+        nu, nv = -(-u.bit_length() // 32), -(-v.bit_length() // 32)
+        q, r, st = orc.divmod1(from_int(u, nu), from_int(v, nv))
+        assert st == 0 and (to_int(q), to_int(r)) == divmod(u, v)
 
 
 def test_divmod_special_cases(orc):
