@@ -122,7 +122,7 @@ def main():
     if args.mode == "divmod":
         return divmod_mode(torch, bi, inputs, args)
 
-    cfg = inputs.config3(args.batch)
+    cfg = inputs.pairs_2e19(args.batch)
     a_np, b_np, n = cfg["a"], cfg["b"], cfg["n"]
     a = torch.from_numpy(a_np.view(np.int32)).cuda()
     b = torch.from_numpy(b_np.view(np.int32)).cuda()
@@ -251,7 +251,7 @@ def peak_mode(torch, bi):
 def ragged_mode(torch, bi, inputs, args):
     """4096 products, bit lengths log-uniform in [2^15, 2^19] (seed 1003), one
     persistent launch replayed from a hipGraph; the plain kernel beside it."""
-    c = inputs.config4()
+    c = inputs.ragged_mul_2e15_2e19()
     lens = c["lens"]
     ta = torch.from_numpy(c["a"].view(np.int32)).cuda()
     tb = torch.from_numpy(c["b"].view(np.int32)).cuda()
@@ -280,7 +280,7 @@ def ragged_mode(torch, bi, inputs, args):
 def divmod_mode(torch, bi, inputs, args):
     """512 divisions (dividend log-uniform in [2^16, 2^18] bits, divisor half
     as many limbs), and the same-size products for the Div/Mul ratio."""
-    c = inputs.config5()
+    c = inputs.ragged_div_2e16_2e18()
     nu, nv = c["nu"], c["nv"]
     tu = torch.from_numpy(c["u"].view(np.int32)).cuda()
     tv = torch.from_numpy(c["v"].view(np.int32)).cuda()

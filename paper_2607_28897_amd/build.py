@@ -1,6 +1,6 @@
 """Build the gfx950 shared library ``_lib/libbigint_rocm.so`` with hipcc.
 
-Run ``python -m paper_2607_28897_amd.build`` (or ``__graft_entry__.build()``).
+Run ``python -m paper_2607_28897_amd.build``.
 Every translation unit under ``csrc/`` is compiled for gfx950 only and linked
 into one library exporting the C-ABI declared in ``include/bigint_rocm.h``.
 """

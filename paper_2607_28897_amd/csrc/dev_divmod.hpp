@@ -37,19 +37,30 @@ struct Shared {
 
 // ---- work-group linear operations on global limb arrays ------------------------
 
+// The loops below are unrolled with unconditional loads so that each thread
+// keeps several global loads in flight (one work-group per division cannot
+// hide memory latency with other work-groups).
+
 __device__ __forceinline__ void wg_fill(uint32_t* x, int n, uint32_t v) {
+#pragma unroll 4
   for (int i = threadIdx.x; i < n; i += blockDim.x) x[i] = v;
   __syncthreads();
 }
 
 __device__ __forceinline__ void wg_copy(uint32_t* dst, const uint32_t* src, int n) {
+#pragma unroll 8
   for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
   __syncthreads();
 }
 
 // dst[0..n) = src[s .. s+n) (limbs past ns read as 0); dst must not overlap src
 __device__ __forceinline__ void wg_shr_copy(uint32_t* dst, int n, const uint32_t* src, int ns, int s) {
-  for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = (i + s < ns) ? src[i + s] : 0u;
+#pragma unroll 8
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const int j = i + s;
+    const uint32_t v = ns > 0 ? src[min(j, ns - 1)] : 0u;
+    dst[i] = j < ns ? v : 0u;
+  }
   __syncthreads();
 }
 
@@ -58,8 +69,8 @@ __device__ __forceinline__ int wg_prec(const uint32_t* x, int n, Shared* sh) {
   if (threadIdx.x == 0) sh->red[0] = 0;
   __syncthreads();
   int m = 0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x)
-    if (x[i] != 0u) m = i + 1;
+#pragma unroll 8
+  for (int i = threadIdx.x; i < n; i += blockDim.x) m = x[i] != 0u ? i + 1 : m;
   if (m) atomicMax(&sh->red[0], (uint32_t)m);
   __syncthreads();
   const int r = (int)sh->red[0];
@@ -73,9 +84,11 @@ __device__ __forceinline__ int wg_cmp(const uint32_t* x, int nx, const uint32_t*
   if (threadIdx.x == 0) sh->red[1] = 0;
   __syncthreads();
   int m = 0;
+#pragma unroll 8
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    const uint32_t a = i < nx ? x[i] : 0u, b = i < ny ? y[i] : 0u;
-    if (a != b) m = i + 1;
+    const uint32_t a = nx > 0 ? x[min(i, nx - 1)] : 0u, b = ny > 0 ? y[min(i, ny - 1)] : 0u;
+    const uint32_t av = i < nx ? a : 0u, bv = i < ny ? b : 0u;
+    m = av != bv ? i + 1 : m;
   }
   if (m) atomicMax(&sh->red[1], (uint32_t)m);
   __syncthreads();
@@ -93,9 +106,9 @@ __device__ __forceinline__ int wg_cmp(const uint32_t* x, int nx, const uint32_t*
 template <bool SUB>
 __device__ __forceinline__ uint32_t wg_arith(uint32_t* dst, int n, const uint32_t* x, int nx,
                                              const uint32_t* y, int ny, Shared* sh) {
-  auto X = [&](int j) -> uint32_t { return j < nx ? x[j] : 0u; };
-  auto Y = [&](int j) -> uint32_t { return j < ny ? y[j] : 0u; };
-  const uint32_t c = wg_addsub<4, SUB>(dst, n, X, Y, 0u, sh->scan);
+  auto X = [&](int j) -> uint32_t { return (j < nx) ? x[min(j, nx - 1)] : 0u; };
+  auto Y = [&](int j) -> uint32_t { return (j < ny) ? y[min(j, ny - 1)] : 0u; };
+  const uint32_t c = wg_addsub<16, SUB>(dst, n, X, Y, 0u, sh->scan);
   return c;
 }
 
@@ -103,9 +116,9 @@ __device__ __forceinline__ uint32_t wg_arith(uint32_t* dst, int n, const uint32_
 template <bool SUB>
 __device__ __forceinline__ uint32_t wg_arith1(uint32_t* dst, int n, const uint32_t* x, int nx,
                                               uint32_t small, Shared* sh) {
-  auto X = [&](int j) -> uint32_t { return j < nx ? x[j] : 0u; };
+  auto X = [&](int j) -> uint32_t { return (j < nx) ? x[min(j, nx - 1)] : 0u; };
   auto Y = [&](int j) -> uint32_t { return j == 0 ? small : 0u; };
-  return wg_addsub<4, SUB>(dst, n, X, Y, 0u, sh->scan);
+  return wg_addsub<16, SUB>(dst, n, X, Y, 0u, sh->scan);
 }
 
 // dst[0 .. na+nb) = a * b (MFMA-split multiply; dst must not overlap a, b).
@@ -167,7 +180,7 @@ __device__ inline int fixup(const uint32_t* v, int k1, int c, Bufs& bf, int lw, 
     neg = false;
     auto X = [&](int) -> uint32_t { return 0u; };
     auto Y = [&](int j) -> uint32_t { return j < lp ? bf.T[j] : 0u; };
-    wg_addsub<4, true>(bf.T, min(c, lp), X, Y, 0u, sh->scan);  // in place
+    wg_addsub<16, true>(bf.T, min(c, lp), X, Y, 0u, sh->scan);  // in place
     // limbs [min(c,lp), c) of 0 - P are all ones only if P == 0, which w >= 1 rules out
     wg_shr_copy(bf.E, le, bf.T, min(c, lp), 0);
     if (c > lp) {
@@ -213,7 +226,8 @@ __device__ inline int fixup(const uint32_t* v, int k1, int c, Bufs& bf, int lw, 
   }
   if (adjust) *adjust += adj;
   if (adj >= kMaxAdjust) sh->failed = 1u;
-  return wg_prec(bf.W, lw, sh) > 0 ? wg_prec(bf.W, lw, sh) : 1;
+  const int pw = wg_prec(bf.W, lw, sh);
+  return pw > 0 ? pw : 1;
 }
 
 // w = floor(B^h / v) for a divisor with k1 >= 2 significant limbs and h >= k1.
@@ -280,9 +294,13 @@ __device__ inline int shifted_inverse(const uint32_t* v, int k1, int h, Bufs& bf
         const int s = j + cur - m;
         return s < ly ? bf.T[s] : 0u;
       };
-      wg_addsub<4, false>(bf.U2, lnew, X, Y, 0u, sh->scan);
+      wg_addsub<16, false>(bf.U2, lnew, X, Y, 0u, sh->scan);
     }
-    wg_copy(bf.W, bf.U2, lnew);
+    {  // the new w is in U2: swap the two buffers instead of copying
+      uint32_t* t = bf.W;
+      bf.W = bf.U2;
+      bf.U2 = t;
+    }
     lw = wg_prec(bf.W, lnew, sh);
     cur += m;
     lw = fixup(v, k1, cur, bf, lw, sh, smem, adjust);

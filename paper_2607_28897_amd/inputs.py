@@ -12,8 +12,8 @@ an ``int64`` prefix-offset array of length ``batch + 1`` (instance ``i`` is
 
 The paper's evaluation uses random digits for addition and multiplication
 because their cost depends only on the size (Section 6, datasets paragraph);
-the workloads below follow the five configurations of the build (sizes
-2^15..2^19 bits), each with a fixed seed ``1000 + index``.
+the five workloads below (sizes 2^15..2^19 bits) each draw from a fixed seed
+(1000 .. 1004).
 """
 from __future__ import annotations
 
@@ -90,7 +90,7 @@ def ragged_rows(flat: np.ndarray, off: np.ndarray):
 
 # ---- the five workloads ---------------------------------------------------------
 
-def config1():
+def pairs_2e15():
     """64 pairs of 2^15-bit integers (1024 u32 limbs), uniform; for a - b the
     pair is ordered so that a >= b."""
     g = rng(SEED_BASE + 0)
@@ -100,7 +100,7 @@ def config1():
     return {"a": a, "b": b, "sub_a": sa, "sub_b": sb, "n": 1024}
 
 
-def config2():
+def pairs_2e17_mixed():
     """1024 pairs of 2^17-bit integers (4096 limbs): pairs 0..511 uniform,
     512..1023 carry-adversarial (runs of 0xFFFFFFFF)."""
     g = rng(SEED_BASE + 1)
@@ -114,7 +114,7 @@ def config2():
     return {"a": a, "b": b, "sub_a": sa, "sub_b": sb, "n": n}
 
 
-def config3(batch: int = 256):
+def pairs_2e19(batch: int = 256):
     """256 pairs of 2^19-bit integers (16384 limbs), uniform."""
     g = rng(SEED_BASE + 2)
     n = 16384
@@ -123,7 +123,7 @@ def config3(batch: int = 256):
     return {"a": a, "b": b, "n": n}
 
 
-def config4(batch: int = 4096):
+def ragged_mul_2e15_2e19(batch: int = 4096):
     """4096 multiplications, bit lengths log-uniform in [2^15, 2^19] rounded
     up to 32-bit limbs, one length per pair (both operands), uniform limbs."""
     g = rng(SEED_BASE + 3)
@@ -134,7 +134,7 @@ def config4(batch: int = 4096):
     return {"a": a, "a_off": a_off, "b": b, "b_off": b_off, "lens": lens}
 
 
-def config5(batch: int = 512):
+def ragged_div_2e16_2e18(batch: int = 512):
     """512 divisions: dividend bit length log-uniform in [2^16, 2^18] (limbs
     rounded up), divisor half as many limbs with a nonzero top limb."""
     g = rng(SEED_BASE + 4)

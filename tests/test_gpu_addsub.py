@@ -26,18 +26,18 @@ def _check(bi, orc, a, b):
     assert np.array_equal(host(c), wc)
 
 
-def test_config1(bi, orc):
+def test_pairs_2e15(bi, orc):
     from paper_2607_28897_amd import inputs
-    c = inputs.config1()
+    c = inputs.pairs_2e15()
     _check(bi, orc, c["a"], c["b"])
     out, br = bi.sub(dev(c["sub_a"]), dev(c["sub_b"]))
     want, wb = orc.sub(c["sub_a"], c["sub_b"])
     assert np.array_equal(host(out), want) and not host(br).any()
 
 
-def test_config2_uniform_and_carry_adversarial(bi, orc):
+def test_pairs_2e17_uniform_and_carry_adversarial(bi, orc):
     from paper_2607_28897_amd import inputs
-    c = inputs.config2()
+    c = inputs.pairs_2e17_mixed()
     _check(bi, orc, c["a"], c["b"])
     out, br = bi.sub(dev(c["sub_a"]), dev(c["sub_b"]))
     want, _ = orc.sub(c["sub_a"], c["sub_b"])

@@ -73,10 +73,10 @@ def test_edge_alphabet(bi, orc):
         _check_batch(bi, orc, u, v)
 
 
-def test_config5_sampled(bi, orc):
+def test_ragged_512_divisions_sampled(bi, orc):
     import torch
     from paper_2607_28897_amd import inputs
-    c = inputs.config5()
+    c = inputs.ragged_div_2e16_2e18()
     nu, nv = c["nu"], c["nv"]
     plan = bi.DivPlan(nu, nv)
     q, r, st = plan(dev(c["u"]), torch.from_numpy(c["u_off"]).cuda(), dev(c["v"]),

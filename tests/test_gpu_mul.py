@@ -58,17 +58,17 @@ def test_coefficients_all_ones_bound(bi, orc):
 # ---- full products --------------------------------------------------------------------
 
 @pytest.mark.parametrize("algo", ALGOS)
-def test_config1(bi, orc, algo):
+def test_pairs_2e15(bi, orc, algo):
     from paper_2607_28897_amd import inputs
-    c = inputs.config1()
+    c = inputs.pairs_2e15()
     p = bi.mul(dev(c["a"]), dev(c["b"]), _algo(bi, algo))
     assert np.array_equal(host(p), orc.mul(c["a"], c["b"]))
 
 
 @pytest.mark.parametrize("algo", ALGOS)
-def test_config2_sampled(bi, orc, algo):
+def test_pairs_2e17_sampled(bi, orc, algo):
     from paper_2607_28897_amd import inputs
-    c = inputs.config2()
+    c = inputs.pairs_2e17_mixed()
     p = host(bi.mul(dev(c["a"]), dev(c["b"]), _algo(bi, algo)))
     # every instance is checked against the oracle on a sample of rows, half
     # uniform and half carry-adversarial
@@ -77,9 +77,9 @@ def test_config2_sampled(bi, orc, algo):
 
 
 @pytest.mark.parametrize("algo", ALGOS)
-def test_config3_sampled(bi, orc, algo):
+def test_pairs_2e19_sampled(bi, orc, algo):
     from paper_2607_28897_amd import inputs
-    c = inputs.config3()
+    c = inputs.pairs_2e19()
     p = host(bi.mul(dev(c["a"]), dev(c["b"]), _algo(bi, algo)))
     for i in (0, 1, 77, 128, 200, 255):
         assert np.array_equal(p[i], orc.mul1(c["a"][i], c["b"][i])), i

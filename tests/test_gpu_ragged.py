@@ -48,10 +48,10 @@ def test_small_ragged_mixed_sizes(bi, orc, flags):
         assert np.array_equal(res[oo[i]:oo[i + 1]], want), i
 
 
-def test_config4_sampled_and_replay(bi, orc):
+def test_ragged_4096_sampled_and_replay(bi, orc):
     import torch
     from paper_2607_28897_amd import inputs
-    c = inputs.config4()
+    c = inputs.ragged_mul_2e15_2e19()
     lens = c["lens"]
     plan = bi.MulPlan(lens, lens)
     ta, tao = dev(c["a"]), torch.from_numpy(c["a_off"]).cuda()
