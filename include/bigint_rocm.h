@@ -59,7 +59,7 @@ extern "C" {
 /* multiplication algorithms */
 #define BIGINT_MUL_AUTO 0  /* MFMA-split where supported, else plain        */
 #define BIGINT_MUL_PLAIN 1 /* u64-digit schoolbook convolution               */
-#define BIGINT_MUL_MFMA 2  /* 7-bit digits, int8 MFMA Toeplitz tiles         */
+#define BIGINT_MUL_MFMA 2  /* 7- or 8-bit digits, int8 MFMA Toeplitz tiles   */
 
 /* plan operations */
 #define BIGINT_OP_MUL 1
@@ -71,8 +71,11 @@ extern "C" {
 #define BIGINT_PLAN_NO_GRAPH 2 /* launch directly instead of a hipGraph        */
 
 /* Largest operand (in u32 limbs) the MFMA-split multiply takes: both digit
- * arrays of an instance must fit in one work-group's 160 KiB of LDS. */
-#define BIGINT_MFMA_MAX_LIMBS 16896
+ * arrays of an instance must fit in one work-group's 160 KiB of LDS.  With
+ * 8-bit digits that holds up to 18,460 limbs; a configuration forced to
+ * 7-bit digits fits up to 16,397 limbs (8 waves) or 16,831 (4 waves) and
+ * beyond that returns BIGINT_EUNSUPPORTED. */
+#define BIGINT_MFMA_MAX_LIMBS 18432
 
 typedef struct bigint_plan_s* bigint_plan_t;
 
@@ -109,10 +112,14 @@ int bigint_sub(uint32_t* out, uint32_t* borrow_out, const uint32_t* a,
  *     outputs and their balancing partners (threadConv/halfConv), partial
  *     sums kept as (low, high, carry) triples and resolved by one carry scan
  *     (bmulReg: convolution, then baddReg of the low and shifted high parts);
- *   BIGINT_MUL_MFMA: on 7-bit digits as a sum of Toeplitz-times-Hankel
- *     int8 MFMA tiles with int32 accumulation (exact: every coefficient is at
- *     most min(Na,Nb)*127^2 < 2^31), recombined in 64-bit columns and
- *     resolved by the same carry scan.
+ *   BIGINT_MUL_MFMA: on small digits as a sum of Toeplitz-times-Hankel
+ *     int8 MFMA tiles with int32 accumulation, recombined in 64-bit columns
+ *     and resolved by the same carry scan.  The digit width is a tuned
+ *     parameter: 7-bit digits (exact: every coefficient is at most
+ *     min(Na,Nb)*127^2 < 2^31) or 8-bit digits fed as alpha - 128 (signed
+ *     int8; every MFMA sum is at most min(Na,Nb)*2^14 < 2^31) with the
+ *     offset terms 128 (window sums of the digits) + 2^14 (pair counts)
+ *     added per coefficient in 64-bit arithmetic.  Both give the same bytes.
  * a: batch*na limbs, b: batch*nb limbs, out: batch*(na+nb) limbs.
  * na, nb >= 1.  MFMA needs na, nb <= BIGINT_MFMA_MAX_LIMBS (else
  * BIGINT_EUNSUPPORTED); PLAIN needs na+nb <= 32768; AUTO picks MFMA when it
@@ -205,10 +212,11 @@ int bigint_shinv(uint32_t* w, const uint32_t* v, int64_t nv, int64_t h,
 int bigint_diag_mfma_rate(int32_t* scratch, int64_t blocks, int64_t iters, void* stream);
 
 /* Tile parameters of the MFMA multiply used by the next calls on this thread
- * (strips per wave band: 4, 8 or 16; waves per work-group: 4 or 8); 0 keeps
- * the default.  Exists so tests can check that every configuration gives the
- * same bytes. */
-int bigint_set_mfma_config(int strips_per_band, int waves);
+ * (strips per wave band: 4, 8 or 16; waves per work-group: 4 or 8; digit
+ * width: 7 or 8 bits); 0 keeps the tuned default.  Plans read the tuned
+ * table only.  Exists so tests can check that every configuration gives the
+ * same bytes; other values return BIGINT_EINVAL. */
+int bigint_set_mfma_config(int strips_per_band, int waves, int digit_bits);
 
 #ifdef __cplusplus
 }

@@ -32,7 +32,7 @@ DIV_OK, DIVZERO = 0, 1
 MUL_AUTO, MUL_PLAIN, MUL_MFMA = 0, 1, 2
 OP_MUL, OP_DIVMOD = 1, 2
 PLAN_DEFAULT, PLAN_PLAIN, PLAN_NO_GRAPH = 0, 1, 2
-MFMA_MAX_LIMBS = 16896
+MFMA_MAX_LIMBS = 18432
 
 
 class BigIntError(RuntimeError):
@@ -81,7 +81,7 @@ def lib() -> ctypes.CDLL:
             "bigint_digits7": ([_vp, _vp, _i64, _i64, _i64, _vp], _int),
             "bigint_conv7": ([_vp, _vp, _i64, _vp, _i64, _i64, _vp], _int),
             "bigint_shinv": ([_vp, _vp, _i64, _i64, _i64, _vp], _int),
-            "bigint_set_mfma_config": ([_int, _int], _int),
+            "bigint_set_mfma_config": ([_int, _int, _int], _int),
             "bigint_diag_mfma_rate": ([_vp, _i64, _i64, _vp], _int),
         }
         for name, (args, res) in sig.items():
@@ -212,8 +212,8 @@ def shinv(v, h: int):
     return w
 
 
-def set_mfma_config(strips_per_band: int = 0, waves: int = 0):
-    _check(lib().bigint_set_mfma_config(strips_per_band, waves), "bigint_set_mfma_config")
+def set_mfma_config(strips_per_band: int = 0, waves: int = 0, digit_bits: int = 0):
+    _check(lib().bigint_set_mfma_config(strips_per_band, waves, digit_bits), "bigint_set_mfma_config")
 
 
 def autotune(cache_path: str | None = None, flags: int = 0):

@@ -14,31 +14,43 @@ namespace bi {
 static thread_local int t_last_hip = 0;
 void set_hip_error(hipError_t e) { t_last_hip = (int)e; }
 
-static thread_local int t_cfg_P = 0, t_cfg_waves = 0;
+static thread_local int t_cfg_P = 0, t_cfg_waves = 0, t_cfg_dw = 0;
 
 // Tile choice per size bin.  The built-in table is what bigint_autotune
 // picked on an MI355X; a table loaded with bigint_autotune_load (or produced
 // by bigint_autotune) replaces it.
 struct TuneEntry {
   int max_limbs;  // bin upper bound (operand limbs)
-  int P, waves;
+  int P, waves, dw;
 };
 static std::mutex g_tune_mu;
 static std::vector<TuneEntry> g_tune = {
-    {1448, 4, 4}, {2896, 8, 8}, {5792, 8, 8}, {11585, 16, 8}, {BIGINT_MFMA_MAX_LIMBS, 16, 8}};
+    {1448, 4, 4, 8}, {2896, 8, 4, 8}, {5792, 8, 8, 8}, {11585, 8, 8, 8},
+    {BIGINT_MFMA_MAX_LIMBS, 16, 8, 8}};
 
+// The tuned configuration for this size; when its LDS does not fit (7-bit
+// digits near the top of the range) the same tiles with 8-bit digits, which
+// need 8/7 fewer bytes per operand.
 MfmaCfg default_mfma_cfg(int na, int nb) {
   const int n = std::max(na, nb);
-  std::lock_guard<std::mutex> lk(g_tune_mu);
-  for (const auto& e : g_tune)
-    if (n <= e.max_limbs) return MfmaCfg{e.P, e.waves};
-  return MfmaCfg{16, 8};
+  MfmaCfg c{16, 8, 8};
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const auto& e : g_tune)
+      if (n <= e.max_limbs) {
+        c = MfmaCfg{e.P, e.waves, e.dw};
+        break;
+      }
+  }
+  if (c.dw == 7 && mfma_lds(na, nb, c) > 163840) c.dw = 8;
+  return c;
 }
 
 MfmaCfg current_mfma_cfg(int na, int nb) {
   MfmaCfg c = default_mfma_cfg(na, nb);
   if (t_cfg_P) c.P = t_cfg_P;
   if (t_cfg_waves) c.waves = t_cfg_waves;
+  if (t_cfg_dw) c.dw = t_cfg_dw;
   return c;
 }
 
@@ -84,13 +96,15 @@ const char* bigint_strerror(int code) {
 
 int bigint_last_hip_error(void) { return t_last_hip; }
 
-int bigint_set_mfma_config(int strips_per_band, int waves) {
+int bigint_set_mfma_config(int strips_per_band, int waves, int digit_bits) {
   if (strips_per_band != 0 && strips_per_band != 4 && strips_per_band != 8 &&
       strips_per_band != 16)
     return BIGINT_EINVAL;
   if (waves != 0 && waves != 4 && waves != 8) return BIGINT_EINVAL;
+  if (digit_bits != 0 && digit_bits != 7 && digit_bits != 8) return BIGINT_EINVAL;
   t_cfg_P = strips_per_band;
   t_cfg_waves = waves;
+  t_cfg_dw = digit_bits;
   return BIGINT_OK;
 }
 
@@ -162,7 +176,8 @@ int bigint_digits7(uint8_t* out, const uint32_t* a, int64_t n, int64_t D, int64_
 int bigint_conv7(int32_t* c, const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb,
                  int64_t batch, void* stream) {
   if (!c || !a || !b || na <= 0 || nb <= 0 || batch < 0) return BIGINT_EINVAL;
-  const MfmaCfg cfg = current_mfma_cfg((int)na, (int)nb);
+  MfmaCfg cfg = current_mfma_cfg((int)na, (int)nb);
+  cfg.dw = 7;  // the raw coefficients are those of the 7-bit digits
   if (!mfma_fits(na, nb, cfg) || batch > 0x7fffffff) return BIGINT_EUNSUPPORTED;
   const int64_t K = (32 * na + 6) / 7 + (32 * nb + 6) / 7 - 1;
   const size_t cb = (size_t)K * batch * 4;
@@ -226,7 +241,7 @@ static int plan_build_mul(bigint_plan_s* p) {
     } else {
       MfmaCfg c = default_mfma_cfg((int)p->la[i], (int)p->lb[i]);
       c.waves = p->waves;
-      q[t].cfg = c.P == 4 ? 0 : (c.P == 8 ? 1 : 2);
+      q[t].cfg = ragged_cfg_id(c);
       lds = std::max(lds, mfma_lds((int)p->la[i], (int)p->lb[i], c));
     }
   }
@@ -265,7 +280,8 @@ static int plan_build_div(bigint_plan_s* p) {
   std::stable_sort(idx.begin(), idx.end(), [&](int64_t x, int64_t y) { return cost(x) > cost(y); });
   std::vector<int32_t> q(B);
   for (int64_t t = 0; t < B; ++t) q[t] = (int32_t)idx[t];
-  p->grid = (int)std::max<int64_t>(1, std::min<int64_t>(B, num_cus()));
+  p->grid = (int)std::max<int64_t>(
+      1, std::min<int64_t>(B, (int64_t)num_cus() * div_groups_per_cu(p->cap_u, p->cap_v)));
   if (B > 0) {
     BI_HIP(hipMalloc(&p->d_queue, sizeof(int32_t) * B));
     BI_HIP(hipMemcpy(p->d_queue, q.data(), sizeof(int32_t) * B, hipMemcpyHostToDevice));
@@ -376,7 +392,8 @@ static int divmod_launch_alloc(uint32_t* q, uint32_t* r, int32_t* status, const 
                                hipStream_t s) {
   const int cap_u = h_inv >= 0 ? h_inv + 2 : (int)nu;
   const int cap_v = (int)nv;
-  const int grid = (int)std::min<int64_t>(batch, num_cus());
+  const int grid =
+      (int)std::min<int64_t>(batch, (int64_t)num_cus() * div_groups_per_cu(cap_u, cap_v));
   const size_t bytes = div_ws_bytes(cap_u, cap_v, grid);
   void* ws = nullptr;
   hipError_t e = hipMallocAsync(&ws, bytes, s);
@@ -446,14 +463,16 @@ int bigint_diag_mfma_rate(int32_t* scratch, int64_t blocks, int64_t iters, void*
 
 // ---- autotuning ------------------------------------------------------------------
 // For each size bin, every tile configuration (strips per band P, waves per
-// work-group) multiplies the same random batch; the fastest is kept.  All
-// candidates must give identical bytes (checked on the first instance).
+// work-group, digit width) multiplies the same random batch; the fastest is
+// kept.  All candidates must give identical bytes (checked on the first
+// instance).
 
 int bigint_autotune(const char* cache_path, int flags) {
   (void)flags;
   static const int kBins[] = {1024, 2048, 4096, 8192, 16384};
   static const int kP[] = {4, 8, 16};
   static const int kW[] = {4, 8};
+  static const int kD[] = {7, 8};
   std::vector<TuneEntry> table;
   hipStream_t s = nullptr;
   BI_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
@@ -488,11 +507,12 @@ int bigint_autotune(const char* cache_path, int flags) {
         rc = BIGINT_EHIP;
     }
     float best = 1e30f;
-    TuneEntry pick{n, 16, 8};
+    TuneEntry pick{n, 16, 8, 7};
+    for (int D : kD)
     for (int P : kP)
       for (int W : kW) {
         if (rc != BIGINT_OK) break;
-        const MfmaCfg cfg{P, W};
+        const MfmaCfg cfg{P, W, D};
         if (mfma_lds(n, n, cfg) > 163840) continue;
         rc = launch_mul_mfma(out, nullptr, a, n, b, n, nb, cfg, s);  // warm-up
         if (rc != BIGINT_OK) break;
@@ -512,7 +532,7 @@ int bigint_autotune(const char* cache_path, int flags) {
         }
         if (first.empty()) first = cur;
         else if (first != cur) { rc = BIGINT_EHIP; set_hip_error(hipErrorUnknown); break; }
-        if (ms < best) { best = ms; pick = TuneEntry{n, P, W}; }
+        if (ms < best) { best = ms; pick = TuneEntry{n, P, W, D}; }
       }
     if (a) (void)hipFree(a);
     if (b) (void)hipFree(b);
@@ -540,8 +560,8 @@ int bigint_autotune(const char* cache_path, int flags) {
     const bool have = hipGetDeviceProperties(&prop, dev) == hipSuccess;
     fprintf(f, "{\"arch\": \"%s\", \"op\": \"mul_mfma\", \"bins\": [", have ? prop.gcnArchName : "?");
     for (size_t i = 0; i < table.size(); ++i)
-      fprintf(f, "%s{\"max_limbs\": %d, \"strips_per_band\": %d, \"waves\": %d}", i ? ", " : "",
-              table[i].max_limbs, table[i].P, table[i].waves);
+      fprintf(f, "%s{\"max_limbs\": %d, \"strips_per_band\": %d, \"waves\": %d, \"digit_bits\": %d}",
+              i ? ", " : "", table[i].max_limbs, table[i].P, table[i].waves, table[i].dw);
     fprintf(f, "]}\n");
     fclose(f);
   }
@@ -572,8 +592,11 @@ int bigint_autotune_load(const char* cache_path) {
   for (;;) {
     TuneEntry e;
     if (!field("\"max_limbs\"", &e.max_limbs)) break;
-    if (!field("\"strips_per_band\"", &e.P) || !field("\"waves\"", &e.waves)) return BIGINT_EINVAL;
-    if ((e.P != 4 && e.P != 8 && e.P != 16) || (e.waves != 4 && e.waves != 8) || e.max_limbs <= 0)
+    if (!field("\"strips_per_band\"", &e.P) || !field("\"waves\"", &e.waves) ||
+        !field("\"digit_bits\"", &e.dw))
+      return BIGINT_EINVAL;
+    if ((e.P != 4 && e.P != 8 && e.P != 16) || (e.waves != 4 && e.waves != 8) ||
+        (e.dw != 7 && e.dw != 8) || e.max_limbs <= 0)
       return BIGINT_EINVAL;
     table.push_back(e);
   }

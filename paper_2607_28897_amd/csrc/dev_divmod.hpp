@@ -24,7 +24,8 @@
 namespace bi {
 namespace div {
 
-constexpr int kP = 16;  // strips per band of the multiplications
+constexpr int kP = 8;   // strips per band of the multiplications
+constexpr int kDW = 8;  // digit width of the multiplications
 constexpr int kMaxAdjust = 64;  // cap on fix-up rounds per scale
 
 // LDS words used by the division itself (besides the multiply's area)
@@ -126,7 +127,7 @@ __device__ __forceinline__ uint32_t wg_arith1(uint32_t* dst, int n, const uint32
 // kernel's code stays small enough for the instruction cache.
 __device__ __noinline__ void wg_mul(uint32_t* dst, const uint32_t* a, int na, const uint32_t* b,
                                        int nb, char* smem) {
-  mfma::wg_mul_mfma<kP>(dst, nullptr, a, na, b, nb, smem);
+  mfma::wg_mul_mfma<kDW, kP>(dst, nullptr, a, na, b, nb, smem);
 }
 
 // ---- one-lane helpers for the starting value ------------------------------------

@@ -1,5 +1,6 @@
-// dev_mul_mfma.hpp -- the MFMA-split multiply: 7-bit digits, int8 MFMA
-// Toeplitz tiles, int32 accumulation, 64-bit recombination and a carry scan.
+// dev_mul_mfma.hpp -- the MFMA-split multiply: 7-bit (or offset 8-bit)
+// digits, int8 MFMA Toeplitz tiles, int32 accumulation, 64-bit recombination
+// and a carry scan.
 //
 // What is computed is the quadratic formula of Section 5.2,
 // c_k = sum_{i+j=k} alpha_i beta_j, over the 7-bit digits alpha, beta of the
@@ -38,6 +39,21 @@
 // limb) with a one-bit ballot carry scan, writes the 56 limbs and keeps the
 // 57th column (with its carry) as the strip's carry word C_w.  A final
 // work-group carry scan adds every C_w at limb 56(w+1).
+//
+// Offset 8-bit digits (DW = 8).  The digits are the bytes of the limbs
+// (Na = 4 na), fed to the MFMA as alpha'_i = alpha_i - 128 in [-128, 127]
+// (the byte with its top bit flipped, read as signed), zero outside [0, Na).
+// Then c_k = c'_k + 128 S_k + 2^14 cnt_k with c'_k = sum alpha'_i beta'_j
+// from the MFMA (|alpha' beta'| <= 2^14, so int32 is exact up to 131,071
+// digits), cnt_k = the number of pairs (i, k - i) inside both operands and
+// S_k = sum over those pairs of alpha'_i + beta'_{k-i}.  With PA / PB the
+// prefix sums of alpha' / beta', S_k = PA(k+1) - PA(k+1-Nb) + PB(k+1) -
+// PB(k+1-Na); from one k to the next it changes by alpha'_k - alpha'_{k-Nb}
+// + beta'_k - beta'_{k-Na}, four digits of 4-digit groups that are limbs.
+// A strip (256 coefficients = 64 limbs) takes S at its start from per-block
+// (256 digit) prefix sums plus a partial block, and the rest by a wave scan
+// of those differences.  The strip's limb j then takes X_j = sum_t c_{4j+t}
+// 2^(8t) < 2^58, and the spill of limb 63 is the strip's carry word.
 #pragma once
 
 #include "common.hpp"
@@ -50,9 +66,16 @@ constexpr int kPadA = 320;  // zero bytes on both sides of reversed alpha (>= 30
 constexpr int kPadB = 64;   // zero bytes before beta (a tile reads from Y >= -64)
 constexpr int kPadBt = 96;  // zero bytes after beta (reads reach Y + 80)
 constexpr int kStrip = 256; // coefficients per strip
-constexpr int kStripLimbs = 56;
 
+// limbs per strip of 256 coefficients: 7 * 256 / 32 and 8 * 256 / 32
+template <int DW>
+__host__ __device__ constexpr int strip_limbs() { return 8 * DW; }
+
+// 7-bit digits of an n-limb integer
 __host__ __device__ inline int ndigits(int n) { return (32 * n + 6) / 7; }
+
+template <int DW>
+__host__ __device__ inline int ndigits_w(int n) { return DW == 8 ? 4 * n : ndigits(n); }
 
 struct Geo {
   int na, nb, Na, Nb;
@@ -61,12 +84,16 @@ struct Geo {
   int SB;   // bytes of Bbuf; Bbuf[kPadB + j] = beta[j]
   int W;    // strips
   int nout; // na + nb
+  int NBa, NBb;  // 8-bit digits: 256-digit blocks of each operand
 };
 
+template <int DW>
 __host__ __device__ inline Geo make_geo(int na, int nb) {
   Geo g;
   g.na = na; g.nb = nb;
-  g.Na = ndigits(na); g.Nb = ndigits(nb);
+  g.Na = ndigits_w<DW>(na); g.Nb = ndigits_w<DW>(nb);
+  g.NBa = (g.Na + kStrip - 1) / kStrip;
+  g.NBb = (g.Nb + kStrip - 1) / kStrip;
   g.QA = ((g.Na - 1 + kPadA) + 15) & ~15;
   g.SA = ((g.QA + kPadA + 1) + 15) & ~15;
   g.SB = ((kPadB + g.Nb + kPadBt) + 15) & ~15;
@@ -76,13 +103,17 @@ __host__ __device__ inline Geo make_geo(int na, int nb) {
   return g;
 }
 
+// block prefix sums (8-bit digits): NBa + 1 and NBb + 1 ints
+__host__ __device__ inline int bs_bytes(const Geo& g) { return (4 * (g.NBa + g.NBb + 2) + 15) & ~15; }
+
 // LDS layout: [Abuf SA][Bbuf SB][per-wave scratch 1 KiB each][strip carries
-// 8W][band order 2*NB][misc 128]
+// 8W][band order 2*NB][misc 128][block prefix sums (8-bit digits)]
+template <int DW>
 __host__ __device__ inline size_t lds_bytes(int na, int nb, int nwaves, int P) {
-  const Geo g = make_geo(na, nb);
+  const Geo g = make_geo<DW>(na, nb);
   const int NB = (g.W + P - 1) / P;
   return (size_t)g.SA + g.SB + (size_t)nwaves * 1024 + (size_t)8 * g.W +
-         (size_t)((2 * NB + 15) & ~15) + 128;
+         (size_t)((2 * NB + 15) & ~15) + 128 + (DW == 8 ? bs_bytes(g) : 0);
 }
 
 struct Lds {
@@ -93,6 +124,8 @@ struct Lds {
   uint64_t* carry;   // W words
   uint16_t* order;   // NB entries
   uint32_t* misc;    // [0] band counter, [1..16] scan scratch (32 words)
+  int32_t* bsa;      // 8-bit digits: bsa[b] = sum of alpha'_i, i < 256 b (b <= NBa)
+  int32_t* bsb;      // the same for beta' (b <= NBb)
 };
 
 __device__ __forceinline__ Lds carve(char* smem, const Geo& g, int P) {
@@ -105,7 +138,9 @@ __device__ __forceinline__ Lds carve(char* smem, const Geo& g, int P) {
   s.wscr = s.scr + wave_id() * 256; p += num_waves() * 1024;
   s.carry = reinterpret_cast<uint64_t*>(p); p += 8 * g.W;
   s.order = reinterpret_cast<uint16_t*>(p); p += (2 * NB + 15) & ~15;
-  s.misc = reinterpret_cast<uint32_t*>(p);
+  s.misc = reinterpret_cast<uint32_t*>(p); p += 128;
+  s.bsa = reinterpret_cast<int32_t*>(p);
+  s.bsb = s.bsa + g.NBa + 1;
   return s;
 }
 
@@ -127,22 +162,149 @@ __device__ __forceinline__ uint32_t digits4(const uint32_t* __restrict__ a, int 
   return k0 >= 0 ? w : (k0 <= -4 ? 0u : w << (8 * -k0));
 }
 
+// Limb m of an n-limb operand as four offset 8-bit digits (bytes with the
+// top bit flipped: alpha' = alpha - 128 read as signed); 0 outside [0, n).
+__device__ __forceinline__ uint32_t limb8(const uint32_t* __restrict__ a, int n, int m) {
+  // a mask rather than a select, so that the load stays unconditional and
+  // the loads of an unrolled loop issue together
+  const uint32_t mask = (m >= 0 && m < n) ? 0xffffffffu : 0u;
+  return (a[min(max(m, 0), n - 1)] ^ 0x80808080u) & mask;
+}
+
 // Stage the reversed digits of a and the digits of b into LDS (zero padded).
 // Abuf[q] = alpha[QA - q]: dword d holds digits QA-4d-3 .. QA-4d, byte-reversed.
+template <int DW>
 __device__ __forceinline__ void stage(const Lds& s, const Geo& g, const uint32_t* __restrict__ a,
                                       const uint32_t* __restrict__ b) {
   const int T = blockDim.x;
   uint32_t* A32 = reinterpret_cast<uint32_t*>(s.A);
   uint32_t* B32 = reinterpret_cast<uint32_t*>(s.B);
   const int nA = g.SA / 4, nB = g.SB / 4;
+  if constexpr (DW == 8) {
+    // digits QA-4d-3 .. QA-4d: bytes 1..3 of limb l and byte 0 of limb l+1
+    // (QA = 0 mod 16, so QA-4d-4 = 4l)
 #pragma unroll 8
-  for (int d = threadIdx.x; d < nA; d += T) {
-    const int k0 = g.QA - 4 * d - 3;
-    // digits at index >= Na come out 0 because the bits past the top limb are 0
-    A32[d] = __builtin_bswap32(digits4(a, g.na, k0));
+    for (int d = threadIdx.x; d < nA; d += T) {
+      const int l = (g.QA - 4 * d - 4) >> 2;
+      const uint32_t v = __builtin_amdgcn_alignbyte(limb8(a, g.na, l + 1), limb8(a, g.na, l), 1);
+      A32[d] = __builtin_bswap32(v);
+    }
+#pragma unroll 8
+    for (int d = threadIdx.x; d < nB; d += T) B32[d] = limb8(b, g.nb, d - kPadB / 4);
+  } else {
+#pragma unroll 8
+    for (int d = threadIdx.x; d < nA; d += T) {
+      const int k0 = g.QA - 4 * d - 3;
+      // digits at index >= Na come out 0 because the bits past the top limb are 0
+      A32[d] = __builtin_bswap32(digits4(a, g.na, k0));
+    }
+#pragma unroll 8
+    for (int d = threadIdx.x; d < nB; d += T) B32[d] = digits4(b, g.nb, 4 * d - kPadB);
   }
-#pragma unroll 8
-  for (int d = threadIdx.x; d < nB; d += T) B32[d] = digits4(b, g.nb, 4 * d - kPadB);
+}
+
+// ---- 8-bit digits: sums of alpha' and beta' ---------------------------------------
+
+// sum of the four signed digits of an offset group (0 for a zero group)
+__device__ __forceinline__ int group_sum(uint32_t x) {
+  return (int)__builtin_amdgcn_sad_u8(x ^ 0x80808080u, 0u, 0u) - 512;
+}
+
+// digits 4m .. 4m+3 of alpha' from the reversed buffer (byte t = digit
+// 4m+3-t); 0 outside [0, na)
+__device__ __forceinline__ uint32_t groupA(const uint8_t* Abuf, const Geo& g, int m) {
+  const int mc = min(max(m, 0), g.na - 1);
+  const uint32_t* p = reinterpret_cast<const uint32_t*>(Abuf + (g.QA - 4 * mc - 4));
+  const uint32_t v = __builtin_amdgcn_alignbyte(p[1], p[0], 1);
+  return v & ((m >= 0 && m < g.na) ? 0xffffffffu : 0u);
+}
+
+// digits 4m .. 4m+3 of beta' (byte t = digit 4m+t); 0 outside [0, nb)
+__device__ __forceinline__ uint32_t groupB(const uint8_t* Bbuf, const Geo& g, int m) {
+  const int mc = min(max(m, 0), g.nb - 1);
+  const uint32_t v = reinterpret_cast<const uint32_t*>(Bbuf + kPadB)[mc];
+  return v & ((m >= 0 && m < g.nb) ? 0xffffffffu : 0u);
+}
+
+// inclusive prefix sum over the 64 lanes with DPP: shifts of 1, 2, 4, 8
+// inside each row of 16 lanes, then the row totals broadcast to the rows
+// above (row_bcast:15 into rows 1 and 3, row_bcast:31 into rows 2 and 3)
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp_add(int x) {
+  return x + __builtin_amdgcn_update_dpp(0, x, CTRL, ROWS, 0xf, false);
+}
+
+__device__ __forceinline__ int wave_incl_scan(int x) {
+  x = dpp_add<0x111, 0xf>(x);  // row_shr:1
+  x = dpp_add<0x112, 0xf>(x);  // row_shr:2
+  x = dpp_add<0x114, 0xf>(x);  // row_shr:4
+  x = dpp_add<0x118, 0xf>(x);  // row_shr:8
+  x = dpp_add<0x142, 0xa>(x);  // row_bcast:15
+  x = dpp_add<0x143, 0xc>(x);  // row_bcast:31
+  return x;
+}
+
+__device__ __forceinline__ int wave_sum(int x) {
+  return __builtin_amdgcn_readlane(wave_incl_scan(x), 63);
+}
+
+// bsa[b] = sum of alpha'_i over i < 256 b for b = 0..NBa (bsa[NBa] is the
+// whole sum); likewise bsb.  Reads the staged buffers; the caller
+// synchronises before and after.
+__device__ __forceinline__ void block_sums(const Lds& s, const Geo& g) {
+  // a row of 16 lanes per block, four consecutive groups per lane (no LDS
+  // bank conflicts); the row total by DPP shifts inside the row
+  const int nblk = g.NBa + g.NBb;
+  const int lane = lane_id(), row = lane >> 4, col = lane & 15;
+  for (int t0 = 4 * wave_id(); t0 < nblk; t0 += 4 * num_waves()) {
+    const int t = t0 + row;
+    const bool isA = t < g.NBa;
+    const int blk = isA ? t : t - g.NBa;
+    const int m = 64 * blk + 4 * col;
+    int v = 0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) v += group_sum(isA ? groupA(s.A, g, m + e) : groupB(s.B, g, m + e));
+    v = dpp_add<0x111, 0xf>(v);  // row_shr:1
+    v = dpp_add<0x112, 0xf>(v);  // row_shr:2
+    v = dpp_add<0x114, 0xf>(v);  // row_shr:4
+    v = dpp_add<0x118, 0xf>(v);  // row_shr:8
+    if (col == 15 && t < nblk) (isA ? s.bsa : s.bsb)[blk + 1] = v;
+  }
+}
+
+// exclusive prefix over the block totals (wave 0: alpha', wave 1 or 0: beta')
+__device__ __forceinline__ void block_prefix(const Lds& s, const Geo& g) {
+  const int wid = wave_id();
+  for (int op = 0; op < 2; ++op) {
+    if (wid != (num_waves() > 1 ? op : 0)) continue;
+    int32_t* bs = op == 0 ? s.bsa : s.bsb;
+    const int nb = op == 0 ? g.NBa : g.NBb;
+    int carry = 0;
+    for (int base = 0; base < nb; base += 64) {
+      const int b = base + lane_id();
+      const int v = b < nb ? bs[b + 1] : 0;
+      const int inc = wave_incl_scan(v) + carry;
+      if (b < nb) bs[b + 1] = inc;
+      carry = __builtin_amdgcn_readlane(inc, 63);
+    }
+    if (lane_id() == 0) bs[0] = 0;
+  }
+}
+
+// prefix sum of alpha' (or beta') over digits [0, 4 gx) = a block prefix
+// (the whole blocks below gx, returned in .base, the same in every lane)
+// plus this lane's group of the partial block when it lies below gx (.part;
+// the wave-wide sum of .part completes it).
+struct Prefix { int base, part; };
+
+__device__ __forceinline__ Prefix prefix_groups(const Lds& s, const Geo& g, bool isA, int gx) {
+  const int n = isA ? g.na : g.nb;
+  const int32_t* bs = isA ? s.bsa : s.bsb;
+  const int gc = min(max(gx, 0), n);
+  const int blk = gc >> 6;
+  const int m = 64 * blk + lane_id();
+  const uint32_t x = m < gc ? (isA ? groupA(s.A, g, m) : groupB(s.B, g, m)) : 0u;
+  return Prefix{bs[blk], group_sum(x)};
 }
 
 // y range of phase rho for the band starting at strip w0 (P strips).
@@ -267,8 +429,9 @@ __device__ __forceinline__ void band_phase(v4i (&acc)[P], const Lds& s, const Ge
 
 // Per strip: turn the 256 coefficients of acc (strip w) into 56 limbs of out
 // and the strip carry word; or, for the diagnostic path, store them raw.
-__device__ __forceinline__ void strip_out(v4i acc, int w, const Lds& s, const Geo& g,
-                                          uint32_t* out, int32_t* coef) {
+__device__ __forceinline__ void strip_out7(v4i acc, int w, const Lds& s, const Geo& g,
+                                           uint32_t* out, int32_t* coef) {
+  constexpr int kStripLimbs = strip_limbs<7>();
   const int lane = lane_id();
   int32_t* sc = s.wscr;
   // lane l holds column p = l & 15, rows 4(l>>4)+v: coefficient 16 row + p
@@ -311,8 +474,9 @@ __device__ __forceinline__ void strip_out(v4i acc, int w, const Lds& s, const Ge
   __builtin_amdgcn_wave_barrier();
   const uint32_t L = (uint32_t)X;
   const uint32_t H = (uint32_t)(X >> 32);
-  const uint32_t Hprev = __shfl_up(H, 1, 64);
-  const uint64_t sum = (uint64_t)L + (lane > 0 ? Hprev : 0u);
+  // H of the lane below, 0 into lane 0 (DPP wave_shr:1)
+  const uint32_t Hprev = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)H, 0x138, 0xf, 0xf, false);
+  const uint64_t sum = (uint64_t)L + Hprev;
   const uint32_t res = (uint32_t)sum;
   const bool gb = (sum >> 32) != 0;
   const bool pb = (lane <= kStripLimbs) && res == 0xffffffffu;
@@ -333,7 +497,93 @@ __device__ __forceinline__ void strip_out(v4i acc, int w, const Lds& s, const Ge
   }
 }
 
-template <int P>
+// The same for offset 8-bit digits: the strip's 64 limbs and its carry word.
+__device__ __forceinline__ void strip_out8(v4i acc, int w, const Lds& s, const Geo& g,
+                                           uint32_t* out) {
+  const int lane = lane_id();
+  int32_t* sc = s.wscr;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) sc[16 * (4 * (lane >> 4) + v) + (lane & 15)] = acc[v];
+  const int g0 = 64 * w;         // the strip's first limb (4-digit group)
+  const int m1 = g0 + lane;      // this lane's limb; its digits k = 4 m1 + t
+  // S at the strip start, S_{256w-1} = PA(256w) - PA(256w-Nb) + PB(256w) -
+  // PB(256w-Na): block prefixes, plus a partial block where a boundary is not
+  // block-aligned (the tests are wave-uniform)
+  int S0 = 0, part = 0;
+  bool partial = false;
+  auto pre = [&](bool isA, int gx, int sign) __attribute__((always_inline)) {
+    const int n = isA ? g.na : g.nb;
+    const int gc = min(max(gx, 0), n);
+    const int blk = gc >> 6;
+    S0 += sign * (isA ? s.bsa : s.bsb)[blk];
+    if (gc & 63) {
+      partial = true;
+      const int m = 64 * blk + lane;
+      const uint32_t x = m < gc ? (isA ? groupA(s.A, g, m) : groupB(s.B, g, m)) : 0u;
+      part += sign * group_sum(x);
+    }
+  };
+  pre(true, g0, 1);
+  pre(true, g0 - g.nb, -1);
+  pre(false, g0, 1);
+  pre(false, g0 - g.na, -1);
+  if (partial) S0 += wave_sum(part);
+  // per-digit changes of S: alpha'_k - alpha'_{k-Nb} + beta'_k - beta'_{k-Na};
+  // a group range entirely outside its operand is skipped (wave-uniform)
+  int d[4] = {0, 0, 0, 0};
+  int sigma = 0;
+  auto add_group = [&](uint32_t x, int sign, bool rev) __attribute__((always_inline)) {
+    sigma += sign * group_sum(x);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) d[t] += sign * __builtin_amdgcn_sbfe((int)x, 8 * (rev ? 3 - t : t), 8);
+  };
+  auto live = [&](int lo, int n) { return lo + 63 >= 0 && lo < n; };  // [lo, lo+64) meets [0, n)
+  if (live(g0, g.na)) add_group(groupA(s.A, g, m1), 1, true);
+  if (live(g0 - g.nb, g.na)) add_group(groupA(s.A, g, m1 - g.nb), -1, true);
+  if (live(g0, g.nb)) add_group(groupB(s.B, g, m1), 1, false);
+  if (live(g0 - g.na, g.nb)) add_group(groupB(s.B, g, m1 - g.na), -1, false);
+  const int excl = wave_incl_scan(sigma) - sigma;
+  // pair counts cnt_k = min(k+1, Na) - max(0, k+1-Nb) (clamped at 0) change by
+  // the same step for the four digits of a limb: both bounds are multiples of 4
+  const int k0 = 4 * m1;
+  const int cnt0 = min(k0 + 1, g.Na) - max(0, k0 + 1 - g.Nb);
+  const int step = (k0 + 4 <= g.Na ? 1 : 0) - (m1 >= g.nb ? 1 : 0);
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  const v4i cp = *reinterpret_cast<const v4i*>(sc + 4 * lane);
+  int S = S0 + excl;
+  uint64_t X = 0;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    S += d[t];
+    const int cnt = max(0, cnt0 + t * step);
+    // c_k = c'_k + 128 (S_k + 128 cnt_k), at most 2^33
+    const int64_t c = (int64_t)cp[t] + ((int64_t)(S + 128 * cnt) << 7);
+    X += (uint64_t)c << (8 * t);
+  }
+  __builtin_amdgcn_wave_barrier();
+  const uint32_t L = (uint32_t)X;
+  const uint32_t H = (uint32_t)(X >> 32);
+  // H of the lane below, 0 into lane 0 (DPP wave_shr:1)
+  const uint32_t Hprev = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)H, 0x138, 0xf, 0xf, false);
+  const uint64_t sum = (uint64_t)L + Hprev;
+  const uint32_t res = (uint32_t)sum;
+  const bool gb = (sum >> 32) != 0;
+  const bool pb = res == 0xffffffffu;
+  const WaveCarry wc = wave_carry_masks(gb, pb);
+  const uint32_t cin = wave_carry_in(wc, 0);
+  const uint32_t limb = res + cin;
+  const int jg = g0 + lane;
+  const uint64_t tail = ~3ull;   // limbs 2..63
+  const uint64_t ones = __ballot(jg >= g.nout || limb == 0xffffffffu);
+  if (jg < g.nout) out[jg] = limb;
+  if (lane == 63) {
+    const uint32_t cout = (uint32_t)gb | ((uint32_t)pb & cin);
+    s.carry[w] = (uint64_t)(H + cout) | ((uint64_t)((ones & tail) == tail) << 63);
+  }
+}
+
+template <int DW, int P>
 __device__ __forceinline__ void run_band(int band, const Lds& s, const Geo& g, uint32_t* out, int32_t* coef) {
   const int w0 = band * P;
   v4i acc[P];
@@ -343,19 +593,33 @@ __device__ __forceinline__ void run_band(int band, const Lds& s, const Geo& g, u
   for (int rho = 0; rho < 4; ++rho) band_phase<P>(acc, s, g, w0, rho);
 #pragma unroll
   for (int i = 0; i < P; ++i)
-    if (w0 + i < g.W) strip_out(acc[i], w0 + i, s, g, out, coef);
+    if (w0 + i < g.W) {
+      if constexpr (DW == 8)
+        strip_out8(acc[i], w0 + i, s, g, out);
+      else
+        strip_out7(acc[i], w0 + i, s, g, out, coef);
+    }
 }
 
-// out[0 .. na+nb) = a * b for one instance (whole work-group).  With coef
-// != nullptr the raw coefficients c_k (k < Na+Nb-1) are written instead.
-template <int P>
+// out[0 .. na+nb) = a * b for one instance (whole work-group), digits of DW
+// bits.  With coef != nullptr (7-bit digits only) the raw coefficients c_k
+// (k < Na+Nb-1) are written instead.
+template <int DW, int P>
 __device__ __forceinline__ void wg_mul_mfma(uint32_t* out, int32_t* coef, const uint32_t* __restrict__ a, int na,
                             const uint32_t* __restrict__ b, int nb, char* smem) {
-  const Geo g = make_geo(na, nb);
+  static_assert(DW == 7 || DW == 8, "digit width");
+  constexpr int kStripLimbs = strip_limbs<DW>();
+  const Geo g = make_geo<DW>(na, nb);
   const Lds s = carve(smem, g, P);
   const int NB = (g.W + P - 1) / P;
 
-  stage(s, g, a, b);
+  stage<DW>(s, g, a, b);
+  if constexpr (DW == 8) {
+    __syncthreads();
+    block_sums(s, g);
+    __syncthreads();
+    block_prefix(s, g);
+  }
   // band order: most expensive first (rank sort by cost; the costs sit in
   // the wave scratch area, which holds 256 ints per wave >= NB)
   for (int t = threadIdx.x; t < NB; t += blockDim.x) s.scr[t] = band_cost(g, t, P);
@@ -378,11 +642,11 @@ __device__ __forceinline__ void wg_mul_mfma(uint32_t* out, int32_t* coef, const 
     t = __builtin_amdgcn_readfirstlane(t);
     if ((int)t >= NB) break;
     const int band = __builtin_amdgcn_readfirstlane((int)s.order[t]);
-    run_band<P>(band, s, g, out, coef);
+    run_band<DW, P>(band, s, g, out, coef);
   }
   __syncthreads();
   if (coef == nullptr) {
-    // out += sum_w C_w B^(56(w+1)).  Strip w' receives C_{w'-1} (< 2^35) on its
+    // out += sum_w C_w B^(L(w+1)), L limbs per strip.  Strip w' receives C_{w'-1} (< 2^35) on its
     // limbs 0 and 1; a carry out of limb 1 runs on only through a tail of
     // all-ones limbs.  So an exclusive carry scan over strips, one strip per
     // thread, resolves everything: strip w' generates when limbs 0..1 plus

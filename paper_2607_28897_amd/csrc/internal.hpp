@@ -9,7 +9,13 @@ namespace bi {
 struct MfmaCfg {
   int P;       // strips per wave band (4, 8, 16)
   int waves;   // waves per work-group (4, 8)
+  int dw;      // digit width: 7 (plain 7-bit digits) or 8 (offset 8-bit digits)
 };
+
+// index of a tile configuration in the ragged kernel's dispatch
+inline int ragged_cfg_id(MfmaCfg c) {
+  return (c.dw == 8 ? 3 : 0) + (c.P == 4 ? 0 : (c.P == 8 ? 1 : 2));
+}
 
 MfmaCfg default_mfma_cfg(int na, int nb);
 MfmaCfg current_mfma_cfg(int na, int nb);  // thread override or default
@@ -32,7 +38,7 @@ size_t plain_lds(int na, int nb);
 // configuration for that instance.
 struct QueueItem {
   int32_t inst;
-  int32_t cfg;   // MFMA: index into kPersistCfgs; plain: 0
+  int32_t cfg;   // MFMA: ragged_cfg_id of the instance's configuration; plain: 0
 };
 
 int launch_mul_ragged(uint32_t* out, const int64_t* out_off, const uint32_t* a,
@@ -45,6 +51,7 @@ int launch_mfma_rate(int32_t* out, int blocks, int iters, hipStream_t s);
 // ---- division -------------------------------------------------------------------
 size_t div_ws_bytes(int cap_u, int cap_v, int grid);
 size_t div_lds_bytes(int cap_u, int cap_v);
+int div_groups_per_cu(int cap_u, int cap_v);
 int launch_divmod(uint32_t* q, const int64_t* q_off, uint32_t* r, const int64_t* r_off,
                   int32_t* status, const uint32_t* u, const int64_t* u_off, int nu,
                   const uint32_t* v, const int64_t* v_off, int nv, const int32_t* queue,

@@ -148,42 +148,54 @@ int launch_mul_plain(uint32_t* out, const uint32_t* a, int64_t na, const uint32_
 // ============================================================================
 // MFMA-split multiply: one work-group per instance
 // ============================================================================
-template <int P>
+template <int DW, int P>
 __global__ __launch_bounds__(512) void k_mul_mfma(uint32_t* out, int32_t* coef, const uint32_t* a,
                                                   int na, const uint32_t* b, int nb) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
   const int64_t inst = blockIdx.x;
   const int K = mfma::ndigits(na) + mfma::ndigits(nb) - 1;
-  mfma::wg_mul_mfma<P>(out ? out + inst * (int64_t)(na + nb) : nullptr,
-                       coef ? coef + inst * (int64_t)K : nullptr, a + inst * (int64_t)na, na,
-                       b + inst * (int64_t)nb, nb, smem);
+  mfma::wg_mul_mfma<DW, P>(out ? out + inst * (int64_t)(na + nb) : nullptr,
+                           coef ? coef + inst * (int64_t)K : nullptr, a + inst * (int64_t)na, na,
+                           b + inst * (int64_t)nb, nb, smem);
 }
 
 size_t mfma_lds(int na, int nb, MfmaCfg cfg) {
-  return mfma::lds_bytes(na, nb, cfg.waves, cfg.P);
+  return cfg.dw == 8 ? mfma::lds_bytes<8>(na, nb, cfg.waves, cfg.P)
+                     : mfma::lds_bytes<7>(na, nb, cfg.waves, cfg.P);
 }
 
-template <int P>
+template <int DW, int P>
 static int launch_mfma_p(uint32_t* out, int32_t* coef, const uint32_t* a, int64_t na,
                          const uint32_t* b, int64_t nb, int64_t batch, int waves, hipStream_t s) {
-  const size_t lds = mfma::lds_bytes((int)na, (int)nb, waves, P);
+  const size_t lds = mfma::lds_bytes<DW>((int)na, (int)nb, waves, P);
   if (lds > 163840) return BIGINT_EUNSUPPORTED;
-  BI_HIP(hipFuncSetAttribute((const void*)k_mul_mfma<P>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)lds));
-  hipLaunchKernelGGL((k_mul_mfma<P>), dim3((unsigned)batch), dim3(64 * waves), lds, s, out, coef,
-                     a, (int)na, b, (int)nb);
+  BI_HIP(hipFuncSetAttribute((const void*)k_mul_mfma<DW, P>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL((k_mul_mfma<DW, P>), dim3((unsigned)batch), dim3(64 * waves), lds, s, out,
+                     coef, a, (int)na, b, (int)nb);
   BI_LAUNCH_CHECK();
   return BIGINT_OK;
 }
 
-int launch_mul_mfma(uint32_t* out, int32_t* coef, const uint32_t* a, int64_t na,
-                    const uint32_t* b, int64_t nb, int64_t batch, MfmaCfg cfg, hipStream_t s) {
+template <int DW>
+static int launch_mfma_dw(uint32_t* out, int32_t* coef, const uint32_t* a, int64_t na,
+                          const uint32_t* b, int64_t nb, int64_t batch, MfmaCfg cfg,
+                          hipStream_t s) {
   switch (cfg.P) {
-    case 4: return launch_mfma_p<4>(out, coef, a, na, b, nb, batch, cfg.waves, s);
-    case 8: return launch_mfma_p<8>(out, coef, a, na, b, nb, batch, cfg.waves, s);
-    case 16: return launch_mfma_p<16>(out, coef, a, na, b, nb, batch, cfg.waves, s);
+    case 4: return launch_mfma_p<DW, 4>(out, coef, a, na, b, nb, batch, cfg.waves, s);
+    case 8: return launch_mfma_p<DW, 8>(out, coef, a, na, b, nb, batch, cfg.waves, s);
+    case 16: return launch_mfma_p<DW, 16>(out, coef, a, na, b, nb, batch, cfg.waves, s);
     default: return BIGINT_EINVAL;
   }
+}
+
+// coef != nullptr (raw coefficients) is served with 7-bit digits only
+int launch_mul_mfma(uint32_t* out, int32_t* coef, const uint32_t* a, int64_t na,
+                    const uint32_t* b, int64_t nb, int64_t batch, MfmaCfg cfg, hipStream_t s) {
+  if (cfg.dw == 8 && coef == nullptr)
+    return launch_mfma_dw<8>(out, nullptr, a, na, b, nb, batch, cfg, s);
+  if (cfg.dw != 7 && cfg.dw != 8) return BIGINT_EINVAL;
+  return launch_mfma_dw<7>(out, coef, a, na, b, nb, batch, cfg, s);
 }
 
 // ============================================================================
@@ -212,10 +224,10 @@ int launch_digits7(uint8_t* out, const uint32_t* a, int64_t n, int64_t D, int64_
 // ============================================================================
 // Each tile configuration is its own (not inlined) function so that the
 // persistent kernel's register budget is that of the largest one alone.
-template <int P>
+template <int DW, int P>
 __device__ __noinline__ void ragged_item(uint32_t* po, const uint32_t* pa, int na,
                                          const uint32_t* pb, int nb, char* smem) {
-  mfma::wg_mul_mfma<P>(po, nullptr, pa, na, pb, nb, smem);
+  mfma::wg_mul_mfma<DW, P>(po, nullptr, pa, na, pb, nb, smem);
 }
 
 __global__ __launch_bounds__(512) void k_mul_mfma_ragged(uint32_t* out, const int64_t* out_off,
@@ -239,9 +251,12 @@ __global__ __launch_bounds__(512) void k_mul_mfma_ragged(uint32_t* out, const in
     const uint32_t* pa = a + a_off[i];
     const uint32_t* pb = b + b_off[i];
     switch (__builtin_amdgcn_readfirstlane(q.cfg)) {
-      case 0: ragged_item<4>(po, pa, na, pb, nb, smem); break;
-      case 1: ragged_item<8>(po, pa, na, pb, nb, smem); break;
-      default: ragged_item<16>(po, pa, na, pb, nb, smem); break;
+      case 0: ragged_item<7, 4>(po, pa, na, pb, nb, smem); break;
+      case 1: ragged_item<7, 8>(po, pa, na, pb, nb, smem); break;
+      case 2: ragged_item<7, 16>(po, pa, na, pb, nb, smem); break;
+      case 3: ragged_item<8, 4>(po, pa, na, pb, nb, smem); break;
+      case 4: ragged_item<8, 8>(po, pa, na, pb, nb, smem); break;
+      default: ragged_item<8, 16>(po, pa, na, pb, nb, smem); break;
     }
   }
 }

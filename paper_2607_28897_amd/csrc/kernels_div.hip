@@ -13,7 +13,7 @@ __global__ void k_zero_u32_div(uint32_t* p, int n) {
 // Uniform batches pass null offsets and the limb counts nu / nv; ragged
 // batches pass prefix offsets.  queue == nullptr means instance t is item t.
 // h_inv >= 0 selects the shifted-inverse diagnostic: q[i] = floor(B^h_inv / v).
-__global__ __launch_bounds__(512) void k_divmod(uint32_t* q, const int64_t* q_off, uint32_t* r,
+__global__ __launch_bounds__(512, 4) void k_divmod(uint32_t* q, const int64_t* q_off, uint32_t* r,
                                                 const int64_t* r_off, int32_t* status,
                                                 const uint32_t* u, const int64_t* u_off, int nu,
                                                 const uint32_t* v, const int64_t* v_off, int nv,
@@ -64,7 +64,14 @@ size_t div_lds_bytes(int cap_u, int cap_v) {
   // the largest product of a division has two factors of at most cap_u + 8 limbs
   const int m = cap_u + 8;
   (void)cap_v;
-  return mfma::lds_bytes(m, m, 8, div::kP);
+  return mfma::lds_bytes<div::kDW>(m, m, 8, div::kP);
+}
+
+// Work-groups that fit one CU: the kernel is built for 4 waves per SIMD (two
+// 8-wave groups), so LDS decides.
+int div_groups_per_cu(int cap_u, int cap_v) {
+  const size_t per = div_lds_bytes(cap_u, cap_v) + sizeof(div::Shared) + 64;
+  return 2 * per <= 163840 ? 2 : 1;
 }
 
 int launch_divmod(uint32_t* q, const int64_t* q_off, uint32_t* r, const int64_t* r_off,

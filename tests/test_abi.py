@@ -64,8 +64,9 @@ def test_host_side_argument_checks(bi):
     assert L.bigint_divmod(ctypes.c_void_p(0x100000), ctypes.c_void_p(0x200000), None, p, 9000,
                            q, 4, 1, None) == EUNS
     assert L.bigint_shinv(ctypes.c_void_p(0x100000), p, 5, 4, 1, None) == EINVAL   # h < nv
-    assert L.bigint_set_mfma_config(5, 0) == EINVAL
-    assert L.bigint_set_mfma_config(0, 3) == EINVAL
+    assert L.bigint_set_mfma_config(5, 0, 0) == EINVAL
+    assert L.bigint_set_mfma_config(0, 3, 0) == EINVAL
+    assert L.bigint_set_mfma_config(0, 0, 6) == EINVAL
     assert L.bigint_digits7(None, p, 4, 5, 1, None) == EINVAL
     assert L.bigint_diag_mfma_rate(None, 1, 1, None) == EINVAL
 

@@ -14,14 +14,21 @@ def bi():
     import paper_2607_28897_amd as m
     m.lib()
     yield m
-    m.set_mfma_config(0, 0)
+    m.set_mfma_config(0, 0, 0)
 
 
-ALGOS = ["plain", "mfma"]
+# the plain kernel, and the MFMA-split kernel with 7-bit and offset 8-bit digits
+ALGOS = ["plain", "mfma7", "mfma8"]
 
 
-def _algo(bi, name):
-    return bi.MUL_PLAIN if name == "plain" else bi.MUL_MFMA
+def _mul(bi, ta, tb, name):
+    if name == "plain":
+        return bi.mul(ta, tb, bi.MUL_PLAIN)
+    bi.set_mfma_config(0, 0, 7 if name == "mfma7" else 8)
+    try:
+        return bi.mul(ta, tb, bi.MUL_MFMA)
+    finally:
+        bi.set_mfma_config(0, 0, 0)
 
 
 # ---- the steps of the MFMA path ---------------------------------------------------
@@ -61,7 +68,7 @@ def test_coefficients_all_ones_bound(bi, orc):
 def test_pairs_2e15(bi, orc, algo):
     from paper_2607_28897_amd import inputs
     c = inputs.pairs_2e15()
-    p = bi.mul(dev(c["a"]), dev(c["b"]), _algo(bi, algo))
+    p = _mul(bi, dev(c["a"]), dev(c["b"]), algo)
     assert np.array_equal(host(p), orc.mul(c["a"], c["b"]))
 
 
@@ -69,7 +76,7 @@ def test_pairs_2e15(bi, orc, algo):
 def test_pairs_2e17_sampled(bi, orc, algo):
     from paper_2607_28897_amd import inputs
     c = inputs.pairs_2e17_mixed()
-    p = host(bi.mul(dev(c["a"]), dev(c["b"]), _algo(bi, algo)))
+    p = host(_mul(bi, dev(c["a"]), dev(c["b"]), algo))
     # every instance is checked against the oracle on a sample of rows, half
     # uniform and half carry-adversarial
     for i in list(range(0, 512, 37)) + list(range(512, 1024, 37)):
@@ -80,7 +87,7 @@ def test_pairs_2e17_sampled(bi, orc, algo):
 def test_pairs_2e19_sampled(bi, orc, algo):
     from paper_2607_28897_amd import inputs
     c = inputs.pairs_2e19()
-    p = host(bi.mul(dev(c["a"]), dev(c["b"]), _algo(bi, algo)))
+    p = host(_mul(bi, dev(c["a"]), dev(c["b"]), algo))
     for i in (0, 1, 77, 128, 200, 255):
         assert np.array_equal(p[i], orc.mul1(c["a"][i], c["b"][i])), i
 
@@ -90,7 +97,7 @@ def test_all_ones_2e19(bi, orc, algo):
     # (B^n - 1)^2: every 7-bit digit is 127, the largest coefficients possible
     n = 16384
     a = np.full((1, n), 0xFFFFFFFF, np.uint32)
-    p = host(bi.mul(dev(a), dev(a), _algo(bi, algo)))[0]
+    p = host(_mul(bi, dev(a), dev(a), algo))[0]
     want = np.concatenate([[1], np.zeros(n - 1), [0xFFFFFFFE], np.full(n - 1, 0xFFFFFFFF)]).astype(np.uint32)
     assert np.array_equal(p, want)
 
@@ -103,7 +110,7 @@ def test_shapes(bi, orc, algo, na, nb):
     a = rand_limbs(g, 3, na)
     b = rand_limbs(g, 3, nb)
     b[2] = 0xFFFFFFFF
-    p = host(bi.mul(dev(a), dev(b), _algo(bi, algo)))
+    p = host(_mul(bi, dev(a), dev(b), algo))
     for i in range(3):
         assert np.array_equal(p[i], orc.mul1(a[i], b[i])), i
 
@@ -114,22 +121,23 @@ def test_zero_and_one(bi, orc):
     a = rand_limbs(g, 2, n)
     b = np.zeros((2, n), np.uint32)
     b[1, 0] = 1
-    for algo in (bi.MUL_PLAIN, bi.MUL_MFMA):
-        p = host(bi.mul(dev(a), dev(b), algo))
+    for algo in ALGOS:
+        p = host(_mul(bi, dev(a), dev(b), algo))
         assert not p[0].any()
         assert np.array_equal(p[1][:n], a[1]) and not p[1][n:].any()
 
 
+@pytest.mark.parametrize("dw", [7, 8])
 @pytest.mark.parametrize("P,waves", [(4, 4), (4, 8), (8, 4), (8, 8), (16, 4), (16, 8)])
-def test_tile_configs_identical(bi, orc, P, waves):
+def test_tile_configs_identical(bi, orc, P, waves, dw):
     g = np.random.default_rng(P * 10 + waves)
     a = rand_limbs(g, 2, 3333)
     b = rand_limbs(g, 2, 2900)
-    bi.set_mfma_config(P, waves)
+    bi.set_mfma_config(P, waves, dw)
     try:
         p = host(bi.mul(dev(a), dev(b), bi.MUL_MFMA))
     finally:
-        bi.set_mfma_config(0, 0)
+        bi.set_mfma_config(0, 0, 0)
     for i in range(2):
         assert np.array_equal(p[i], orc.mul1(a[i], b[i]))
 
@@ -138,18 +146,19 @@ def test_plain_matches_mfma_bytes(bi):
     g = np.random.default_rng(42)
     a = rand_limbs(g, 16, 4096)
     b = rand_limbs(g, 16, 4096)
-    p1 = host(bi.mul(dev(a), dev(b), bi.MUL_PLAIN))
-    p2 = host(bi.mul(dev(a), dev(b), bi.MUL_MFMA))
-    assert np.array_equal(p1, p2)
+    p1 = host(_mul(bi, dev(a), dev(b), "plain"))
+    for algo in ("mfma7", "mfma8"):
+        assert np.array_equal(p1, host(_mul(bi, dev(a), dev(b), algo))), algo
 
 
 def test_repeat_deterministic(bi):
     g = np.random.default_rng(43)
     a = dev(rand_limbs(g, 8, 5000))
     b = dev(rand_limbs(g, 8, 5000))
-    r1 = host(bi.mul(a, b, bi.MUL_MFMA))
-    r2 = host(bi.mul(a, b, bi.MUL_MFMA))
-    assert np.array_equal(r1, r2)
+    for algo in ("mfma7", "mfma8"):
+        r1 = host(_mul(bi, a, b, algo))
+        r2 = host(_mul(bi, a, b, algo))
+        assert np.array_equal(r1, r2)
 
 
 def test_autotune_table_roundtrip(bi, orc, tmp_path):
@@ -160,6 +169,7 @@ def test_autotune_table_roundtrip(bi, orc, tmp_path):
     assert t["op"] == "mul_mfma" and len(t["bins"]) == 5
     for e in t["bins"]:
         assert e["strips_per_band"] in (4, 8, 16) and e["waves"] in (4, 8)
+        assert e["digit_bits"] in (7, 8)
     bi.autotune_load(path)
     g = np.random.default_rng(9)
     a = rand_limbs(g, 3, 5000)
@@ -179,6 +189,50 @@ def test_products_with_long_all_ones_runs(bi, orc, algo, n, m):
     b = rand_limbs(g, 2, m)
     b[1, 0] = 1
     b[1, 1:] = 0
-    p = host(bi.mul(dev(a), dev(b), _algo(bi, algo)))
+    p = host(_mul(bi, dev(a), dev(b), algo))
     for i in range(2):
         assert np.array_equal(p[i], orc.mul1(a[i], b[i])), i
+
+
+@pytest.mark.parametrize("dw,n", [(7, 16397), (8, 18432), (0, 18432)])
+def test_largest_supported_size(bi, orc, dw, n):
+    # 16,397 limbs: the largest 7-bit-digit operands whose digits fit the LDS
+    # with 8 waves; 18,432 = BIGINT_MFMA_MAX_LIMBS (8-bit digits, also the
+    # default there)
+    g = np.random.default_rng(dw)
+    a = rand_limbs(g, 1, n)
+    b = rand_limbs(g, 1, n)
+    bi.set_mfma_config(0, 8, dw)
+    try:
+        p = host(bi.mul(dev(a), dev(b), bi.MUL_MFMA))[0]
+    finally:
+        bi.set_mfma_config(0, 0, 0)
+    assert np.array_equal(p, orc.mul1(a[0], b[0]))
+
+
+def test_forced_7bit_beyond_lds_is_unsupported(bi):
+    a = dev(np.zeros((1, 16398), np.uint32))
+    bi.set_mfma_config(0, 8, 7)
+    try:
+        with pytest.raises(bi.BigIntError) as e:
+            bi.mul(a, a, bi.MUL_MFMA)
+        assert e.value.code == bi.EUNSUPPORTED
+    finally:
+        bi.set_mfma_config(0, 0, 0)
+
+
+@pytest.mark.parametrize("pat", ["zeros", "zeros_ones", "alt"])
+def test_offset_digit_extremes(bi, orc, pat):
+    # offset 8-bit digits: zero bytes are -128, 0xFF bytes +127, so zero
+    # operands drive every MFMA sum to its largest magnitude (2^14 per pair at
+    # the deepest column of the largest size)
+    n = 18432
+    a = np.zeros((1, n), np.uint32)
+    b = np.zeros((1, n), np.uint32)
+    if pat == "zeros_ones":
+        b[:] = 0xFFFFFFFF
+    elif pat == "alt":
+        a[:] = 0x00FF00FF
+        b[:] = 0xFF00FF00
+    p = host(_mul(bi, dev(a), dev(b), "mfma8"))[0]
+    assert np.array_equal(p, orc.mul1(a[0], b[0]))
