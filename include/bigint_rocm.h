@@ -218,6 +218,13 @@ int bigint_diag_mfma_rate(int32_t* scratch, int64_t blocks, int64_t iters, void*
  * same bytes; other values return BIGINT_EINVAL. */
 int bigint_set_mfma_config(int strips_per_band, int waves, int digit_bits);
 
+/* The tile configuration bigint_mul would use on this thread for an na x nb
+ * product (tuned table, then this thread's overrides), written to the three
+ * host ints.  BIGINT_EUNSUPPORTED if the MFMA multiply does not take that
+ * size with it; BIGINT_EINVAL for null pointers or sizes < 1. */
+int bigint_mfma_config(int64_t na, int64_t nb, int* strips_per_band, int* waves,
+                       int* digit_bits);
+
 #ifdef __cplusplus
 }
 #endif

@@ -20,7 +20,7 @@ import os
 
 __all__ = [
     "lib", "add", "sub", "mul", "divmod", "digits7", "conv7", "shinv",
-    "MulPlan", "DivPlan", "autotune", "autotune_load", "set_mfma_config", "BigIntError",
+    "MulPlan", "DivPlan", "autotune", "autotune_load", "set_mfma_config", "mfma_config", "BigIntError",
     "MUL_AUTO", "MUL_PLAIN", "MUL_MFMA",
 ]
 
@@ -47,6 +47,7 @@ class BigIntError(RuntimeError):
 _lib = None
 _vp = ctypes.c_void_p
 _i64 = ctypes.c_int64
+_pint = ctypes.POINTER(ctypes.c_int)
 _int = ctypes.c_int
 
 
@@ -82,6 +83,7 @@ def lib() -> ctypes.CDLL:
             "bigint_conv7": ([_vp, _vp, _i64, _vp, _i64, _i64, _vp], _int),
             "bigint_shinv": ([_vp, _vp, _i64, _i64, _i64, _vp], _int),
             "bigint_set_mfma_config": ([_int, _int, _int], _int),
+            "bigint_mfma_config": ([_i64, _i64, _pint, _pint, _pint], _int),
             "bigint_diag_mfma_rate": ([_vp, _i64, _i64, _vp], _int),
         }
         for name, (args, res) in sig.items():
@@ -214,6 +216,15 @@ def shinv(v, h: int):
 
 def set_mfma_config(strips_per_band: int = 0, waves: int = 0, digit_bits: int = 0):
     _check(lib().bigint_set_mfma_config(strips_per_band, waves, digit_bits), "bigint_set_mfma_config")
+
+
+def mfma_config(na: int, nb: int):
+    """(strips_per_band, waves, digit_bits) that bigint_mul uses for na x nb."""
+    import ctypes
+    p, w, d = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(lib().bigint_mfma_config(na, nb, ctypes.byref(p), ctypes.byref(w), ctypes.byref(d)),
+           "bigint_mfma_config")
+    return p.value, w.value, d.value
 
 
 def autotune(cache_path: str | None = None, flags: int = 0):

@@ -108,6 +108,16 @@ int bigint_set_mfma_config(int strips_per_band, int waves, int digit_bits) {
   return BIGINT_OK;
 }
 
+int bigint_mfma_config(int64_t na, int64_t nb, int* strips_per_band, int* waves, int* digit_bits) {
+  if (na <= 0 || nb <= 0 || !strips_per_band || !waves || !digit_bits) return BIGINT_EINVAL;
+  if (na > BIGINT_MFMA_MAX_LIMBS || nb > BIGINT_MFMA_MAX_LIMBS) return BIGINT_EUNSUPPORTED;
+  const MfmaCfg c = current_mfma_cfg((int)na, (int)nb);
+  *strips_per_band = c.P;
+  *waves = c.waves;
+  *digit_bits = c.dw;
+  return mfma_lds((int)na, (int)nb, c) <= 163840 ? BIGINT_OK : BIGINT_EUNSUPPORTED;
+}
+
 static int addsub_common(bool sub, uint32_t* out, uint32_t* cout, const uint32_t* a,
                          const uint32_t* b, int64_t n, int64_t batch, void* stream) {
   if (!out || !a || !b || n <= 0 || batch < 0) return BIGINT_EINVAL;

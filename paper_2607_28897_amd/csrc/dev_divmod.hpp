@@ -24,7 +24,7 @@
 namespace bi {
 namespace div {
 
-constexpr int kP = 8;   // strips per band of the multiplications
+constexpr int kP = 4;   // strips per band of the multiplications
 constexpr int kDW = 8;  // digit width of the multiplications
 constexpr int kMaxAdjust = 64;  // cap on fix-up rounds per scale
 

@@ -1,9 +1,14 @@
 // kernels_div.hip -- division kernels: one work-group per division, pulling
 // instances from a queue (largest first) until the queue is empty.
+#include <algorithm>
+
 #include "internal.hpp"
 #include "dev_divmod.hpp"
 
 namespace bi {
+
+// threads per division work-group
+constexpr int kDivThreads = 512;
 
 __global__ void k_zero_u32_div(uint32_t* p, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -13,7 +18,7 @@ __global__ void k_zero_u32_div(uint32_t* p, int n) {
 // Uniform batches pass null offsets and the limb counts nu / nv; ragged
 // batches pass prefix offsets.  queue == nullptr means instance t is item t.
 // h_inv >= 0 selects the shifted-inverse diagnostic: q[i] = floor(B^h_inv / v).
-__global__ __launch_bounds__(512, 4) void k_divmod(uint32_t* q, const int64_t* q_off, uint32_t* r,
+__global__ __launch_bounds__(kDivThreads, 4) void k_divmod(uint32_t* q, const int64_t* q_off, uint32_t* r,
                                                 const int64_t* r_off, int32_t* status,
                                                 const uint32_t* u, const int64_t* u_off, int nu,
                                                 const uint32_t* v, const int64_t* v_off, int nv,
@@ -64,14 +69,15 @@ size_t div_lds_bytes(int cap_u, int cap_v) {
   // the largest product of a division has two factors of at most cap_u + 8 limbs
   const int m = cap_u + 8;
   (void)cap_v;
-  return mfma::lds_bytes<div::kDW>(m, m, 8, div::kP);
+  return mfma::lds_bytes<div::kDW>(m, m, kDivThreads / 64, div::kP);
 }
 
-// Work-groups that fit one CU: the kernel is built for 4 waves per SIMD (two
-// 8-wave groups), so LDS decides.
+// Work-groups that fit one CU: the kernel is built for 4 waves per SIMD (16
+// per CU), so that many waves and then the LDS decide.
 int div_groups_per_cu(int cap_u, int cap_v) {
   const size_t per = div_lds_bytes(cap_u, cap_v) + sizeof(div::Shared) + 64;
-  return 2 * per <= 163840 ? 2 : 1;
+  const int by_waves = 16 / (kDivThreads / 64);
+  return std::max(1, std::min<int>(by_waves, (int)(163840 / per)));
 }
 
 int launch_divmod(uint32_t* q, const int64_t* q_off, uint32_t* r, const int64_t* r_off,
@@ -87,7 +93,7 @@ int launch_divmod(uint32_t* q, const int64_t* q_off, uint32_t* r, const int64_t*
   BI_LAUNCH_CHECK();
   BI_HIP(hipFuncSetAttribute((const void*)k_divmod, hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)lds));
-  hipLaunchKernelGGL(k_divmod, dim3(grid), dim3(512), lds, s, q, q_off, r, r_off, status, u, u_off,
+  hipLaunchKernelGGL(k_divmod, dim3(grid), dim3(kDivThreads), lds, s, q, q_off, r, r_off, status, u, u_off,
                      nu, v, v_off, nv, queue, (int)nitems, counter, bufs, cap_u, cap_v, h_inv,
                      adjust);
   BI_LAUNCH_CHECK();

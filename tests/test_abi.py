@@ -93,3 +93,19 @@ def test_binding_fails_loudly_without_library(monkeypatch):
     monkeypatch.setattr(m, "LIB_PATH", "/nonexistent/libbigint_rocm.so")
     with pytest.raises(RuntimeError):
         m.lib()
+
+
+def test_mfma_config_query(bi):
+    # host-side only: the tuned table, the LDS fit and the thread overrides
+    assert bi.mfma_config(16384, 16384) == (16, 8, 8)
+    assert bi.mfma_config(1024, 1024) == (4, 4, 8)
+    bi.set_mfma_config(0, 0, 7)
+    try:
+        assert bi.mfma_config(16384, 16384) == (16, 8, 7)
+        assert bi.mfma_config(16397, 16397)[2] == 7
+        with pytest.raises(bi.BigIntError):
+            bi.mfma_config(16398, 16398)          # 7-bit digits no longer fit the LDS
+    finally:
+        bi.set_mfma_config(0, 0, 0)
+    with pytest.raises(bi.BigIntError):
+        bi.mfma_config(18433, 1)                   # beyond BIGINT_MFMA_MAX_LIMBS
