@@ -27,6 +27,7 @@ namespace div {
 constexpr int kP = 4;   // strips per band of the multiplications
 constexpr int kDW = 8;  // digit width of the multiplications
 constexpr int kMaxAdjust = 64;  // cap on fix-up rounds per scale
+constexpr int kGuard = 2;       // divisor limbs kept beyond the precision of a Newton step
 
 // LDS words used by the division itself (besides the multiply's area)
 struct Shared {
@@ -273,14 +274,26 @@ __device__ inline int shifted_inverse(const uint32_t* v, int k1, int h, Bufs& bf
     __syncthreads();
     lw = 1;
   }
-  lw = fixup(v, k1, cur, bf, lw, sh, smem, adjust);
-  while (cur < h) {
+  // Newton steps.  w ~ floor(B^cur / v) carries p = cur - k1 + 1 limbs, and a
+  // step to precision p' only needs the divisor to about p' limbs: with V =
+  // the top t = min(k1, p' + kGuard) limbs of v (v = V B^s + low, s = k1 - t),
+  // floor(B^(cur-s) / V) differs from floor(B^cur / v) by at most a unit or
+  // two, so each step runs on V at the scale cur - s: an exact fix-up there
+  // (which also yields e = B^(cur-s) - V w in [0, V)), then the step.  The
+  // last fix-up, at scale h, uses all of v.
+  for (;;) {
     const int m = min(h - cur, cur - k1);
-    // Y = w * e (e < v has at most k1 limbs)
-    const int le = wg_prec(bf.E, k1 + 2, sh);
+    const int t = cur == h ? k1 : min(k1, cur + m - k1 + 1 + kGuard);
+    const int sdrop = k1 - t;
+    const uint32_t* V = v + sdrop;
+    const int c = cur - sdrop;
+    lw = fixup(V, t, c, bf, lw, sh, smem, adjust);
+    if (cur == h) break;
+    // Y = w * e (e < V has at most t limbs)
+    const int le = wg_prec(bf.E, t + 2, sh);
     int lnew;
     if (le == 0) {
-      // e = 0: v divides B^cur, so w' = w B^m exactly
+      // e = 0: V divides B^c, so w' = w B^m exactly
       lnew = lw + m;
       wg_fill(bf.U2, lnew + 1, 0u);
       for (int i = threadIdx.x; i < lw; i += blockDim.x) bf.U2[i + m] = bf.W[i];
@@ -288,23 +301,23 @@ __device__ inline int shifted_inverse(const uint32_t* v, int k1, int h, Bufs& bf
     } else {
       wg_mul(bf.T, bf.W, lw, bf.E, le, smem);
       const int ly = lw + le;
-      // w' = w B^m + floor(Y / B^(cur - m))
+      // w' = w B^m + floor(Y / B^(c - m))
       lnew = lw + m + 1;
       auto X = [&](int j) -> uint32_t { return (j >= m && j - m < lw) ? bf.W[j - m] : 0u; };
       auto Y = [&](int j) -> uint32_t {
-        const int s = j + cur - m;
-        return s < ly ? bf.T[s] : 0u;
+        const int s2 = j + c - m;
+        return s2 < ly ? bf.T[s2] : 0u;
       };
       wg_addsub<16, false>(bf.U2, lnew, X, Y, 0u, sh->scan);
     }
     {  // the new w is in U2: swap the two buffers instead of copying
-      uint32_t* t = bf.W;
+      uint32_t* tmp = bf.W;
       bf.W = bf.U2;
-      bf.U2 = t;
+      bf.U2 = tmp;
     }
     lw = wg_prec(bf.W, lnew, sh);
+    if (lw == 0) lw = 1;
     cur += m;
-    lw = fixup(v, k1, cur, bf, lw, sh, smem, adjust);
   }
   return lw;
 }

@@ -115,3 +115,25 @@ def test_knuth_add_back_inputs(bi, orc):
     for u, v in ADD_BACK_CASES:
         nu, nv = -(-u.bit_length() // 32), -(-v.bit_length() // 32)
         _check_batch(bi, orc, from_int(u, nu)[None], from_int(v, nv)[None])
+
+
+@pytest.mark.parametrize("nu,nv", [(40, 17), (2000, 600), (2000, 1000), (4100, 2049)])
+def test_divisor_structures(bi, orc, nu, nv):
+    # the Newton steps read only the top limbs of v: divisors whose low limbs
+    # are zero, whose top limbs are a power of B or all ones, or whose low
+    # limbs alone differ, must still give the exact quotient
+    g = np.random.default_rng(nu + 7 * nv)
+    u = rand_limbs(g, 6, nu)
+    v = rand_limbs(g, 6, nv)
+    v[0, :] = 0
+    v[0, -1] = 1                                   # B^(nv-1)
+    v[1, : nv - 3] = 0                             # three random top limbs, zeros below
+    v[2, nv // 2:] = 0xFFFFFFFF                    # all-ones top half
+    v[3] = v[2]
+    v[3, 0] ^= 1                                   # differs from row 2 in the lowest bit only
+    u[4] = 0xFFFFFFFF
+    v[4, :] = 0xFFFFFFFF
+    v[4, 0] = 0xFFFFFFFE                           # B^nv - 2
+    u[5, :] = 0
+    u[5, -1] = 1                                   # u = B^(nu-1)
+    _check_batch(bi, orc, u, v)
