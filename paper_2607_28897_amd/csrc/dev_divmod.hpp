@@ -123,12 +123,13 @@ __device__ __forceinline__ uint32_t wg_arith1(uint32_t* dst, int n, const uint32
   return wg_addsub<16, SUB>(dst, n, X, Y, 0u, sh->scan);
 }
 
-// dst[0 .. na+nb) = a * b (MFMA-split multiply; dst must not overlap a, b).
-// One out-of-line copy serves every call site of the division, so the
-// kernel's code stays small enough for the instruction cache.
+// dst[0 .. nout) = a * b mod B^nout (nout < 0: all na+nb limbs; MFMA-split
+// multiply; dst must not overlap a, b).  One out-of-line copy serves every
+// call site of the division, so the kernel's code stays small enough for the
+// instruction cache.
 __device__ __noinline__ void wg_mul(uint32_t* dst, const uint32_t* a, int na, const uint32_t* b,
-                                       int nb, char* smem) {
-  mfma::wg_mul_mfma<kDW, kP>(dst, nullptr, a, na, b, nb, smem);
+                                       int nb, char* smem, int nout) {
+  mfma::wg_mul_mfma<kDW, kP>(dst, nullptr, a, na, b, nb, smem, nout);
 }
 
 // ---- one-lane helpers for the starting value ------------------------------------
@@ -172,31 +173,54 @@ __device__ inline int fixup(const uint32_t* v, int k1, int c, Bufs& bf, int lw, 
                             char* smem, int* adjust) {
   // P = v * w
   const int lp = k1 + lw;
-  wg_mul(bf.T, v, k1, bf.W, lw, smem);
-  // sign: P >= B^c  <=>  some limb at index >= c is nonzero
-  const int pp = wg_prec(bf.T, lp, sh);
   const int le = max(k1 + 2, 2);
-  bool neg;
-  if (pp <= c) {
-    // e = B^c - P (P < B^c): the low c limbs of 0 - P; it is < few v
-    neg = false;
-    auto X = [&](int) -> uint32_t { return 0u; };
-    auto Y = [&](int j) -> uint32_t { return j < lp ? bf.T[j] : 0u; };
-    wg_addsub<16, true>(bf.T, min(c, lp), X, Y, 0u, sh->scan);  // in place
-    // limbs [min(c,lp), c) of 0 - P are all ones only if P == 0, which w >= 1 rules out
-    wg_shr_copy(bf.E, le, bf.T, min(c, lp), 0);
-    if (c > lp) {
-      // B^c - P with P < B^lp <= B^(c-1): e would be >= B^(c-1) -- far from w
-      // exact; keep it exact anyway by filling the all-ones limbs
-      for (int i = threadIdx.x; i < le; i += blockDim.x)
-        if (i >= lp && i < c) bf.E[i] = 0xffffffffu;
-      __syncthreads();
+  bool neg = false;
+  bool have_e = false;
+  if (c >= le && lp > le) {
+    // |e| = |B^c - P| is a few v at most, below B^(le-1): P mod B^le then
+    // ends in limb 0 (P >= B^c, and P mod B^le = P - B^c) or in an all-ones
+    // limb (P < B^c, e = -P mod B^le), so the low le limbs of P suffice.  Any
+    // other top limb means a far estimate: the whole product below decides.
+    wg_mul(bf.T, v, k1, bf.W, lw, smem, le);
+    // every wave reads the same limb after the multiply's closing barrier
+    const uint32_t top = __builtin_amdgcn_readfirstlane(bf.T[le - 1]);
+    if (top == 0u) {
+      neg = true;
+      wg_copy(bf.E, bf.T, le);
+      have_e = true;
+    } else if (top == 0xffffffffu) {
+      neg = false;
+      auto X = [&](int) -> uint32_t { return 0u; };
+      auto Y = [&](int j) -> uint32_t { return bf.T[j]; };
+      wg_addsub<16, true>(bf.E, le, X, Y, 0u, sh->scan);
+      have_e = true;
     }
-  } else {
-    // e = -(P - B^c)
-    neg = true;
-    wg_arith1<true>(bf.T + c, lp - c, bf.T + c, lp - c, 1u, sh);
-    wg_shr_copy(bf.E, le, bf.T, lp, 0);
+  }
+  if (!have_e) {
+    wg_mul(bf.T, v, k1, bf.W, lw, smem, -1);
+    // sign: P >= B^c  <=>  some limb at index >= c is nonzero
+    const int pp = wg_prec(bf.T, lp, sh);
+    if (pp <= c) {
+      // e = B^c - P (P < B^c): the low c limbs of 0 - P; it is < few v
+      neg = false;
+      auto X = [&](int) -> uint32_t { return 0u; };
+      auto Y = [&](int j) -> uint32_t { return j < lp ? bf.T[j] : 0u; };
+      wg_addsub<16, true>(bf.T, min(c, lp), X, Y, 0u, sh->scan);  // in place
+      // limbs [min(c,lp), c) of 0 - P are all ones only if P == 0, which w >= 1 rules out
+      wg_shr_copy(bf.E, le, bf.T, min(c, lp), 0);
+      if (c > lp) {
+        // B^c - P with P < B^lp <= B^(c-1): e would be >= B^(c-1) -- far from w
+        // exact; keep it exact anyway by filling the all-ones limbs
+        for (int i = threadIdx.x; i < le; i += blockDim.x)
+          if (i >= lp && i < c) bf.E[i] = 0xffffffffu;
+        __syncthreads();
+      }
+    } else {
+      // e = -(P - B^c)
+      neg = true;
+      wg_arith1<true>(bf.T + c, lp - c, bf.T + c, lp - c, 1u, sh);
+      wg_shr_copy(bf.E, le, bf.T, lp, 0);
+    }
   }
   int adj = 0;
   // while e < 0: w -= 1, e += v   (a correct estimate needs at most a few
@@ -299,13 +323,17 @@ __device__ inline int shifted_inverse(const uint32_t* v, int k1, int h, Bufs& bf
       for (int i = threadIdx.x; i < lw; i += blockDim.x) bf.U2[i + m] = bf.W[i];
       __syncthreads();
     } else {
-      wg_mul(bf.T, bf.W, lw, bf.E, le, smem);
-      const int ly = lw + le;
-      // w' = w B^m + floor(Y / B^(c - m))
+      // only floor(w e / B^(c-m)) is needed: the low sd limbs of e add less
+      // than w B^sd <= B^(c-m-1) to w e, which moves that floor by at most
+      // one unit (the next fix-up absorbs it)
+      const int sd = max(0, min(le - 1, c - m - 1 - lw));
+      wg_mul(bf.T, bf.W, lw, bf.E + sd, le - sd, smem, -1);
+      const int ly = lw + le - sd;
+      // w' = w B^m + floor(Y / B^(c - m)), Y = w (e >> sd limbs)
       lnew = lw + m + 1;
       auto X = [&](int j) -> uint32_t { return (j >= m && j - m < lw) ? bf.W[j - m] : 0u; };
       auto Y = [&](int j) -> uint32_t {
-        const int s2 = j + c - m;
+        const int s2 = j + c - m - sd;
         return s2 < ly ? bf.T[s2] : 0u;
       };
       wg_addsub<16, false>(bf.U2, lnew, X, Y, 0u, sh->scan);
@@ -371,24 +399,30 @@ __device__ inline int wg_divmod(uint32_t* q, int nq, uint32_t* r, int nr, const 
     wg_shr_copy(q, nq, bf.W, lw, 0);
     return sh->failed ? BIGINT_DIV_FAILED : BIGINT_DIV_OK;
   }
-  // q = floor(u w / B^h)
-  wg_mul(bf.T, u, h, bf.W, lw, smem);
-  const int lz = h + lw;
-  const int lq = max(lz - h, 1);
-  wg_shr_copy(bf.U2, lq + 1, bf.T, lz, h);
-  // r = u - q v
+  // q = floor(u w / B^h), from the top limbs of u only: the low su limbs add
+  // less than B^(su+lw) <= B^(h-1) to u w, so q comes out exact or one low
+  // (and floor(u w / B^h) itself is floor(u / v) or one below)
+  const int su = max(0, h - 1 - lw);
+  wg_mul(bf.T, u + su, h - su, bf.W, lw, smem, -1);
+  const int lz = h - su + lw;
+  const int lq = max(lz - (h - su), 1);
+  wg_shr_copy(bf.U2, lq + 2, bf.T, lz, h - su);
+  // r = u - q v, which lies in [0, 3v) and so fits k1 + 2 limbs: only
+  // q v mod B^(k1+2) is needed
   const int lq2 = max(wg_prec(bf.U2, lq + 1, sh), 1);
-  wg_mul(bf.T, bf.U2, lq2, v, k1, smem);
-  const int lqv = lq2 + k1;
-  wg_arith<true>(bf.E, k1 + 2, u, h, bf.T, lqv, sh);   // fits: 0 <= r < 2v
-  // one correction: r >= v  ->  q += 1, r -= v
-  if (wg_cmp(bf.E, k1 + 2, v, k1, k1 + 2, sh) >= 0) {
-    wg_arith<true>(bf.E, k1 + 2, bf.E, k1 + 2, v, k1, sh);
-    wg_arith1<false>(bf.U2, lq2 + 1, bf.U2, lq2, 1u, sh);
+  const int lr = k1 + 2;
+  wg_mul(bf.T, bf.U2, lq2, v, k1, smem, lr);
+  wg_arith<true>(bf.E, lr, u, h, bf.T, min(lr, lq2 + k1), sh);
+  // corrections: while r >= v, q += 1 and r -= v (at most twice)
+  for (int rounds = 0; rounds < 4; ++rounds) {
+    if (wg_cmp(bf.E, lr, v, k1, lr, sh) < 0) break;
+    wg_arith<true>(bf.E, lr, bf.E, lr, v, k1, sh);
+    wg_arith1<false>(bf.U2, lq2 + 1, bf.U2, lq2 + 1, 1u, sh);
     if (adjust) *adjust += 1;
+    if (rounds == 3 && threadIdx.x == 0) sh->failed = 1u;
   }
   wg_shr_copy(q, nq, bf.U2, lq2 + 1, 0);
-  wg_shr_copy(r, nr, bf.E, k1 + 2, 0);
+  wg_shr_copy(r, nr, bf.E, lr, 0);
   return sh->failed ? BIGINT_DIV_FAILED : BIGINT_DIV_OK;
 }
 

@@ -87,8 +87,10 @@ struct Geo {
   int NBa, NBb;  // 8-bit digits: 256-digit blocks of each operand
 };
 
+// nout < na + nb asks for the product mod B^nout only: the strips past limb
+// nout are not computed (carries only move up, so the low limbs are exact).
 template <int DW>
-__host__ __device__ inline Geo make_geo(int na, int nb) {
+__host__ __device__ inline Geo make_geo(int na, int nb, int nout = -1) {
   Geo g;
   g.na = na; g.nb = nb;
   g.Na = ndigits_w<DW>(na); g.Nb = ndigits_w<DW>(nb);
@@ -99,7 +101,8 @@ __host__ __device__ inline Geo make_geo(int na, int nb) {
   g.SB = ((kPadB + g.Nb + kPadBt) + 15) & ~15;
   const int K = g.Na + g.Nb - 1;
   g.W = (K + kStrip - 1) / kStrip;
-  g.nout = na + nb;
+  g.nout = (nout < 0 || nout > na + nb) ? na + nb : nout;
+  g.W = min(g.W, (g.nout + strip_limbs<DW>() - 1) / strip_limbs<DW>());
   return g;
 }
 
@@ -601,15 +604,16 @@ __device__ __forceinline__ void run_band(int band, const Lds& s, const Geo& g, u
     }
 }
 
-// out[0 .. na+nb) = a * b for one instance (whole work-group), digits of DW
-// bits.  With coef != nullptr (7-bit digits only) the raw coefficients c_k
+// out[0 .. nout) = a * b mod B^nout for one instance (whole work-group),
+// digits of DW bits; nout < 0 means the whole na+nb limbs.  With coef !=
+// nullptr (7-bit digits only, whole product) the raw coefficients c_k
 // (k < Na+Nb-1) are written instead.
 template <int DW, int P>
 __device__ __forceinline__ void wg_mul_mfma(uint32_t* out, int32_t* coef, const uint32_t* __restrict__ a, int na,
-                            const uint32_t* __restrict__ b, int nb, char* smem) {
+                            const uint32_t* __restrict__ b, int nb, char* smem, int nout = -1) {
   static_assert(DW == 7 || DW == 8, "digit width");
   constexpr int kStripLimbs = strip_limbs<DW>();
-  const Geo g = make_geo<DW>(na, nb);
+  const Geo g = make_geo<DW>(na, nb, coef ? -1 : nout);
   const Lds s = carve(smem, g, P);
   const int NB = (g.W + P - 1) / P;
 
