@@ -47,12 +47,14 @@ def lib():
         L.orc_sub.argtypes = [_u32p, _u32p, _u32p, _u32p, _i64]
         L.orc_mul.argtypes = [_u32p, _u32p, _i64, _u32p, _i64]
         L.orc_mullo.argtypes = [_u32p, _u32p, _u32p, _i64]
+        L.orc_add6.argtypes = [_u32p, _u32p, _u32p, _u32p, _i64]
+        L.orc_poly.argtypes = [_u32p, _u32p, _u32p, _i64]
         L.orc_divmod.argtypes = [_u32p, _u32p, _u32p, _i64, _u32p, _i64]
         L.orc_shinv.argtypes = [_u32p, _u32p, _i64, _i64]
         L.orc_digits.argtypes = [_u8p, _u32p, _i64, ctypes.c_int, _i64]
         L.orc_conv.argtypes = [_i64p, _u8p, _i64, _u8p, _i64]
         L.orc_recombine.argtypes = [_u32p, _i64, _i64p, _i64, ctypes.c_int]
-        for f in ("orc_add", "orc_sub", "orc_mul", "orc_mullo", "orc_divmod",
+        for f in ("orc_add", "orc_sub", "orc_mul", "orc_mullo", "orc_add6", "orc_poly", "orc_divmod",
                   "orc_shinv", "orc_digits", "orc_conv", "orc_recombine"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
@@ -98,6 +100,22 @@ def mullo1(a, b):
     assert a.size == b.size
     out = np.zeros(a.size, np.uint32)
     lib().orc_mullo(_p(out, _u32p), _p(a, _u32p), _p(b, _u32p), a.size)
+    return out
+
+
+def add6_1(a, b):
+    a, b = _row(a), _row(b)
+    out = np.zeros_like(a)
+    c = np.zeros(1, np.uint32)
+    lib().orc_add6(_p(out, _u32p), _p(c, _u32p), _p(a, _u32p), _p(b, _u32p), a.size)
+    return out, int(c[0])
+
+
+def poly1(a, b):
+    a, b = _row(a), _row(b)
+    assert a.size == b.size
+    out = np.zeros_like(a)
+    lib().orc_poly(_p(out, _u32p), _p(a, _u32p), _p(b, _u32p), a.size)
     return out
 
 

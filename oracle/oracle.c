@@ -20,6 +20,9 @@
  *   sub     r = (a-b) mod 2^(32n), borrow = [a < b]
  *   mul     the full product (na+nb limbs); row-by-row schoolbook
  *   mullo   (a*b) mod 2^(32m)
+ *   add6    six additions in sequence, ((((((a+b)+a)+b)+a)+b)+a) mod 2^(32n),
+ *           and how many of them overflowed
+ *   poly    ((a*a + b) * (b*b + b) + a*b) mod 2^(32n)
  *   divmod  q = floor(u/v), r = u - q v (Knuth, TAOCP vol. 2, 4.3.1, Alg. D)
  *   shinv   floor(B^h / v) with B = 2^32 (divmod of B^h by v)
  *   digits  the base-2^w digits of a (bit extraction)
@@ -150,6 +153,48 @@ int orc_mullo(uint32_t* out, const uint32_t* a, const uint32_t* b, int64_t m)
     orc_mul(full, a, m, b, m);
     memcpy(out, full, (size_t)m * sizeof(uint32_t));
     free(full);
+    return 0;
+}
+
+/* ---- fused workloads of the evaluation (Section 6) ----------------------- */
+
+/* The 6-Add benchmark: six dependent additions per instance (the paper does
+ * not print the expression; this one alternates the two inputs):
+ * out = ((((((a+b)+a)+b)+a)+b)+a) mod 2^(32n), *overflow = the number of the
+ * six additions that carried out of the top limb. */
+int orc_add6(uint32_t* out, uint32_t* overflow, const uint32_t* a,
+             const uint32_t* b, int64_t n)
+{
+    uint32_t* t = (uint32_t*)calloc((size_t)n, sizeof(uint32_t));
+    uint32_t total = 0, c = 0;
+    orc_add(t, &c, a, b, n);
+    total += c;
+    for (int step = 1; step < 6; ++step) {
+        orc_add(t, &c, t, (step % 2) ? a : b, n);
+        total += c;
+    }
+    memcpy(out, t, (size_t)n * sizeof(uint32_t));
+    if (overflow) *overflow = total;
+    free(t);
+    return 0;
+}
+
+/* The Poly benchmark in fixed precision (products and sums mod 2^(32n), as
+ * the paper's multiplication keeps the operand width):
+ * out = ((a*a + b) * (b*b + b) + a*b) mod 2^(32n). */
+int orc_poly(uint32_t* out, const uint32_t* a, const uint32_t* b, int64_t n)
+{
+    uint32_t* x = (uint32_t*)calloc((size_t)n, sizeof(uint32_t));
+    uint32_t* y = (uint32_t*)calloc((size_t)n, sizeof(uint32_t));
+    uint32_t* z = (uint32_t*)calloc((size_t)n, sizeof(uint32_t));
+    orc_mullo(x, a, a, n);
+    orc_add(x, NULL, x, b, n);          /* a*a + b */
+    orc_mullo(y, b, b, n);
+    orc_add(y, NULL, y, b, n);          /* b*b + b */
+    orc_mullo(z, x, y, n);              /* (a*a + b)(b*b + b) */
+    orc_mullo(x, a, b, n);
+    orc_add(out, NULL, z, x, n);        /* + a*b */
+    free(x); free(y); free(z);
     return 0;
 }
 

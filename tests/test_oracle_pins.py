@@ -349,3 +349,60 @@ def test_conv_all_ones_bound(orc):
     c = orc.conv1(d, d)
     assert int(c.max()) <= d.size * 127 * 127 < 2**31
     assert to_int(orc.recombine1(c, 2 * n)) == ((1 << (32 * n)) - 1) ** 2
+
+
+# ---- fused workloads of the evaluation: 6-Add and Poly (Section 6) ----------------
+
+@pytest.mark.parametrize("n", [1, 2, 3, 7, 64, 1000])
+def test_add6_vs_python(orc, n):
+    # six additions alternating the inputs: 4a + 3b, reduced mod B^n, with the
+    # number of additions that carried out of the top limb
+    g = np.random.default_rng(700 + n)
+    M = 1 << (32 * n)
+    for _ in range(6):
+        a = g.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)
+        b = g.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)
+        r, ovf = orc.add6_1(a, b)
+        ia, ib = to_int(a), to_int(b)
+        assert to_int(r) == (4 * ia + 3 * ib) % M
+        # each partial sum is taken mod M, so the count is the floor of the
+        # exact result: 4a + 3b = r + ovf * M
+        assert ovf == (4 * ia + 3 * ib) // M
+
+
+def test_add6_closed_forms(orc):
+    n = 5
+    ones = np.full(n, 0xFFFFFFFF, np.uint32)
+    r, ovf = orc.add6_1(ones, ones)           # 7 (B^n - 1) = 6 B^n + (B^n - 7)
+    assert to_int(r) == (1 << (32 * n)) - 7 and ovf == 6
+    z = np.zeros(n, np.uint32)
+    r, ovf = orc.add6_1(z, z)
+    assert not r.any() and ovf == 0
+    one = from_int(1, n)
+    r, ovf = orc.add6_1(one, z)               # 4
+    assert to_int(r) == 4 and ovf == 0
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 33, 300])
+def test_poly_vs_python(orc, n):
+    g = np.random.default_rng(900 + n)
+    M = 1 << (32 * n)
+    for _ in range(4):
+        a = g.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)
+        b = g.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)
+        ia, ib = to_int(a), to_int(b)
+        want = ((ia * ia + ib) * (ib * ib + ib) + ia * ib) % M
+        assert to_int(orc.poly1(a, b)) == want
+
+
+def test_poly_special_values(orc):
+    n = 4
+    M = 1 << (32 * n)
+    one, z = from_int(1, n), np.zeros(n, np.uint32)
+    assert to_int(orc.poly1(one, one)) == 5                  # (1+1)(1+1) + 1
+    b = from_int(123456789123456789, n)
+    ib = to_int(b)
+    assert to_int(orc.poly1(z, b)) == (ib * (ib * ib + ib)) % M   # b^3 + b^2
+    assert to_int(orc.poly1(b, z)) == 0                      # (a^2)(0) + 0
+    m1 = from_int(M - 1, n)                                  # a = -1 mod M: a*a = 1, a*b = -b
+    assert to_int(orc.poly1(m1, b)) == ((1 + ib) * (ib * ib + ib) - ib) % M
