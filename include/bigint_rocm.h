@@ -127,6 +127,33 @@ int bigint_sub(uint32_t* out, uint32_t* borrow_out, const uint32_t* a,
 int bigint_mul(uint32_t* out, const uint32_t* a, int64_t na, const uint32_t* b,
                int64_t nb, int64_t batch, int algo, void* stream);
 
+/* ---- fixed-precision product and the evaluation's fused workloads (Section 6) ---
+ * bigint_mullo: out[i] = a[i] * b[i] mod B^n (B = 2^32), the paper's
+ *   multiplication, whose quadratic formula keeps only digits k < n
+ *   (Section 5.2).  MFMA-split, computing only the strips below limb n.
+ *   a, b, out: batch*n limbs; 1 <= n <= BIGINT_MFMA_MAX_LIMBS; out must not
+ *   overlap a or b.
+ * bigint_add6: the 6-Add benchmark (Table tab-add): six dependent additions
+ *   out[i] = ((((((a+b)+a)+b)+a)+b)+a) mod B^n = (4a + 3b) mod B^n with the
+ *   operands and partial sums held in registers, so the batch moves the
+ *   bytes of one addition.  overflow[i] (nullable) = how many of the six
+ *   carried out of limb n-1, i.e. floor((4a + 3b) / B^n).  The paper does
+ *   not print its 6-Add expression; this one alternates the two inputs.
+ *   1 <= n <= 16384; out may equal a or b exactly (in place), other overlap
+ *   is BIGINT_EINVAL.
+ * bigint_poly: the Poly benchmark (Table tab-mul) in the paper's fixed
+ *   precision: out[i] = ((a a + b)(b b + b) + a b) mod B^n, four products
+ *   mod B^n and three additions per instance in one persistent launch; the
+ *   call allocates 2n limbs of workspace per work-group on `stream`
+ *   (stream-ordered) and frees it the same way.  1 <= n <=
+ *   BIGINT_MFMA_MAX_LIMBS; out must not overlap a or b. */
+int bigint_mullo(uint32_t* out, const uint32_t* a, const uint32_t* b, int64_t n,
+                 int64_t batch, void* stream);
+int bigint_add6(uint32_t* out, uint32_t* overflow, const uint32_t* a,
+                const uint32_t* b, int64_t n, int64_t batch, void* stream);
+int bigint_poly(uint32_t* out, const uint32_t* a, const uint32_t* b, int64_t n,
+                int64_t batch, void* stream);
+
 /* ---- division (Section 5.3) ------------------------------------------------------
  * q[i] = floor(u[i] / v[i]), r[i] = u[i] - q[i]*v[i], 0 <= r[i] < v[i].
  * The quotient comes from the whole shifted inverse w = floor(B^h / v)

@@ -21,6 +21,7 @@ import os
 __all__ = [
     "lib", "add", "sub", "mul", "divmod", "digits7", "conv7", "shinv",
     "MulPlan", "DivPlan", "autotune", "autotune_load", "set_mfma_config", "mfma_config", "BigIntError",
+    "mullo", "add6", "poly",
     "MUL_AUTO", "MUL_PLAIN", "MUL_MFMA",
 ]
 
@@ -84,6 +85,9 @@ def lib() -> ctypes.CDLL:
             "bigint_shinv": ([_vp, _vp, _i64, _i64, _i64, _vp], _int),
             "bigint_set_mfma_config": ([_int, _int, _int], _int),
             "bigint_mfma_config": ([_i64, _i64, _pint, _pint, _pint], _int),
+            "bigint_mullo": ([_vp, _vp, _vp, _i64, _i64, _vp], _int),
+            "bigint_add6": ([_vp, _vp, _vp, _vp, _i64, _i64, _vp], _int),
+            "bigint_poly": ([_vp, _vp, _vp, _i64, _i64, _vp], _int),
             "bigint_diag_mfma_rate": ([_vp, _i64, _i64, _vp], _int),
         }
         for name, (args, res) in sig.items():
@@ -216,6 +220,46 @@ def shinv(v, h: int):
 
 def set_mfma_config(strips_per_band: int = 0, waves: int = 0, digit_bits: int = 0):
     _check(lib().bigint_set_mfma_config(strips_per_band, waves, digit_bits), "bigint_set_mfma_config")
+
+
+def mullo(a, b):
+    """a * b mod B^n row by row ([batch, n] x [batch, n] -> [batch, n])."""
+    torch = _torch()
+    a, b = _limbs(a, "a"), _limbs(b, "b")
+    ba, n = _rows(a)
+    bb, nb = _rows(b)
+    if ba != bb or n != nb:
+        raise ValueError("shape mismatch")
+    out = torch.empty((ba, n), dtype=a.dtype, device=a.device)
+    _check(lib().bigint_mullo(_p(out), _p(a), _p(b), n, ba, _stream()), "bigint_mullo")
+    return out if a.dim() == 2 else out.view(-1)
+
+
+def add6(a, b, out=None):
+    """The 6-Add workload: (4a + 3b) mod B^n by six dependent additions, and
+    the count of additions that overflowed (uint32 per row)."""
+    torch = _torch()
+    a, b = _limbs(a, "a"), _limbs(b, "b")
+    ba, n = _rows(a)
+    if b.shape != a.shape:
+        raise ValueError("shape mismatch")
+    if out is None:
+        out = torch.empty_like(a)
+    ovf = torch.empty(ba, dtype=a.dtype, device=a.device)
+    _check(lib().bigint_add6(_p(out), _p(ovf), _p(a), _p(b), n, ba, _stream()), "bigint_add6")
+    return out, ovf
+
+
+def poly(a, b):
+    """The Poly workload: ((a a + b)(b b + b) + a b) mod B^n row by row."""
+    torch = _torch()
+    a, b = _limbs(a, "a"), _limbs(b, "b")
+    ba, n = _rows(a)
+    if b.shape != a.shape:
+        raise ValueError("shape mismatch")
+    out = torch.empty_like(a)
+    _check(lib().bigint_poly(_p(out), _p(a), _p(b), n, ba, _stream()), "bigint_poly")
+    return out
 
 
 def mfma_config(na: int, nb: int):

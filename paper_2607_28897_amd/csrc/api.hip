@@ -174,6 +174,58 @@ int bigint_mul(uint32_t* out, const uint32_t* a, int64_t na, const uint32_t* b, 
   return launch_mul_plain(out, a, na, b, nb, batch, (hipStream_t)stream);
 }
 
+int bigint_mullo(uint32_t* out, const uint32_t* a, const uint32_t* b, int64_t n, int64_t batch,
+                 void* stream) {
+  if (!out || !a || !b || n <= 0 || batch < 0) return BIGINT_EINVAL;
+  if (batch > 0x7fffffff || n > BIGINT_MFMA_MAX_LIMBS) return BIGINT_EUNSUPPORTED;
+  const size_t bytes = (size_t)n * batch * 4;
+  if (overlap(out, bytes, a, bytes) || overlap(out, bytes, b, bytes)) return BIGINT_EINVAL;
+  const MfmaCfg cfg = current_mfma_cfg((int)n, (int)n);
+  if (!mfma_fits(n, n, cfg)) return BIGINT_EUNSUPPORTED;
+  if (batch == 0) return BIGINT_OK;
+  return launch_mul_mfma(out, nullptr, a, n, b, n, batch, cfg, (hipStream_t)stream, (int)n);
+}
+
+int bigint_add6(uint32_t* out, uint32_t* overflow, const uint32_t* a, const uint32_t* b,
+                int64_t n, int64_t batch, void* stream) {
+  if (!out || !a || !b || n <= 0 || batch < 0) return BIGINT_EINVAL;
+  if (n > 16384 || batch > 0x7fffffff) return BIGINT_EUNSUPPORTED;
+  const size_t bytes = (size_t)n * batch * 4;
+  if (out != a && overlap(out, bytes, a, bytes)) return BIGINT_EINVAL;
+  if (out != b && overlap(out, bytes, b, bytes)) return BIGINT_EINVAL;
+  if (overflow) {
+    const size_t cb = (size_t)batch * 4;
+    if (overlap(overflow, cb, out, bytes) || overlap(overflow, cb, a, bytes) ||
+        overlap(overflow, cb, b, bytes))
+      return BIGINT_EINVAL;
+  }
+  if (batch == 0) return BIGINT_OK;
+  return launch_add6(out, overflow, a, b, n, batch, (hipStream_t)stream);
+}
+
+int bigint_poly(uint32_t* out, const uint32_t* a, const uint32_t* b, int64_t n, int64_t batch,
+                void* stream) {
+  if (!out || !a || !b || n <= 0 || batch < 0) return BIGINT_EINVAL;
+  if (batch > 0x7fffffff || n > BIGINT_MFMA_MAX_LIMBS) return BIGINT_EUNSUPPORTED;
+  const size_t bytes = (size_t)n * batch * 4;
+  if (overlap(out, bytes, a, bytes) || overlap(out, bytes, b, bytes)) return BIGINT_EINVAL;
+  MfmaCfg cfg = default_mfma_cfg((int)n, (int)n);
+  cfg.dw = 8;
+  if (poly_lds((int)n, cfg) > 163840) return BIGINT_EUNSUPPORTED;
+  if (batch == 0) return BIGINT_OK;
+  // a persistent grid of resident work-groups, each owning 2n limbs of workspace
+  const int grid = poly_grid((int)n, batch, cfg);
+  hipStream_t s = (hipStream_t)stream;
+  void* ws = nullptr;
+  hipError_t e = hipMallocAsync(&ws, (size_t)grid * 2 * n * 4, s);
+  if (e != hipSuccess) { set_hip_error(e); return BIGINT_ENOMEM; }
+  const int rc = launch_poly(out, a, b, n, batch, (uint32_t*)ws, grid, cfg, s);
+  e = hipFreeAsync(ws, s);
+  if (rc != BIGINT_OK) return rc;
+  if (e != hipSuccess) { set_hip_error(e); return BIGINT_EHIP; }
+  return BIGINT_OK;
+}
+
 int bigint_digits7(uint8_t* out, const uint32_t* a, int64_t n, int64_t D, int64_t batch,
                    void* stream) {
   if (!out || !a || n <= 0 || D <= 0 || batch < 0) return BIGINT_EINVAL;

@@ -26,7 +26,14 @@ int launch_addsub(bool sub, uint32_t* out, uint32_t* cout, const uint32_t* a, co
 int launch_mul_plain(uint32_t* out, const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb,
                      int64_t batch, hipStream_t s);
 int launch_mul_mfma(uint32_t* out, int32_t* coef, const uint32_t* a, int64_t na,
-                    const uint32_t* b, int64_t nb, int64_t batch, MfmaCfg cfg, hipStream_t s);
+                    const uint32_t* b, int64_t nb, int64_t batch, MfmaCfg cfg, hipStream_t s,
+                    int nout = -1);
+int launch_add6(uint32_t* out, uint32_t* ovf, const uint32_t* a, const uint32_t* b, int64_t n,
+                int64_t batch, hipStream_t s);
+size_t poly_lds(int n, MfmaCfg cfg);
+int poly_grid(int n, int64_t batch, MfmaCfg cfg);
+int launch_poly(uint32_t* out, const uint32_t* a, const uint32_t* b, int64_t n, int64_t batch,
+                uint32_t* ws, int grid, MfmaCfg cfg, hipStream_t s);
 int launch_digits7(uint8_t* out, const uint32_t* a, int64_t n, int64_t D, int64_t batch,
                    hipStream_t s);
 

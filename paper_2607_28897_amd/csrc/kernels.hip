@@ -148,15 +148,16 @@ int launch_mul_plain(uint32_t* out, const uint32_t* a, int64_t na, const uint32_
 // ============================================================================
 // MFMA-split multiply: one work-group per instance
 // ============================================================================
+// out instance i = a_i * b_i mod B^nout (nout = na + nb: the whole product)
 template <int DW, int P>
 __global__ __launch_bounds__(512) void k_mul_mfma(uint32_t* out, int32_t* coef, const uint32_t* a,
-                                                  int na, const uint32_t* b, int nb) {
+                                                  int na, const uint32_t* b, int nb, int nout) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
   const int64_t inst = blockIdx.x;
   const int K = mfma::ndigits(na) + mfma::ndigits(nb) - 1;
-  mfma::wg_mul_mfma<DW, P>(out ? out + inst * (int64_t)(na + nb) : nullptr,
+  mfma::wg_mul_mfma<DW, P>(out ? out + inst * (int64_t)nout : nullptr,
                            coef ? coef + inst * (int64_t)K : nullptr, a + inst * (int64_t)na, na,
-                           b + inst * (int64_t)nb, nb, smem);
+                           b + inst * (int64_t)nb, nb, smem, nout);
 }
 
 size_t mfma_lds(int na, int nb, MfmaCfg cfg) {
@@ -166,36 +167,190 @@ size_t mfma_lds(int na, int nb, MfmaCfg cfg) {
 
 template <int DW, int P>
 static int launch_mfma_p(uint32_t* out, int32_t* coef, const uint32_t* a, int64_t na,
-                         const uint32_t* b, int64_t nb, int64_t batch, int waves, hipStream_t s) {
+                         const uint32_t* b, int64_t nb, int64_t batch, int waves, int nout,
+                         hipStream_t s) {
   const size_t lds = mfma::lds_bytes<DW>((int)na, (int)nb, waves, P);
   if (lds > 163840) return BIGINT_EUNSUPPORTED;
   BI_HIP(hipFuncSetAttribute((const void*)k_mul_mfma<DW, P>,
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   hipLaunchKernelGGL((k_mul_mfma<DW, P>), dim3((unsigned)batch), dim3(64 * waves), lds, s, out,
-                     coef, a, (int)na, b, (int)nb);
+                     coef, a, (int)na, b, (int)nb, nout);
   BI_LAUNCH_CHECK();
   return BIGINT_OK;
 }
 
 template <int DW>
 static int launch_mfma_dw(uint32_t* out, int32_t* coef, const uint32_t* a, int64_t na,
-                          const uint32_t* b, int64_t nb, int64_t batch, MfmaCfg cfg,
+                          const uint32_t* b, int64_t nb, int64_t batch, MfmaCfg cfg, int nout,
                           hipStream_t s) {
   switch (cfg.P) {
-    case 4: return launch_mfma_p<DW, 4>(out, coef, a, na, b, nb, batch, cfg.waves, s);
-    case 8: return launch_mfma_p<DW, 8>(out, coef, a, na, b, nb, batch, cfg.waves, s);
-    case 16: return launch_mfma_p<DW, 16>(out, coef, a, na, b, nb, batch, cfg.waves, s);
+    case 4: return launch_mfma_p<DW, 4>(out, coef, a, na, b, nb, batch, cfg.waves, nout, s);
+    case 8: return launch_mfma_p<DW, 8>(out, coef, a, na, b, nb, batch, cfg.waves, nout, s);
+    case 16: return launch_mfma_p<DW, 16>(out, coef, a, na, b, nb, batch, cfg.waves, nout, s);
     default: return BIGINT_EINVAL;
   }
 }
 
-// coef != nullptr (raw coefficients) is served with 7-bit digits only
+// coef != nullptr (raw coefficients) is served with 7-bit digits only.
+// nout < 0: the whole na+nb limbs; else the product mod B^nout per instance.
 int launch_mul_mfma(uint32_t* out, int32_t* coef, const uint32_t* a, int64_t na,
-                    const uint32_t* b, int64_t nb, int64_t batch, MfmaCfg cfg, hipStream_t s) {
+                    const uint32_t* b, int64_t nb, int64_t batch, MfmaCfg cfg, hipStream_t s,
+                    int nout) {
+  if (nout < 0 || nout > na + nb) nout = (int)(na + nb);
   if (cfg.dw == 8 && coef == nullptr)
-    return launch_mfma_dw<8>(out, nullptr, a, na, b, nb, batch, cfg, s);
+    return launch_mfma_dw<8>(out, nullptr, a, na, b, nb, batch, cfg, nout, s);
   if (cfg.dw != 7 && cfg.dw != 8) return BIGINT_EINVAL;
-  return launch_mfma_dw<7>(out, coef, a, na, b, nb, batch, cfg, s);
+  return launch_mfma_dw<7>(out, coef, a, na, b, nb, batch, cfg, coef ? (int)(na + nb) : nout, s);
+}
+
+// ============================================================================
+// fused workloads of the evaluation: 6-Add and Poly
+// ============================================================================
+// 6-Add: ((((((a+b)+a)+b)+a)+b)+a) mod B^n with the operands and the running
+// sum in registers: one HBM pass (read a, b; write the result), six
+// work-group carry scans.  ovf[i] = how many of the six additions carried out.
+template <int Q, bool VEC>
+__global__ __launch_bounds__(1024) void k_add6(uint32_t* out, uint32_t* ovf, const uint32_t* a,
+                                               const uint32_t* b, int n) {
+  __shared__ uint32_t scratch[32];
+  const int64_t inst = blockIdx.x;
+  const uint32_t* pa = a + inst * n;
+  const uint32_t* pb = b + inst * n;
+  uint32_t* po = out + inst * n;
+  const int j0 = threadIdx.x * Q;
+  const int valid = min(Q, max(0, n - j0));
+  uint32_t av[Q], bv[Q], x[Q];
+  if (VEC && valid == Q) {
+#pragma unroll
+    for (int i = 0; i < Q; i += 4) {
+      const uint4 va = *reinterpret_cast<const uint4*>(pa + j0 + i);
+      const uint4 vb = *reinterpret_cast<const uint4*>(pb + j0 + i);
+      av[i] = va.x; av[i + 1] = va.y; av[i + 2] = va.z; av[i + 3] = va.w;
+      bv[i] = vb.x; bv[i + 1] = vb.y; bv[i + 2] = vb.z; bv[i + 3] = vb.w;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const int jj = min(j0 + i, n - 1);
+      av[i] = i < valid ? pa[jj] : 0u;
+      bv[i] = i < valid ? pb[jj] : 0u;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < Q; ++i) x[i] = av[i];
+  uint32_t total = 0;
+#pragma unroll
+  for (int step = 0; step < 6; ++step) {
+    LimbRun<Q, false> run;
+    run.build(x, (step & 1) ? av : bv, valid);
+    uint32_t cout;
+    const uint32_t c = wg_carry_scan(run.G, run.P, 0u, scratch, &cout);
+    run.apply(c);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) x[i] = run.s[i];
+    total += cout;
+  }
+  if (VEC && valid == Q) {
+#pragma unroll
+    for (int i = 0; i < Q; i += 4)
+      *reinterpret_cast<uint4*>(po + j0 + i) = make_uint4(x[i], x[i + 1], x[i + 2], x[i + 3]);
+  } else {
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+      if (i < valid) po[j0 + i] = x[i];
+  }
+  if (ovf && threadIdx.x == 0) ovf[inst] = total;
+}
+
+template <int Q>
+static int launch_add6_q(uint32_t* out, uint32_t* ovf, const uint32_t* a, const uint32_t* b,
+                         int64_t n, int64_t batch, hipStream_t s) {
+  const int T = (int)((cdiv(n, Q) + 63) / 64 * 64);
+  const bool vec = (n % 4 == 0) && ((uintptr_t)a % 16 == 0) && ((uintptr_t)b % 16 == 0) &&
+                   ((uintptr_t)out % 16 == 0);
+  if (vec)
+    hipLaunchKernelGGL((k_add6<Q, true>), dim3((unsigned)batch), dim3(T), 0, s, out, ovf, a, b,
+                       (int)n);
+  else
+    hipLaunchKernelGGL((k_add6<Q, false>), dim3((unsigned)batch), dim3(T), 0, s, out, ovf, a, b,
+                       (int)n);
+  BI_LAUNCH_CHECK();
+  return BIGINT_OK;
+}
+
+int launch_add6(uint32_t* out, uint32_t* ovf, const uint32_t* a, const uint32_t* b, int64_t n,
+                int64_t batch, hipStream_t s) {
+  if (n <= 1024) return launch_add6_q<4>(out, ovf, a, b, n, batch, s);
+  if (n <= 2048) return launch_add6_q<8>(out, ovf, a, b, n, batch, s);
+  if (n <= 16384) return launch_add6_q<16>(out, ovf, a, b, n, batch, s);
+  return BIGINT_EUNSUPPORTED;
+}
+
+// Poly: ((a*a + b) * (b*b + b) + a*b) mod B^n.  A persistent grid walks the
+// instances; per instance the four products mod B^n run one after another on
+// the MFMA-split multiply (a single call site, so its code is emitted once)
+// with two n-limb temporaries in a global workspace, each followed by its
+// addition on the whole work-group.
+template <int P>
+__global__ __launch_bounds__(512) void k_poly(uint32_t* out, const uint32_t* a, const uint32_t* b,
+                                              int n, int64_t batch, uint32_t* ws) {
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  __shared__ uint32_t scratch[32];
+  uint32_t* t1 = ws + (int64_t)blockIdx.x * 2 * n;
+  uint32_t* t2 = t1 + n;
+  for (int64_t inst = blockIdx.x; inst < batch; inst += gridDim.x) {
+    const uint32_t* pa = a + inst * n;
+    const uint32_t* pb = b + inst * n;
+    uint32_t* po = out + inst * n;
+#pragma unroll 1
+    for (int op = 0; op < 4; ++op) {
+      // products: t1 = a a, t2 = b b, out = t1 t2, t1 = a b
+      const uint32_t* x = op == 0 ? pa : (op == 1 ? pb : (op == 2 ? t1 : pa));
+      const uint32_t* y = op == 0 ? pa : (op == 1 ? pb : (op == 2 ? t2 : pb));
+      uint32_t* dst = op == 0 ? t1 : (op == 1 ? t2 : (op == 2 ? po : t1));
+      mfma::wg_mul_mfma<8, P>(dst, nullptr, x, n, y, n, smem, n);
+      if (op == 2) continue;
+      // sums: t1 += b, t2 += b, out += t1
+      uint32_t* acc = op == 3 ? po : dst;
+      const uint32_t* add = op == 3 ? t1 : pb;
+      auto X = [&](int j) -> uint32_t { return acc[j]; };
+      auto Y = [&](int j) -> uint32_t { return add[j]; };
+      wg_addsub<16, false>(acc, n, X, Y, 0u, scratch);
+    }
+  }
+}
+
+size_t poly_lds(int n, MfmaCfg cfg) { return mfma::lds_bytes<8>(n, n, cfg.waves, cfg.P) + 256; }
+
+static const void* poly_kernel(int P) {
+  return P == 4 ? (const void*)k_poly<4> : (P == 8 ? (const void*)k_poly<8> : (const void*)k_poly<16>);
+}
+
+// work-groups of the persistent Poly grid: as many as stay resident together
+int poly_grid(int n, int64_t batch, MfmaCfg cfg) {
+  int per_cu = 1;
+  const size_t lds = mfma::lds_bytes<8>(n, n, cfg.waves, cfg.P);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, poly_kernel(cfg.P), 64 * cfg.waves,
+                                                   lds) != hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(batch, (int64_t)num_cus() * per_cu));
+}
+
+int launch_poly(uint32_t* out, const uint32_t* a, const uint32_t* b, int64_t n, int64_t batch,
+                uint32_t* ws, int grid, MfmaCfg cfg, hipStream_t s) {
+  const size_t lds = mfma::lds_bytes<8>((int)n, (int)n, cfg.waves, cfg.P);
+  if (lds + 256 > 163840) return BIGINT_EUNSUPPORTED;
+  BI_HIP(hipFuncSetAttribute(poly_kernel(cfg.P), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)lds));
+  const dim3 gd(grid), bd(64 * cfg.waves);
+  switch (cfg.P) {
+    case 4: hipLaunchKernelGGL(k_poly<4>, gd, bd, lds, s, out, a, b, (int)n, batch, ws); break;
+    case 8: hipLaunchKernelGGL(k_poly<8>, gd, bd, lds, s, out, a, b, (int)n, batch, ws); break;
+    default: hipLaunchKernelGGL(k_poly<16>, gd, bd, lds, s, out, a, b, (int)n, batch, ws); break;
+  }
+  BI_LAUNCH_CHECK();
+  return BIGINT_OK;
 }
 
 // ============================================================================
