@@ -39,7 +39,8 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--cpu-seconds", type=float, default=15.0,
                    help="target CPU work (core-seconds) of the oracle sample")
-    p.add_argument("--mode", default="bench", choices=["bench", "copy", "mfma-peak", "ragged", "divmod"],
+    p.add_argument("--mode", default="bench",
+                   choices=["bench", "copy", "mfma-peak", "ragged", "divmod", "addsub", "poly"],
                    help="copy: a plain copy kernel of known size (counter calibration); "
                         "mfma-peak: register-only int8 MFMA rate probe; ragged / divmod: the "
                         "4096-product ragged batch and the 512-division batch (extra lines)")
@@ -121,6 +122,10 @@ def main():
         return ragged_mode(torch, bi, inputs, args)
     if args.mode == "divmod":
         return divmod_mode(torch, bi, inputs, args)
+    if args.mode == "addsub":
+        return addsub_mode(torch, bi, inputs, args)
+    if args.mode == "poly":
+        return poly_mode(torch, bi, args)
 
     cfg = inputs.pairs_2e19(args.batch)
     a_np, b_np, n = cfg["a"], cfg["b"], cfg["n"]
@@ -314,6 +319,71 @@ def divmod_mode(torch, bi, inputs, args):
                       "same_size_products_ms": round(mms, 4), "div_over_mul": round(ms / mms, 3)}))
     plan.close()
     mplan.close()
+
+
+def _rand_dev(torch, g, rows, n):
+    """rows x n random u32 limbs generated on the device (too large for host copies)."""
+    x = torch.randint(-2**31, 2**31, (rows, n), dtype=torch.int32, device="cuda", generator=g)
+    return x
+
+
+def addsub_mode(torch, bi, inputs, args):
+    """1-Add, 1-Sub and 6-Add in GB/s on the paper's addition datasets
+    (NumBits x NumInsts = 2^32, Table tab-add; bytes = 3 NumInsts NumBits / 8,
+    each input and the result once), and on the 2^17-bit configuration
+    (1024 pairs, half carry-adversarial)."""
+    g = torch.Generator(device="cuda")
+    g.manual_seed(1005)
+    res = {"mode": "addsub", "unit": "GB/s", "rows": []}
+    steps = max(3, args.steps // 5)
+    for bits in (2**15, 2**16, 2**17, 2**18):
+        n, insts = bits // 32, 2**32 // bits
+        a = _rand_dev(torch, g, insts, n)
+        b = _rand_dev(torch, g, insts, n)
+        out = torch.empty_like(a)
+        byts = 3 * insts * bits / 8
+        row = {"num_bits": bits, "num_insts": insts}
+        for name, fn in (("add", lambda: bi.add(a, b, out=out)), ("sub", lambda: bi.sub(a, b, out=out)),
+                         ("add6", lambda: bi.add6(a, b, out=out))):
+            total, _ = time_launches(fn, steps, args.warmup, torch)
+            row[name] = round(byts / (total / steps * 1e-3) / 1e9, 1)
+        res["rows"].append(row)
+        del a, b, out
+        torch.cuda.empty_cache()
+    c = inputs.pairs_2e17_mixed()
+    a = torch.from_numpy(c["a"].view(np.int32)).cuda()
+    b = torch.from_numpy(c["b"].view(np.int32)).cuda()
+    out = torch.empty_like(a)
+    byts = 3 * a.numel() * 4
+    cfg = {"workload": "1024 pairs of 2^17-bit integers, half carry-adversarial"}
+    for name, fn in (("add", lambda: bi.add(a, b, out=out)), ("sub", lambda: bi.sub(a, b, out=out)),
+                     ("add6", lambda: bi.add6(a, b, out=out))):
+        total, _ = time_launches(fn, steps * 5, args.warmup, torch)
+        cfg[name] = round(byts / (total / (steps * 5) * 1e-3) / 1e9, 1)
+    res["pairs_2e17_mixed"] = cfg
+    print(json.dumps(res))
+
+
+def poly_mode(torch, bi, args):
+    """Poly = (a a + b)(b b + b) + a b against one product, both mod B^n (the
+    paper's fixed precision, Table tab-mul), on its datasets NumBits x NumInsts
+    = 2^32."""
+    g = torch.Generator(device="cuda")
+    g.manual_seed(1006)
+    res = {"mode": "poly", "unit": "ms", "rows": []}
+    for bits in (2**15, 2**16, 2**17, 2**18, 2**19):
+        n, insts = bits // 32, 2**32 // bits
+        a = _rand_dev(torch, g, insts, n)
+        b = _rand_dev(torch, g, insts, n)
+        steps = 3
+        t_mul, _ = time_launches(lambda: bi.mullo(a, b), steps, 1, torch)
+        t_poly, _ = time_launches(lambda: bi.poly(a, b), steps, 1, torch)
+        res["rows"].append({"num_bits": bits, "num_insts": insts,
+                            "mul_ms": round(t_mul / steps, 3), "poly_ms": round(t_poly / steps, 3),
+                            "poly_over_mul": round(t_poly / t_mul, 3)})
+        del a, b
+        torch.cuda.empty_cache()
+    print(json.dumps(res))
 
 
 def kernel_sha():
