@@ -68,8 +68,11 @@ struct LimbRun {
 //
 // SPARSE: out aliases X's storage and most Y limbs are zero; a limb is only
 // stored when its value changes (saves rewriting the whole array).
+// top (LDS, nullable): raised by atomicMax to 1 + the index of the highest
+// nonzero result limb (the caller zeroes it before the call).
 template <int Q, bool SUB, class FX, class FY, bool SPARSE = false>
-__device__ __forceinline__ uint32_t wg_addsub(uint32_t* out, int n, FX X, FY Y, uint32_t cin, uint32_t* scratch) {
+__device__ __forceinline__ uint32_t wg_addsub(uint32_t* out, int n, FX X, FY Y, uint32_t cin, uint32_t* scratch,
+                                              uint32_t* top = nullptr) {
   constexpr bool out_differs = false;
   const int T = blockDim.x;
   uint32_t carry = cin;
@@ -93,6 +96,12 @@ __device__ __forceinline__ uint32_t wg_addsub(uint32_t* out, int n, FX X, FY Y, 
 #pragma unroll
     for (int i = 0; i < Q; ++i)
       if (i < valid && (!SPARSE || run.s[i] != x[i] || out_differs)) out[j0 + i] = run.s[i];
+    if (top) {
+      int m = 0;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) m = (i < valid && run.s[i] != 0u) ? j0 + i + 1 : m;
+      if (m) atomicMax(top, (uint32_t)m);
+    }
     carry = cout;
     __syncthreads();
   }

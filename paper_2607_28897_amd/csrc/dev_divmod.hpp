@@ -80,6 +80,35 @@ __device__ __forceinline__ int wg_prec(const uint32_t* x, int n, Shared* sh) {
   return r;
 }
 
+// sign of x - y over n limbs (both zero-extended to n), and whether x is 0,
+// in one pass
+struct Cmp { int sign; bool xzero; };
+
+__device__ __forceinline__ Cmp wg_cmp_z(const uint32_t* x, int nx, const uint32_t* y, int ny, int n,
+                                        Shared* sh) {
+  if (threadIdx.x == 0) { sh->red[1] = 0; sh->red[2] = 0; }
+  __syncthreads();
+  int m = 0, z = 0;
+#pragma unroll 8
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const uint32_t a = nx > 0 ? x[min(i, nx - 1)] : 0u, b = ny > 0 ? y[min(i, ny - 1)] : 0u;
+    const uint32_t av = i < nx ? a : 0u, bv = i < ny ? b : 0u;
+    m = av != bv ? i + 1 : m;
+    z = av != 0u ? 1 : z;
+  }
+  if (m) atomicMax(&sh->red[1], (uint32_t)m);
+  if (z) sh->red[2] = 1u;
+  __syncthreads();
+  const int top = (int)sh->red[1];
+  Cmp r{0, sh->red[2] == 0u};
+  if (top) {
+    const uint32_t a = top - 1 < nx ? x[top - 1] : 0u, b = top - 1 < ny ? y[top - 1] : 0u;
+    r.sign = a > b ? 1 : -1;
+  }
+  __syncthreads();
+  return r;
+}
+
 // sign of x - y over n limbs (both zero-extended to n)
 __device__ __forceinline__ int wg_cmp(const uint32_t* x, int nx, const uint32_t* y, int ny, int n,
                                       Shared* sh) {
@@ -223,6 +252,20 @@ __device__ inline int fixup(const uint32_t* v, int k1, int c, Bufs& bf, int lw, 
     }
   }
   int adj = 0;
+  if (neg) {
+    // the usual cases in one pass: e = 0 (w is exact) or -v <= e < 0 (one
+    // step down: w -= 1, e = v - |e|)
+    const Cmp cz = wg_cmp_z(bf.E, le, v, k1, le, sh);
+    if (cz.xzero) return lw;   // v w = B^c: w is exact and e = 0
+    if (cz.sign <= 0) {
+      wg_arith1<true>(bf.W, lw, bf.W, lw, 1u, sh);
+      wg_arith<true>(bf.E, le, v, k1, bf.E, le, sh);
+      neg = false;
+      ++adj;
+      if (adjust) *adjust += adj;
+      return lw;
+    }
+  }
   // while e < 0: w -= 1, e += v   (a correct estimate needs at most a few
   // rounds; the cap only guarantees that every wave terminates)
   while (neg && adj < kMaxAdjust) {
@@ -252,8 +295,9 @@ __device__ inline int fixup(const uint32_t* v, int k1, int c, Bufs& bf, int lw, 
   }
   if (adjust) *adjust += adj;
   if (adj >= kMaxAdjust) sh->failed = 1u;
-  const int pw = wg_prec(bf.W, lw, sh);
-  return pw > 0 ? pw : 1;
+  // lw stays an upper bound of w's length (a leading zero limb after w -= 1
+  // is harmless to every later operation)
+  return lw;
 }
 
 // w = floor(B^h / v) for a divisor with k1 >= 2 significant limbs and h >= k1.
@@ -313,16 +357,10 @@ __device__ inline int shifted_inverse(const uint32_t* v, int k1, int h, Bufs& bf
     const int c = cur - sdrop;
     lw = fixup(V, t, c, bf, lw, sh, smem, adjust);
     if (cur == h) break;
-    // Y = w * e (e < V has at most t limbs)
-    const int le = wg_prec(bf.E, t + 2, sh);
+    // Y = w * e (e < V has at most t limbs; a zero e costs one product of zeros)
+    const int le = t;
     int lnew;
-    if (le == 0) {
-      // e = 0: V divides B^c, so w' = w B^m exactly
-      lnew = lw + m;
-      wg_fill(bf.U2, lnew + 1, 0u);
-      for (int i = threadIdx.x; i < lw; i += blockDim.x) bf.U2[i + m] = bf.W[i];
-      __syncthreads();
-    } else {
+    {
       // only floor(w e / B^(c-m)) is needed: the low sd limbs of e add less
       // than w B^sd <= B^(c-m-1) to w e, which moves that floor by at most
       // one unit (the next fix-up absorbs it)
@@ -336,15 +374,16 @@ __device__ inline int shifted_inverse(const uint32_t* v, int k1, int h, Bufs& bf
         const int s2 = j + c - m - sd;
         return s2 < ly ? bf.T[s2] : 0u;
       };
-      wg_addsub<16, false>(bf.U2, lnew, X, Y, 0u, sh->scan);
+      if (threadIdx.x == 0) sh->red[3] = 0;
+      wg_addsub<16, false>(bf.U2, lnew, X, Y, 0u, sh->scan, &sh->red[3]);
     }
     {  // the new w is in U2: swap the two buffers instead of copying
       uint32_t* tmp = bf.W;
       bf.W = bf.U2;
       bf.U2 = tmp;
     }
-    lw = wg_prec(bf.W, lnew, sh);
-    if (lw == 0) lw = 1;
+    lw = max((int)sh->red[3], 1);   // w's length, reduced by the addition itself
+    __syncthreads();
     cur += m;
   }
   return lw;
