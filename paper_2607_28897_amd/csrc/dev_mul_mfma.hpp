@@ -501,17 +501,13 @@ __device__ __forceinline__ void strip_out7(v4i acc, int w, const Lds& s, const G
 }
 
 // The same for offset 8-bit digits: the strip's 64 limbs and its carry word.
-__device__ __forceinline__ void strip_out8(v4i acc, int w, const Lds& s, const Geo& g,
-                                           uint32_t* out) {
+// S_{256w-1} = PA(256w) - PA(256w-Nb) + PB(256w) - PB(256w-Na), the digit-sum
+// term at the start of strip w: block prefixes, plus a partial block where a
+// boundary is not block-aligned (the tests are wave-uniform).  Later strips of
+// a band carry it forward instead (strip_out8 returns the next one).
+__device__ __forceinline__ int strip_start_sum(const Lds& s, const Geo& g, int w) {
   const int lane = lane_id();
-  int32_t* sc = s.wscr;
-#pragma unroll
-  for (int v = 0; v < 4; ++v) sc[16 * (4 * (lane >> 4) + v) + (lane & 15)] = acc[v];
-  const int g0 = 64 * w;         // the strip's first limb (4-digit group)
-  const int m1 = g0 + lane;      // this lane's limb; its digits k = 4 m1 + t
-  // S at the strip start, S_{256w-1} = PA(256w) - PA(256w-Nb) + PB(256w) -
-  // PB(256w-Na): block prefixes, plus a partial block where a boundary is not
-  // block-aligned (the tests are wave-uniform)
+  const int g0 = 64 * w;
   int S0 = 0, part = 0;
   bool partial = false;
   auto pre = [&](bool isA, int gx, int sign) __attribute__((always_inline)) {
@@ -531,6 +527,19 @@ __device__ __forceinline__ void strip_out8(v4i acc, int w, const Lds& s, const G
   pre(false, g0, 1);
   pre(false, g0 - g.na, -1);
   if (partial) S0 += wave_sum(part);
+  return S0;
+}
+
+// Strip w with offset 8-bit digits: its 64 limbs and carry word.  S0 is the
+// digit-sum term at the strip start; returns the one of strip w + 1.
+__device__ __forceinline__ int strip_out8(v4i acc, int w, const Lds& s, const Geo& g,
+                                          uint32_t* out, int S0) {
+  const int lane = lane_id();
+  int32_t* sc = s.wscr;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) sc[16 * (4 * (lane >> 4) + v) + (lane & 15)] = acc[v];
+  const int g0 = 64 * w;         // the strip's first limb (4-digit group)
+  const int m1 = g0 + lane;      // this lane's limb; its digits k = 4 m1 + t
   // per-digit changes of S: alpha'_k - alpha'_{k-Nb} + beta'_k - beta'_{k-Na};
   // a group range entirely outside its operand is skipped (wave-uniform)
   int d[4] = {0, 0, 0, 0};
@@ -545,7 +554,9 @@ __device__ __forceinline__ void strip_out8(v4i acc, int w, const Lds& s, const G
   if (live(g0 - g.nb, g.na)) add_group(groupA(s.A, g, m1 - g.nb), -1, true);
   if (live(g0, g.nb)) add_group(groupB(s.B, g, m1), 1, false);
   if (live(g0 - g.na, g.nb)) add_group(groupB(s.B, g, m1 - g.na), -1, false);
-  const int excl = wave_incl_scan(sigma) - sigma;
+  const int incl = wave_incl_scan(sigma);
+  const int excl = incl - sigma;
+  const int S_next = S0 + __builtin_amdgcn_readlane(incl, 63);
   // pair counts cnt_k = min(k+1, Na) - max(0, k+1-Nb) (clamped at 0) change by
   // the same step for the four digits of a limb: both bounds are multiples of 4
   const int k0 = 4 * m1;
@@ -584,6 +595,7 @@ __device__ __forceinline__ void strip_out8(v4i acc, int w, const Lds& s, const G
     const uint32_t cout = (uint32_t)gb | ((uint32_t)pb & cin);
     s.carry[w] = (uint64_t)(H + cout) | ((uint64_t)((ones & tail) == tail) << 63);
   }
+  return S_next;
 }
 
 template <int DW, int P>
@@ -594,13 +606,16 @@ __device__ __forceinline__ void run_band(int band, const Lds& s, const Geo& g, u
   for (int i = 0; i < P; ++i) acc[i] = v4i{0, 0, 0, 0};
 #pragma unroll 1
   for (int rho = 0; rho < 4; ++rho) band_phase<P>(acc, s, g, w0, rho);
+  int S = 0;
 #pragma unroll
   for (int i = 0; i < P; ++i)
     if (w0 + i < g.W) {
-      if constexpr (DW == 8)
-        strip_out8(acc[i], w0 + i, s, g, out);
-      else
+      if constexpr (DW == 8) {
+        if (i == 0) S = strip_start_sum(s, g, w0);
+        S = strip_out8(acc[i], w0 + i, s, g, out, S);
+      } else {
         strip_out7(acc[i], w0 + i, s, g, out, coef);
+      }
     }
 }
 
