@@ -90,10 +90,14 @@ static int launch_addsub_q(uint32_t* out, uint32_t* cout, const uint32_t* a, con
 template <bool SUB>
 static int launch_addsub_t(uint32_t* out, uint32_t* cout, const uint32_t* a, const uint32_t* b,
                            int64_t n, int64_t batch, hipStream_t s) {
-  // about 256 threads per instance, 4..64 limbs each
+  // up to 2048 limbs: 256 threads per instance; above: 1024 threads, which
+  // keeps more loads in flight per CU (measured: 5.6 against 4.4 TB/s at 8192
+  // limbs), with 4..32 limbs each
   if (n <= 1024) return launch_addsub_q<4, SUB>(out, cout, a, b, n, batch, s);
   if (n <= 2048) return launch_addsub_q<8, SUB>(out, cout, a, b, n, batch, s);
-  if (n <= 4096) return launch_addsub_q<16, SUB>(out, cout, a, b, n, batch, s);
+  if (n <= 4096) return launch_addsub_q<4, SUB>(out, cout, a, b, n, batch, s);
+  if (n <= 8192) return launch_addsub_q<8, SUB>(out, cout, a, b, n, batch, s);
+  if (n <= 16384) return launch_addsub_q<16, SUB>(out, cout, a, b, n, batch, s);
   if (n <= 32768) return launch_addsub_q<32, SUB>(out, cout, a, b, n, batch, s);
   // beyond 1024 threads x 32 limbs: rounds of the work-group add, carry chained
   hipLaunchKernelGGL((k_addsub_rounds<SUB>), dim3((unsigned)batch), dim3(1024), 0, s, out, cout, a,
@@ -280,6 +284,8 @@ static int launch_add6_q(uint32_t* out, uint32_t* ovf, const uint32_t* a, const 
 
 int launch_add6(uint32_t* out, uint32_t* ovf, const uint32_t* a, const uint32_t* b, int64_t n,
                 int64_t batch, hipStream_t s) {
+  // six scans per instance: fewer, fuller threads than for one addition pay
+  // (measured: 4.4 TB/s at 4096 limbs with 256 threads, 2.2 with 1024)
   if (n <= 1024) return launch_add6_q<4>(out, ovf, a, b, n, batch, s);
   if (n <= 2048) return launch_add6_q<8>(out, ovf, a, b, n, batch, s);
   if (n <= 16384) return launch_add6_q<16>(out, ovf, a, b, n, batch, s);
