@@ -210,8 +210,9 @@ int bigint_divmod_ragged(uint32_t* q, const int64_t* q_off, uint32_t* r,
  * Times every candidate tile configuration of the MFMA-split multiply on the
  * current device for each size bin (2^15..2^19 bits), keeps the fastest and
  * writes the table as JSON to `cache_path` (host path; NULL = do not write).
- * Later plans use the table.  bigint_autotune_load reads such a file.  All
- * candidates produce identical bytes; the table only affects speed. */
+ * Later plans use the table.  bigint_autotune_load reads such a file (a
+ * NULL path restores the built-in table).  All candidates produce identical
+ * bytes; the table only affects speed. */
 int bigint_autotune(const char* cache_path, int flags);
 int bigint_autotune_load(const char* cache_path);
 

@@ -275,8 +275,10 @@ def autotune(cache_path: str | None = None, flags: int = 0):
     _check(lib().bigint_autotune(cache_path.encode() if cache_path else None, flags), "bigint_autotune")
 
 
-def autotune_load(cache_path: str):
-    _check(lib().bigint_autotune_load(cache_path.encode()), "bigint_autotune_load")
+def autotune_load(cache_path: str | None):
+    """Load a table written by autotune(); None restores the built-in table."""
+    _check(lib().bigint_autotune_load(cache_path.encode() if cache_path else None),
+           "bigint_autotune_load")
 
 
 class _Plan:

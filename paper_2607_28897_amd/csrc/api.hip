@@ -24,9 +24,10 @@ struct TuneEntry {
   int P, waves, dw;
 };
 static std::mutex g_tune_mu;
-static std::vector<TuneEntry> g_tune = {
+static const std::vector<TuneEntry> kBuiltinTune = {
     {1448, 4, 4, 8}, {2896, 8, 4, 8}, {5792, 8, 8, 8}, {11585, 8, 8, 8},
     {BIGINT_MFMA_MAX_LIMBS, 16, 8, 8}};
+static std::vector<TuneEntry> g_tune = kBuiltinTune;
 
 // The tuned configuration for this size; when its LDS does not fit (7-bit
 // digits near the top of the range) the same tiles with 8-bit digits, which
@@ -630,9 +631,14 @@ int bigint_autotune(const char* cache_path, int flags) {
   return BIGINT_OK;
 }
 
-// Reads a table written by bigint_autotune (the fields are read in order).
+// Reads a table written by bigint_autotune (the fields are read in order);
+// a null path restores the built-in table.
 int bigint_autotune_load(const char* cache_path) {
-  if (!cache_path) return BIGINT_EINVAL;
+  if (!cache_path) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune = kBuiltinTune;
+    return BIGINT_OK;
+  }
   FILE* f = fopen(cache_path, "r");
   if (!f) return BIGINT_EINVAL;
   std::string txt;

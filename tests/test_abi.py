@@ -109,3 +109,24 @@ def test_mfma_config_query(bi):
         bi.set_mfma_config(0, 0, 0)
     with pytest.raises(bi.BigIntError):
         bi.mfma_config(18433, 1)                   # beyond BIGINT_MFMA_MAX_LIMBS
+
+
+def test_tune_table_load_and_restore(bi, tmp_path):
+    # host-side only: a loaded table changes the configuration bigint_mul
+    # picks, and a null path restores the built-in one
+    import json
+    path = str(tmp_path / "t.json")
+    json.dump({"bins": [{"max_limbs": 18432, "strips_per_band": 8, "waves": 4, "digit_bits": 7}]},
+              open(path, "w"))
+    bi.autotune_load(path)
+    try:
+        assert bi.mfma_config(4096, 4096) == (8, 4, 7)
+    finally:
+        bi.autotune_load(None)
+    assert bi.mfma_config(4096, 4096) == (8, 8, 8)
+    bad = str(tmp_path / "bad.json")
+    json.dump({"bins": [{"max_limbs": 100, "strips_per_band": 5, "waves": 4, "digit_bits": 7}]},
+              open(bad, "w"))
+    with pytest.raises(bi.BigIntError):
+        bi.autotune_load(bad)
+    assert bi.mfma_config(4096, 4096) == (8, 8, 8)

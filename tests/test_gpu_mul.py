@@ -171,12 +171,16 @@ def test_autotune_table_roundtrip(bi, orc, tmp_path):
         assert e["strips_per_band"] in (4, 8, 16) and e["waves"] in (4, 8)
         assert e["digit_bits"] in (7, 8)
     bi.autotune_load(path)
-    g = np.random.default_rng(9)
-    a = rand_limbs(g, 3, 5000)
-    b = rand_limbs(g, 3, 5000)
-    p = host(bi.mul(dev(a), dev(b), bi.MUL_MFMA))
-    for i in range(3):
-        assert np.array_equal(p[i], orc.mul1(a[i], b[i]))
+    try:
+        g = np.random.default_rng(9)
+        a = rand_limbs(g, 3, 5000)
+        b = rand_limbs(g, 3, 5000)
+        p = host(bi.mul(dev(a), dev(b), bi.MUL_MFMA))
+        for i in range(3):
+            assert np.array_equal(p[i], orc.mul1(a[i], b[i]))
+    finally:
+        bi.autotune_load(None)          # the built-in table again
+    assert bi.mfma_config(16384, 16384) == (16, 8, 8)
 
 
 @pytest.mark.parametrize("algo", ALGOS)

@@ -85,3 +85,28 @@ def test_plan_errors(bi):
                                 la.ctypes.data_as(ctypes.c_void_p), 2, 0) == bi.EINVAL
     assert L.bigint_plan_create(ctypes.byref(h), 99, None, None, 0, 0) == bi.EINVAL
     assert L.bigint_plan_destroy(None) == bi.EINVAL
+
+
+@pytest.mark.parametrize("dw", [7, 8])
+def test_ragged_with_loaded_table(bi, orc, tmp_path, dw):
+    # plans read the tuned table: a loaded table with one digit width drives
+    # every configuration of the persistent kernel (P = 4, 8, 16)
+    import json
+    path = str(tmp_path / f"tune{dw}.json")
+    bins = [{"max_limbs": 1500, "strips_per_band": 4, "waves": 8, "digit_bits": dw},
+            {"max_limbs": 6000, "strips_per_band": 8, "waves": 8, "digit_bits": dw},
+            {"max_limbs": 18432, "strips_per_band": 16, "waves": 8, "digit_bits": dw}]
+    json.dump({"arch": "gfx950", "op": "mul_mfma", "bins": bins}, open(path, "w"))
+    bi.autotune_load(path)
+    try:
+        g = np.random.default_rng(40 + dw)
+        la = np.array([1, 1000, 1499, 1501, 5000, 6100, 12000, 16384, 7, 3333], np.int64)
+        lb = np.array([9, 1000, 1400, 1501, 100, 6100, 12000, 16384, 7000, 3], np.int64)
+        a, a_off = _ragged(g, la)
+        b, b_off = _ragged(g, lb)
+        res, oo = _run(bi, la, lb, a, a_off, b, b_off, 0)
+        for i in range(la.size):
+            want = orc.mul1(a[a_off[i]:a_off[i + 1]], b[b_off[i]:b_off[i + 1]])
+            assert np.array_equal(res[oo[i]:oo[i + 1]], want), i
+    finally:
+        bi.autotune_load(None)
