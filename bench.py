@@ -157,6 +157,19 @@ def main():
     p_total, p_kernel = time_launches(run_plain, p_steps, 1, torch)
     print(f"# plain: {p_total / p_steps:.4f} ms/step", file=sys.stderr, flush=True)
     same = bool(torch.equal(out_m, out_p))
+    # one Karatsuba level over the same MFMA-split multiply (three launches), beside it
+    out_k = torch.empty_like(out_m)
+    pk = ctypes.c_void_p(out_k.data_ptr())
+
+    def run_kara():
+        rc = L.bigint_mul(pk, pa, n, pb, n, batch, bi.MUL_KARATSUBA, stream)
+        if rc:
+            raise bi.BigIntError(rc, "bigint_mul")
+
+    k_steps = max(3, args.steps // 2)
+    k_total, _ = time_launches(run_kara, k_steps, 2, torch)
+    print(f"# karatsuba: {k_total / k_steps:.4f} ms/step", file=sys.stderr, flush=True)
+    same_k = bool(torch.equal(out_m, out_k))
 
     ms = total_ms / args.steps
     value = batch / (ms * 1e-3)
@@ -218,6 +231,14 @@ def main():
             "steps": p_steps,
         },
         "mfma_equals_plain": same,
+        "karatsuba": {
+            "value": round(batch / (k_total / k_steps * 1e-3), 1),
+            "unit": "muls/s",
+            "ms_per_step": round(k_total / k_steps, 4),
+            "steps": k_steps,
+            "what": "one Karatsuba level (three 2^18-bit products per pair) over the same MFMA-split multiply",
+            "equals_mfma": same_k,
+        },
     }
     if not args.no_cpu:
         cpu, exact, _ = cpu_baseline(a_np, b_np, out_m.cpu().numpy().view(np.uint32), args.cpu_seconds)

@@ -60,6 +60,7 @@ extern "C" {
 #define BIGINT_MUL_AUTO 0  /* MFMA-split where supported, else plain        */
 #define BIGINT_MUL_PLAIN 1 /* u64-digit schoolbook convolution               */
 #define BIGINT_MUL_MFMA 2  /* 7- or 8-bit digits, int8 MFMA Toeplitz tiles   */
+#define BIGINT_MUL_KARATSUBA 3 /* one Karatsuba level over BIGINT_MUL_MFMA  */
 
 /* plan operations */
 #define BIGINT_OP_MUL 1
@@ -120,6 +121,14 @@ int bigint_sub(uint32_t* out, uint32_t* borrow_out, const uint32_t* a,
  *     int8; every MFMA sum is at most min(Na,Nb)*2^14 < 2^31) with the
  *     offset terms 128 (window sums of the digits) + 2^14 (pair counts)
  *     added per coefficient in 64-bit arithmetic.  Both give the same bytes.
+ *   BIGINT_MUL_KARATSUBA (na == nb >= 2): one level of Karatsuba's method
+ *     over the MFMA-split multiply, with h = ceil(n/2) and s = sign(a0 - a1)
+ *     sign(b1 - b0): a b = p2 B^(2h) + (p0 + p2 + s pm) B^h + p0 with
+ *     p0 = a0 b0, p2 = a1 b1, pm = |a0 - a1| |b1 - b0| (three half-size
+ *     products, 3/4 of the multiply-accumulates).  Not in the paper, whose
+ *     conclusion names more elaborate multiplication algorithms as a next
+ *     step.  The call allocates 5n limbs of workspace per instance on
+ *     `stream` (stream-ordered) and frees it the same way.
  * a: batch*na limbs, b: batch*nb limbs, out: batch*(na+nb) limbs.
  * na, nb >= 1.  MFMA needs na, nb <= BIGINT_MFMA_MAX_LIMBS (else
  * BIGINT_EUNSUPPORTED); PLAIN needs na+nb <= 32768; AUTO picks MFMA when it

@@ -22,7 +22,7 @@ __all__ = [
     "lib", "add", "sub", "mul", "divmod", "digits7", "conv7", "shinv",
     "MulPlan", "DivPlan", "autotune", "autotune_load", "set_mfma_config", "mfma_config", "BigIntError",
     "mullo", "add6", "poly",
-    "MUL_AUTO", "MUL_PLAIN", "MUL_MFMA",
+    "MUL_AUTO", "MUL_PLAIN", "MUL_MFMA", "MUL_KARATSUBA",
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -30,7 +30,7 @@ LIB_PATH = os.path.join(HERE, "_lib", "libbigint_rocm.so")
 
 OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED = 0, -1, -2, -3, -4
 DIV_OK, DIVZERO = 0, 1
-MUL_AUTO, MUL_PLAIN, MUL_MFMA = 0, 1, 2
+MUL_AUTO, MUL_PLAIN, MUL_MFMA, MUL_KARATSUBA = 0, 1, 2, 3
 OP_MUL, OP_DIVMOD = 1, 2
 PLAN_DEFAULT, PLAN_PLAIN, PLAN_NO_GRAPH = 0, 1, 2
 MFMA_MAX_LIMBS = 18432

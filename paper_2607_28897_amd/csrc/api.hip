@@ -155,12 +155,29 @@ static bool mfma_fits(int64_t na, int64_t nb, MfmaCfg cfg) {
 int bigint_mul(uint32_t* out, const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb,
                int64_t batch, int algo, void* stream) {
   if (!out || !a || !b || na <= 0 || nb <= 0 || batch < 0) return BIGINT_EINVAL;
-  if (algo != BIGINT_MUL_AUTO && algo != BIGINT_MUL_PLAIN && algo != BIGINT_MUL_MFMA)
+  if (algo != BIGINT_MUL_AUTO && algo != BIGINT_MUL_PLAIN && algo != BIGINT_MUL_MFMA &&
+      algo != BIGINT_MUL_KARATSUBA)
     return BIGINT_EINVAL;
   if (batch > 0x7fffffff || na > (1 << 20) || nb > (1 << 20)) return BIGINT_EUNSUPPORTED;
   const size_t ob = (size_t)(na + nb) * batch * 4;
   if (overlap(out, ob, a, (size_t)na * batch * 4) || overlap(out, ob, b, (size_t)nb * batch * 4))
     return BIGINT_EINVAL;
+  if (algo == BIGINT_MUL_KARATSUBA) {
+    if (na != nb || na < 2) return BIGINT_EUNSUPPORTED;
+    const int h = (int)((na + 1) / 2);
+    const MfmaCfg hc = current_mfma_cfg(h, h);
+    if (!mfma_fits(h, h, hc)) return BIGINT_EUNSUPPORTED;
+    if (batch == 0) return BIGINT_OK;
+    hipStream_t s = (hipStream_t)stream;
+    void* ws = nullptr;
+    hipError_t e = hipMallocAsync(&ws, kara_ws_bytes((int)na, batch), s);
+    if (e != hipSuccess) { set_hip_error(e); return BIGINT_ENOMEM; }
+    const int rc = launch_mul_kara(out, a, b, na, batch, ws, hc, s);
+    e = hipFreeAsync(ws, s);
+    if (rc != BIGINT_OK) return rc;
+    if (e != hipSuccess) { set_hip_error(e); return BIGINT_EHIP; }
+    return BIGINT_OK;
+  }
   const MfmaCfg cfg = current_mfma_cfg((int)na, (int)nb);
   int use = algo;
   if (use == BIGINT_MUL_AUTO)

@@ -28,6 +28,9 @@ int launch_mul_plain(uint32_t* out, const uint32_t* a, int64_t na, const uint32_
 int launch_mul_mfma(uint32_t* out, int32_t* coef, const uint32_t* a, int64_t na,
                     const uint32_t* b, int64_t nb, int64_t batch, MfmaCfg cfg, hipStream_t s,
                     int nout = -1);
+size_t kara_ws_bytes(int n, int64_t batch);
+int launch_mul_kara(uint32_t* out, const uint32_t* a, const uint32_t* b, int64_t n, int64_t batch,
+                    void* ws, MfmaCfg cfg, hipStream_t s);
 int launch_add6(uint32_t* out, uint32_t* ovf, const uint32_t* a, const uint32_t* b, int64_t n,
                 int64_t batch, hipStream_t s);
 size_t poly_lds(int n, MfmaCfg cfg);

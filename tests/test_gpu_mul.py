@@ -240,3 +240,39 @@ def test_offset_digit_extremes(bi, orc, pat):
         b[:] = 0xFF00FF00
     p = host(_mul(bi, dev(a), dev(b), "mfma8"))[0]
     assert np.array_equal(p, orc.mul1(a[0], b[0]))
+
+
+# ---- one Karatsuba level over the MFMA-split multiply ----------------------------------
+
+@pytest.mark.parametrize("n", [2, 3, 64, 65, 127, 1000, 1001, 4096, 16384, 18432])
+def test_karatsuba(bi, orc, n):
+    g = np.random.default_rng(n + 77)
+    a = rand_limbs(g, 6, n)
+    b = rand_limbs(g, 6, n)
+    h = (n + 1) // 2
+    a[1] = 0xFFFFFFFF
+    b[1] = 0xFFFFFFFF                      # largest operands
+    a[2, h:] = a[2, :n - h]                # a1 = low part of a0: a0 - a1 mostly 0 limbs
+    if 2 * h == n:
+        a[3, h:] = a[3, :h]                # a0 == a1: the middle sign is 0
+    b[4, :h] = 0                           # b0 = 0: b1 - b0 = b1 > 0
+    a[5, :h] = 0                           # a0 = 0 < a1: negative difference
+    b[5, h:] = 0                           # b1 = 0 < b0: negative difference, sign +1
+    p = host(bi.mul(dev(a), dev(b), bi.MUL_KARATSUBA))
+    for i in range(6):
+        assert np.array_equal(p[i], orc.mul1(a[i], b[i])), i
+
+
+def test_karatsuba_matches_mfma_bytes(bi):
+    from paper_2607_28897_amd import inputs
+    c = inputs.pairs_2e19()
+    ta, tb = dev(c["a"]), dev(c["b"])
+    assert np.array_equal(host(bi.mul(ta, tb, bi.MUL_KARATSUBA)), host(bi.mul(ta, tb, bi.MUL_MFMA)))
+
+
+def test_karatsuba_unsupported_shapes(bi):
+    g = np.random.default_rng(1)
+    with pytest.raises(bi.BigIntError):
+        bi.mul(dev(rand_limbs(g, 1, 10)), dev(rand_limbs(g, 1, 11)), bi.MUL_KARATSUBA)
+    with pytest.raises(bi.BigIntError):
+        bi.mul(dev(rand_limbs(g, 1, 1)), dev(rand_limbs(g, 1, 1)), bi.MUL_KARATSUBA)
