@@ -262,27 +262,31 @@ def copy_mode(torch):
 
 def peak_mode(torch, bi):
     """Achievable int8 MFMA rate with no memory traffic (v_mfma_i32_16x16x64_i8,
-    8 independent accumulators per wave), for 4..64 waves per CU."""
+    8 independent accumulators per wave, 64 per loop round), for 4..32 waves
+    per CU, with constant operands and with operands whose bits change every
+    round (as random digits do), and the shader clock that goes with it."""
     import ctypes
     L = bi.lib()
     out = torch.empty(8192 * 256, dtype=torch.int32, device="cuda")
     s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
     ncu = torch.cuda.get_device_properties(0).multi_processor_count
     res = {}
-    for per_cu in (1, 2, 4, 8, 16):
-        blocks, iters = ncu * per_cu, 4000
-        L.bigint_diag_mfma_rate(ctypes.c_void_p(out.data_ptr()), blocks, 100, s)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        rc = L.bigint_diag_mfma_rate(ctypes.c_void_p(out.data_ptr()), blocks, iters, s)
-        e1.record()
-        torch.cuda.synchronize()
-        if rc:
-            raise bi.BigIntError(rc, "bigint_diag_mfma_rate")
-        ms = e0.elapsed_time(e1)
-        macs = blocks * 4 * iters * 8 * 16384
-        res[f"{4 * per_cu}_waves_per_cu_TOPs"] = round(2 * macs / ms / 1e9, 1)
+    for toggle in (0, 1):
+        for per_cu in (1, 2, 4, 8):
+            blocks, iters = ncu * per_cu, 1000
+            L.bigint_diag_mfma_rate(ctypes.c_void_p(out.data_ptr()), blocks, 20, toggle, s)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            rc = L.bigint_diag_mfma_rate(ctypes.c_void_p(out.data_ptr()), blocks, iters, toggle, s)
+            e1.record()
+            torch.cuda.synchronize()
+            if rc:
+                raise bi.BigIntError(rc, "bigint_diag_mfma_rate")
+            ms = e0.elapsed_time(e1)
+            macs = blocks * 4 * iters * 64 * 16384
+            key = ("toggling" if toggle else "constant") + f"_{4 * per_cu}_waves_per_cu_TOPs"
+            res[key] = round(2 * macs / ms / 1e9, 1)
     print(json.dumps({"mode": "mfma-peak", "cus": ncu, **res}))
 
 

@@ -242,11 +242,14 @@ int bigint_shinv(uint32_t* w, const uint32_t* v, int64_t nv, int64_t h,
                  int64_t batch, void* stream);
 
 /* Register-only int8 MFMA rate probe: `blocks` work-groups of 4 waves, each
- * wave issuing 8 independent v_mfma_i32_16x16x64_i8 per iteration for
- * `iters` iterations (16384 multiply-accumulates each), no memory traffic.
+ * wave issuing 64 v_mfma_i32_16x16x64_i8 per iteration (8 independent
+ * accumulators, 16384 multiply-accumulates each) for `iters` iterations, no
+ * memory traffic.  toggle != 0 flips the operand bit patterns between rounds
+ * of 8 (random data draws more power than constant data).
  * scratch: blocks*256 int32 (results kept so the work is not removed).
  * Time it with events on `stream` to get the achievable MFMA rate. */
-int bigint_diag_mfma_rate(int32_t* scratch, int64_t blocks, int64_t iters, void* stream);
+int bigint_diag_mfma_rate(int32_t* scratch, int64_t blocks, int64_t iters, int toggle,
+                          void* stream);
 
 /* Tile parameters of the MFMA multiply used by the next calls on this thread
  * (strips per wave band: 4, 8 or 16; waves per work-group: 4 or 8; digit

@@ -88,7 +88,7 @@ def lib() -> ctypes.CDLL:
             "bigint_mullo": ([_vp, _vp, _vp, _i64, _i64, _vp], _int),
             "bigint_add6": ([_vp, _vp, _vp, _vp, _i64, _i64, _vp], _int),
             "bigint_poly": ([_vp, _vp, _vp, _i64, _i64, _vp], _int),
-            "bigint_diag_mfma_rate": ([_vp, _i64, _i64, _vp], _int),
+            "bigint_diag_mfma_rate": ([_vp, _i64, _i64, _int, _vp], _int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)

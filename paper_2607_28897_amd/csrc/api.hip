@@ -535,10 +535,11 @@ int bigint_divmod_ragged(uint32_t* q, const int64_t* q_off, uint32_t* r, const i
                        plan->cap_u, plan->cap_v, plan->grid, -1, nullptr, s);
 }
 
-int bigint_diag_mfma_rate(int32_t* scratch, int64_t blocks, int64_t iters, void* stream) {
+int bigint_diag_mfma_rate(int32_t* scratch, int64_t blocks, int64_t iters, int toggle,
+                          void* stream) {
   if (!scratch || blocks <= 0 || iters <= 0) return BIGINT_EINVAL;
   if (blocks > (1 << 20) || iters > (1 << 24)) return BIGINT_EUNSUPPORTED;
-  return launch_mfma_rate(scratch, (int)blocks, (int)iters, (hipStream_t)stream);
+  return launch_mfma_rate(scratch, (int)blocks, (int)iters, toggle, (hipStream_t)stream);
 }
 
 // ---- autotuning ------------------------------------------------------------------

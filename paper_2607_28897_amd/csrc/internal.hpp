@@ -56,7 +56,7 @@ int launch_mul_ragged(uint32_t* out, const int64_t* out_off, const uint32_t* a,
                       const QueueItem* queue, int64_t nitems, uint32_t* counter, bool plain,
                       size_t lds, int waves, int grid, hipStream_t s);
 
-int launch_mfma_rate(int32_t* out, int blocks, int iters, hipStream_t s);
+int launch_mfma_rate(int32_t* out, int blocks, int iters, int toggle, hipStream_t s);
 
 // ---- division -------------------------------------------------------------------
 size_t div_ws_bytes(int cap_u, int cap_v, int grid);

@@ -445,18 +445,27 @@ __global__ __launch_bounds__(1024) void k_mul_plain_ragged(uint32_t* out, const 
 
 // ============================================================================
 // register-only MFMA rate probe (diagnostic): every wave keeps 8 independent
-// accumulators busy with v_mfma_i32_16x16x64_i8; no memory traffic inside.
+// accumulators busy with v_mfma_i32_16x16x64_i8, 64 per loop round (so the
+// loop's own register moves stay small next to them); no memory traffic.
+// toggle != 0 changes every operand bit pattern between rounds (one XOR per
+// round), as random digits do; constant operands draw less power.
 // ============================================================================
-__global__ __launch_bounds__(256) void k_mfma_rate(int32_t* out, int iters) {
+__global__ __launch_bounds__(256) void k_mfma_rate(int32_t* out, int iters, int toggle) {
   const int lane = lane_id();
   v4i a = {lane, lane * 3, lane * 5, lane * 7};
   v4i b = {lane * 11, lane * 13, lane, 1};
   v4i acc[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) acc[j] = v4i{j, 0, 0, 0};
+  const int flip = toggle ? (int)0x9e3779b9 : 0;
   for (int i = 0; i < iters; ++i) {
 #pragma unroll
-    for (int j = 0; j < 8; ++j) acc[j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, acc[j], 0, 0, 0);
+    for (int r = 0; r < 8; ++r) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) acc[j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, acc[j], 0, 0, 0);
+      a ^= flip;
+      b ^= flip + r;
+    }
   }
   int32_t t = 0;
 #pragma unroll
@@ -464,8 +473,8 @@ __global__ __launch_bounds__(256) void k_mfma_rate(int32_t* out, int iters) {
   out[blockIdx.x * blockDim.x + threadIdx.x] = t;
 }
 
-int launch_mfma_rate(int32_t* out, int blocks, int iters, hipStream_t s) {
-  hipLaunchKernelGGL(k_mfma_rate, dim3(blocks), dim3(256), 0, s, out, iters);
+int launch_mfma_rate(int32_t* out, int blocks, int iters, int toggle, hipStream_t s) {
+  hipLaunchKernelGGL(k_mfma_rate, dim3(blocks), dim3(256), 0, s, out, iters, toggle);
   BI_LAUNCH_CHECK();
   return BIGINT_OK;
 }

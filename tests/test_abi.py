@@ -68,7 +68,7 @@ def test_host_side_argument_checks(bi):
     assert L.bigint_set_mfma_config(0, 3, 0) == EINVAL
     assert L.bigint_set_mfma_config(0, 0, 6) == EINVAL
     assert L.bigint_digits7(None, p, 4, 5, 1, None) == EINVAL
-    assert L.bigint_diag_mfma_rate(None, 1, 1, None) == EINVAL
+    assert L.bigint_diag_mfma_rate(None, 1, 1, 0, None) == EINVAL
 
 
 def test_plan_argument_checks(bi):
