@@ -297,8 +297,10 @@ int launch_add6(uint32_t* out, uint32_t* ovf, const uint32_t* a, const uint32_t*
 // the MFMA-split multiply (a single call site, so its code is emitted once)
 // with two n-limb temporaries in a global workspace, each followed by its
 // addition on the whole work-group.
+// Two work-groups per CU need 128 registers (4 waves per SIMD); the 16-strip
+// tiles do not fit that, so they keep one.
 template <int P>
-__global__ __launch_bounds__(512) void k_poly(uint32_t* out, const uint32_t* a, const uint32_t* b,
+__global__ __launch_bounds__(512, P == 16 ? 2 : 4) void k_poly(uint32_t* out, const uint32_t* a, const uint32_t* b,
                                               int n, int64_t batch, uint32_t* ws) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
   __shared__ uint32_t scratch[32];
