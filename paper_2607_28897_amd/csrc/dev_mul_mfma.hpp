@@ -379,6 +379,15 @@ __device__ __forceinline__ v4i align_B(const BRaw& b) {
 // the end of the previous step; the raw dwords of the next B tile were loaded
 // one step earlier, and the one new A tile goes into the ring slot that the
 // first MFMA of the step has just read.
+//
+// Band edges: where the low end of the band's y range is set by the A
+// operand (the upper half of the product), strip i's first useful step is i,
+// so the first P-1 steps hold a staircase of MFMAs on all-zero A tiles.
+// There the first P steps run as a "ramp" block that leaves those MFMAs out
+// at compile time.  (The mirror staircase at the high end of the range, in
+// the lower half of the product, is kept: walking those ranges downwards
+// with reversed accumulators measured slower, its extra registers costing
+// more than the MFMAs it saves.)
 template <int P>
 __device__ __forceinline__ void band_phase(v4i (&acc)[P], const Lds& s, const Geo& g, int w0,
                                            int rho) {
@@ -386,39 +395,48 @@ __device__ __forceinline__ void band_phase(v4i (&acc)[P], const Lds& s, const Ge
   const int L = r.hi - r.lo + 1;
   if (L <= 0) return;
   const int xb = w0 - r.lo;  // strip i at step u uses x = xb + i - u
+  // the low end of the range is set by the A operand: strip i starts at step i
+  const bool ramp = L >= 2 * P && r.lo == w0 - r.xhi;
   v4i ring[P];
 #pragma unroll
   for (int i = 0; i < P; ++i) ring[i] = load_A(s.A, g, xb + i, rho, r);
   v4i Bc = align_B(load_B_raw(s.B, r.lo, rho));
   BRaw raw = load_B_raw(s.B, min(r.lo + 1, r.hi), rho);
 
-  // one step of the pipeline (st = step mod P, known at compile time).  The
+  // one step (st = step mod P and the ramp flag known at compile time).  The
   // next B tile is aligned into a second register set half-way through the
   // step, so the step boundary carries no VALU -> MFMA dependency.
-  auto step_fn = [&](const int step, const int st) __attribute__((always_inline)) {
+  auto step_fn = [&](const int step, const int st, const bool rmp) __attribute__((always_inline)) {
+    auto mma = [&](int i) __attribute__((always_inline)) {
+      if (!rmp || i <= st)
+        acc[i] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ring[(P + i - st) % P], Bc, acc[i], 0, 0, 0);
+    };
     // strip P-1 first: its slot is the one the next step's new tile takes
-    acc[P - 1] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ring[(2 * P - 1 - st) % P], Bc,
-                                                        acc[P - 1], 0, 0, 0);
+    mma(P - 1);
     ring[(2 * P - 1 - st) % P] = load_A(s.A, g, xb - step - 1, rho, r);
 #pragma unroll
-    for (int i = P - 2; i >= P / 2; --i)
-      acc[i] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ring[(P + i - st) % P], Bc, acc[i], 0, 0, 0);
+    for (int i = P - 2; i >= P / 2; --i) mma(i);
     __builtin_amdgcn_sched_barrier(0);
     const v4i Bn = align_B(raw);
     raw = load_B_raw(s.B, min(r.lo + step + 2, r.hi), rho);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int i = P / 2 - 1; i >= 0; --i)
-      acc[i] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ring[(P + i - st) % P], Bc, acc[i], 0, 0, 0);
+    for (int i = P / 2 - 1; i >= 0; --i) mma(i);
     __builtin_amdgcn_sched_barrier(0);
     Bc = Bn;
   };
   // full blocks of P steps: no exit inside, the ring returns to its layout
   const int nfull = L / P;
-#pragma unroll 1
-  for (int blk = 0; blk < nfull; ++blk) {
+  int blk0 = 0;
+  if (ramp) {
 #pragma unroll
-    for (int st = 0; st < P; ++st) step_fn(blk * P + st, st);
+    for (int st = 0; st < P; ++st) step_fn(st, st, true);
+    blk0 = 1;
+  }
+#pragma unroll 1
+  for (int blk = blk0; blk < nfull; ++blk) {
+#pragma unroll
+    for (int st = 0; st < P; ++st) step_fn(blk * P + st, st, false);
   }
   // the remaining L mod P steps
   const int rem = L - nfull * P;
@@ -426,7 +444,7 @@ __device__ __forceinline__ void band_phase(v4i (&acc)[P], const Lds& s, const Ge
     // a guarded, fully unrolled block keeps every ring index a constant
 #pragma unroll
     for (int st = 0; st < P - 1; ++st)
-      if (st < rem) step_fn(nfull * P + st, st);
+      if (st < rem) step_fn(nfull * P + st, st, false);
   }
 }
 
