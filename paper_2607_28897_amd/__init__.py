@@ -114,14 +114,32 @@ def _stream():
 
 
 def _limbs(t, name):
+    """The tensor as u32 limbs.  64-bit limb tensors (int64/uint64) are viewed
+    as twice as many u32 limbs: on little-endian hosts and gfx950 the bytes of
+    n u64 digits are those of 2n u32 limbs."""
     torch = _torch()
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
         raise TypeError(f"{name} must be a CUDA tensor")
-    if t.dtype not in (torch.int32, getattr(torch, "uint32", torch.int32)):
-        raise TypeError(f"{name} must hold 32-bit limbs (int32/uint32), got {t.dtype}")
+    wide = (torch.int64, getattr(torch, "uint64", torch.int64))
+    narrow = (torch.int32, getattr(torch, "uint32", torch.int32))
+    if t.dtype not in wide + narrow:
+        raise TypeError(f"{name} must hold 32- or 64-bit limbs, got {t.dtype}")
     if not t.is_contiguous():
         t = t.contiguous()
+    if t.dtype in wide:
+        t = t.view(torch.int32)
     return t
+
+
+def _wide(t):
+    """The dtype to hand results back in: 64-bit limb inputs get 64-bit limb
+    outputs (a view of the same bytes), 32-bit inputs 32-bit outputs."""
+    torch = _torch()
+    return t.dtype if t.dtype in (torch.int64, getattr(torch, "uint64", torch.int64)) else None
+
+
+def _back(t, dtype):
+    return t if dtype is None else t.view(dtype)
 
 
 def _rows(t):
@@ -144,20 +162,21 @@ def sub(a, b, out=None):
 
 def _addsub(fn, a, b, out, what):
     torch = _torch()
+    wd = _wide(a)
     a, b = _limbs(a, "a"), _limbs(b, "b")
     if a.shape != b.shape:
         raise ValueError("a and b must have the same shape")
     batch, n = _rows(a)
-    if out is None:
-        out = torch.empty_like(a)
+    out = torch.empty_like(a) if out is None else _limbs(out, "out")
     carry = torch.empty(batch, dtype=torch.int32, device=a.device)
     _check(fn(_p(out), _p(carry), _p(a), _p(b), n, batch, _stream()), what)
-    return out, carry
+    return _back(out, wd), carry
 
 
 def mul(a, b, algo: int = MUL_AUTO):
     """Full products a * b row by row: [batch, na] x [batch, nb] -> [batch, na+nb]."""
     torch = _torch()
+    wd = _wide(a)
     a, b = _limbs(a, "a"), _limbs(b, "b")
     ba, na = _rows(a)
     bb, nb = _rows(b)
@@ -165,12 +184,13 @@ def mul(a, b, algo: int = MUL_AUTO):
         raise ValueError("batch mismatch")
     out = torch.empty((ba, na + nb), dtype=a.dtype, device=a.device)
     _check(lib().bigint_mul(_p(out), _p(a), na, _p(b), nb, ba, algo, _stream()), "bigint_mul")
-    return out if a.dim() == 2 else out.view(-1)
+    return _back(out if a.dim() == 2 else out.view(-1), wd)
 
 
 def divmod(u, v):
     """(q, r, status): q = floor(u/v) ([batch, nu]), r = u - q v ([batch, nv])."""
     torch = _torch()
+    wd = _wide(u)
     u, v = _limbs(u, "u"), _limbs(v, "v")
     bu, nu = _rows(u)
     bv, nv = _rows(v)
@@ -181,7 +201,7 @@ def divmod(u, v):
     st = torch.empty(bu, dtype=torch.int32, device=u.device)
     _check(lib().bigint_divmod(_p(q), _p(r), _p(st), _p(u), nu, _p(v), nv, bu, _stream()),
            "bigint_divmod")
-    return q, r, st
+    return _back(q, wd), _back(r, wd), st
 
 
 def digits7(a, D=None):
@@ -225,6 +245,7 @@ def set_mfma_config(strips_per_band: int = 0, waves: int = 0, digit_bits: int = 
 def mullo(a, b):
     """a * b mod B^n row by row ([batch, n] x [batch, n] -> [batch, n])."""
     torch = _torch()
+    wd = _wide(a)
     a, b = _limbs(a, "a"), _limbs(b, "b")
     ba, n = _rows(a)
     bb, nb = _rows(b)
@@ -232,34 +253,35 @@ def mullo(a, b):
         raise ValueError("shape mismatch")
     out = torch.empty((ba, n), dtype=a.dtype, device=a.device)
     _check(lib().bigint_mullo(_p(out), _p(a), _p(b), n, ba, _stream()), "bigint_mullo")
-    return out if a.dim() == 2 else out.view(-1)
+    return _back(out if a.dim() == 2 else out.view(-1), wd)
 
 
 def add6(a, b, out=None):
     """The 6-Add workload: (4a + 3b) mod B^n by six dependent additions, and
     the count of additions that overflowed (uint32 per row)."""
     torch = _torch()
+    wd = _wide(a)
     a, b = _limbs(a, "a"), _limbs(b, "b")
     ba, n = _rows(a)
     if b.shape != a.shape:
         raise ValueError("shape mismatch")
-    if out is None:
-        out = torch.empty_like(a)
-    ovf = torch.empty(ba, dtype=a.dtype, device=a.device)
+    out = torch.empty_like(a) if out is None else _limbs(out, "out")
+    ovf = torch.empty(ba, dtype=torch.int32, device=a.device)
     _check(lib().bigint_add6(_p(out), _p(ovf), _p(a), _p(b), n, ba, _stream()), "bigint_add6")
-    return out, ovf
+    return _back(out, wd), ovf
 
 
 def poly(a, b):
     """The Poly workload: ((a a + b)(b b + b) + a b) mod B^n row by row."""
     torch = _torch()
+    wd = _wide(a)
     a, b = _limbs(a, "a"), _limbs(b, "b")
     ba, n = _rows(a)
     if b.shape != a.shape:
         raise ValueError("shape mismatch")
     out = torch.empty_like(a)
     _check(lib().bigint_poly(_p(out), _p(a), _p(b), n, ba, _stream()), "bigint_poly")
-    return out
+    return _back(out, wd)
 
 
 def mfma_config(na: int, nb: int):
