@@ -198,10 +198,12 @@ int bigint_plan_destroy(bigint_plan_t plan);
 /* Ragged multiplication: out instance i = a instance i * b instance i, with
  * out_off[i+1]-out_off[i] == (a_off[i+1]-a_off[i]) + (b_off[i+1]-b_off[i]);
  * the limb counts must equal those given to bigint_plan_create (not checked
- * on the device).  All instances run in one persistent launch fed by a
- * device work queue, captured into a hipGraph and replayed on later calls
- * with the same pointers (unless BIGINT_PLAN_NO_GRAPH).  Offsets are DEVICE
- * int64 arrays of length batch+1. */
+ * on the device).  The instances run largest first, one work-group each, in
+ * a few launches (one per run of instances sharing a tile configuration,
+ * each also taking some smaller instances to fill its end); the launches are
+ * captured into a hipGraph and replayed on later calls with the same
+ * pointers (unless BIGINT_PLAN_NO_GRAPH).  Offsets are DEVICE int64 arrays
+ * of length batch+1. */
 int bigint_mul_ragged(uint32_t* out, const int64_t* out_off, const uint32_t* a,
                       const int64_t* a_off, const uint32_t* b,
                       const int64_t* b_off, int64_t batch, bigint_plan_t plan,

@@ -4,6 +4,7 @@
 #include <cstring>
 #include <mutex>
 #include <numeric>
+#include <queue>
 #include <string>
 #include <vector>
 
@@ -279,8 +280,9 @@ struct bigint_plan_s {
   // multiplication schedule
   bi::QueueItem* d_queue = nullptr;
   uint32_t* d_counter = nullptr;
-  size_t lds = 0;
-  int waves = 8, grid = 0;
+  std::vector<bi::RaggedClass> cls;  // MFMA: one launch per tile configuration
+  size_t lds = 0;                    // plain
+  int grid = 0;
   bool plain = false;
   int cap_u = 0, cap_v = 0;   // division: largest dividend / divisor
   // workspace
@@ -305,37 +307,88 @@ static int plan_build_mul(bigint_plan_s* p) {
     if (plain && p->la[i] + p->lb[i] > 32768) return BIGINT_EUNSUPPORTED;
   p->plain = plain;
   // largest first (cost ~ digit products), ties by index
+  auto cost = [&](int64_t i) { return p->la[i] * p->lb[i]; };
   std::vector<int64_t> idx(B);
   std::iota(idx.begin(), idx.end(), 0);
-  std::stable_sort(idx.begin(), idx.end(), [&](int64_t x, int64_t y) {
-    return p->la[x] * p->lb[x] > p->la[y] * p->lb[y];
-  });
+  std::stable_sort(idx.begin(), idx.end(), [&](int64_t x, int64_t y) { return cost(x) > cost(y); });
   std::vector<QueueItem> q(B);
-  size_t lds = 0;
-  for (int64_t t = 0; t < B; ++t) {
-    const int64_t i = idx[t];
-    q[t].inst = (int32_t)i;
-    if (plain) {
-      q[t].cfg = 0;
-      lds = std::max(lds, plain_lds((int)p->la[i], (int)p->lb[i]));
-    } else {
-      MfmaCfg c = default_mfma_cfg((int)p->la[i], (int)p->lb[i]);
-      c.waves = p->waves;
-      q[t].cfg = ragged_cfg_id(c);
-      lds = std::max(lds, mfma_lds((int)p->la[i], (int)p->lb[i], c));
+  if (plain) {
+    size_t lds = 0;
+    for (int64_t t = 0; t < B; ++t) {
+      q[t] = QueueItem{(int32_t)idx[t], 0};
+      lds = std::max(lds, plain_lds((int)p->la[idx[t]], (int)p->lb[idx[t]]));
     }
+    p->lds = lds;
+    p->grid = (int)std::max<int64_t>(1, std::min<int64_t>(B, (int64_t)num_cus()));
+  } else {
+    // Segments, one launch each.  A segment starts with the largest remaining
+    // instance; its core is the run of instances with the same tile
+    // configuration and the same LDS-bound work-groups per CU.  The core is
+    // list-scheduled largest first on the launch's resident work-groups (as
+    // in-order dispatch will run it); then the following instances of the
+    // same digit width and no more strips per band join the segment as long
+    // as each fits in the idle time before the core's last work-group ends.
+    struct It {
+      int64_t i;
+      MfmaCfg c;
+      int lpc;  // work-groups per CU its LDS allows
+    };
+    std::vector<It> it(B);
+    for (int64_t t = 0; t < B; ++t) {
+      const int64_t i = idx[t];
+      const MfmaCfg c = default_mfma_cfg((int)p->la[i], (int)p->lb[i]);
+      const size_t l = mfma_lds((int)p->la[i], (int)p->lb[i], c);
+      it[t] = It{i, c, (int)std::min<size_t>(4, 163840 / std::max<size_t>(l, 1))};
+    }
+    std::vector<RaggedClass> cls;
+    int64_t pos = 0;
+    while (pos < B) {
+      const It& h = it[pos];
+      RaggedClass k{ragged_cfg_id(h.c), h.c.waves, (int)pos, 0, 0};
+      int64_t end = pos;
+      while (end < B && it[end].c.P == h.c.P && it[end].c.dw == h.c.dw &&
+             it[end].c.waves == h.c.waves && it[end].lpc == h.lpc) {
+        const int64_t i = it[end].i;
+        k.lds = std::max(k.lds, mfma_lds((int)p->la[i], (int)p->lb[i], MfmaCfg{h.c.P, k.waves, h.c.dw}));
+        ++end;
+      }
+      const int slots = ragged_slots(k.cfg, k.waves, k.lds);
+      if (slots < 1) return BIGINT_EUNSUPPORTED;
+      std::priority_queue<double, std::vector<double>, std::greater<double>> fin;
+      for (int m = 0; m < slots; ++m) fin.push(0.0);
+      double span = 0.0;
+      for (int64_t t = pos; t < end; ++t) {
+        const double f = fin.top() + (double)cost(it[t].i);
+        fin.pop();
+        fin.push(f);
+        span = std::max(span, f);
+      }
+      while (end < B) {
+        const It& f = it[end];
+        if (f.c.dw != h.c.dw || f.c.P > h.c.P) break;
+        const MfmaCfg fc{f.c.P, k.waves, f.c.dw};
+        if (mfma_lds((int)p->la[f.i], (int)p->lb[f.i], fc) > k.lds) break;
+        const double t0 = fin.top() + (double)cost(f.i);
+        if (t0 > span) break;
+        fin.pop();
+        fin.push(t0);
+        ++end;
+      }
+      k.count = (int)(end - pos);
+      for (int64_t t = pos; t < end; ++t) q[t] = QueueItem{(int32_t)it[t].i, it[t].c.P};
+      cls.push_back(k);
+      pos = end;
+    }
+    p->cls = cls;
   }
-  p->lds = lds;
-  // work-groups per CU allowed by LDS (registers allow one 8-wave group)
-  const int per_cu = plain ? 1 : std::max(1, std::min<int>(2, (int)(163840 / std::max<size_t>(lds, 1))));
-  p->grid = (int)std::min<int64_t>(B, (int64_t)num_cus() * per_cu);
-  if (p->grid < 1) p->grid = 1;
   if (B > 0) {
     BI_HIP(hipMalloc(&p->d_queue, sizeof(QueueItem) * B));
     BI_HIP(hipMemcpy(p->d_queue, q.data(), sizeof(QueueItem) * B, hipMemcpyHostToDevice));
   }
-  BI_HIP(hipMalloc(&p->d_counter, 64));
-  BI_HIP(hipMemset(p->d_counter, 0, 64));
+  if (plain) {  // the plain kernel's queue head
+    BI_HIP(hipMalloc(&p->d_counter, 64));
+    BI_HIP(hipMemset(p->d_counter, 0, 64));
+  }
   p->ws_need = 0;  // the multiply needs no workspace beyond LDS
   return BIGINT_OK;
 }
@@ -360,8 +413,7 @@ static int plan_build_div(bigint_plan_s* p) {
   std::stable_sort(idx.begin(), idx.end(), [&](int64_t x, int64_t y) { return cost(x) > cost(y); });
   std::vector<int32_t> q(B);
   for (int64_t t = 0; t < B; ++t) q[t] = (int32_t)idx[t];
-  p->grid = (int)std::max<int64_t>(
-      1, std::min<int64_t>(B, (int64_t)num_cus() * div_groups_per_cu(p->cap_u, p->cap_v)));
+  p->grid = div_chunk(p->cap_u, p->cap_v, B);
   if (B > 0) {
     BI_HIP(hipMalloc(&p->d_queue, sizeof(int32_t) * B));
     BI_HIP(hipMemcpy(p->d_queue, q.data(), sizeof(int32_t) * B, hipMemcpyHostToDevice));
@@ -442,8 +494,11 @@ int bigint_mul_ragged(uint32_t* out, const int64_t* out_off, const uint32_t* a,
   if (overlap(out, ob, a, (size_t)ta * 4) || overlap(out, ob, b, (size_t)tb * 4)) return BIGINT_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   auto launch = [&](hipStream_t ls) {
-    return launch_mul_ragged(out, out_off, a, a_off, b, b_off, plan->d_queue, batch,
-                             plan->d_counter, plan->plain, plan->lds, plan->waves, plan->grid, ls);
+    if (plan->plain)
+      return launch_mul_plain_ragged(out, out_off, a, a_off, b, b_off, plan->d_queue, batch,
+                                     plan->d_counter, plan->lds, plan->grid, ls);
+    return launch_mul_ragged(out, out_off, a, a_off, b, b_off, plan->d_queue, plan->cls.data(),
+                             (int)plan->cls.size(), ls);
   };
   if ((plan->flags & BIGINT_PLAN_NO_GRAPH) || s == nullptr) return launch(s);
   const void* key[6] = {out, out_off, a, a_off, b, b_off};
@@ -472,8 +527,7 @@ static int divmod_launch_alloc(uint32_t* q, uint32_t* r, int32_t* status, const 
                                hipStream_t s) {
   const int cap_u = h_inv >= 0 ? h_inv + 2 : (int)nu;
   const int cap_v = (int)nv;
-  const int grid =
-      (int)std::min<int64_t>(batch, (int64_t)num_cus() * div_groups_per_cu(cap_u, cap_v));
+  const int grid = div_chunk(cap_u, cap_v, batch);
   const size_t bytes = div_ws_bytes(cap_u, cap_v, grid);
   void* ws = nullptr;
   hipError_t e = hipMallocAsync(&ws, bytes, s);

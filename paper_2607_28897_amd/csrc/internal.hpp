@@ -44,28 +44,50 @@ size_t mfma_lds(int na, int nb, MfmaCfg cfg);
 size_t plain_lds(int na, int nb);
 
 // ---- ragged (persistent, queue-fed) -------------------------------------------
-// One queue entry per instance, largest first.  cfg_id selects the tile
-// configuration for that instance.
+// One queue entry per instance, largest first.  MFMA plans cut the queue
+// into segments, one launch each (see RaggedClass); the plain plan has one.
 struct QueueItem {
   int32_t inst;
-  int32_t cfg;   // MFMA: ragged_cfg_id of the instance's configuration; plain: 0
+  int32_t cfg;   // MFMA: strips per band (4, 8, 16) of the instance; plain: 0
 };
 
+// One launch of a ragged MFMA plan: queue entries [first, first + count), one
+// work-group each, run by the kernel of the segment's leading tile
+// configuration (digit width and strips per band of cfg), which also takes
+// entries of the same digit width with fewer strips per band.
+struct RaggedClass {
+  int cfg;        // ragged_cfg_id of the leading configuration
+  int waves;      // waves per work-group
+  int first;      // first queue entry of the segment
+  int count;      // entries
+  size_t lds;     // dynamic LDS bytes (largest instance of the segment)
+};
+
+// work-groups of the segment kernel resident on the device at once (0: the
+// configuration or LDS size is not supported)
+int ragged_slots(int cfg_id, int waves, size_t lds);
 int launch_mul_ragged(uint32_t* out, const int64_t* out_off, const uint32_t* a,
                       const int64_t* a_off, const uint32_t* b, const int64_t* b_off,
-                      const QueueItem* queue, int64_t nitems, uint32_t* counter, bool plain,
-                      size_t lds, int waves, int grid, hipStream_t s);
+                      const QueueItem* queue, const RaggedClass* cls, int ncls, hipStream_t s);
+int launch_mul_plain_ragged(uint32_t* out, const int64_t* out_off, const uint32_t* a,
+                            const int64_t* a_off, const uint32_t* b, const int64_t* b_off,
+                            const QueueItem* queue, int64_t nitems, uint32_t* counter, size_t lds,
+                            int grid, hipStream_t s);
 
 int launch_mfma_rate(int32_t* out, int blocks, int iters, int toggle, hipStream_t s);
 
 // ---- division -------------------------------------------------------------------
-size_t div_ws_bytes(int cap_u, int cap_v, int grid);
+// A division launch runs at most `chunk` work-groups at once (one workspace
+// slot each, div_ws_bytes(cap_u, cap_v, chunk) bytes in all); larger batches
+// go in consecutive launches.
+size_t div_ws_bytes(int cap_u, int cap_v, int slots);
 size_t div_lds_bytes(int cap_u, int cap_v);
 int div_groups_per_cu(int cap_u, int cap_v);
+int div_chunk(int cap_u, int cap_v, int64_t batch);
 int launch_divmod(uint32_t* q, const int64_t* q_off, uint32_t* r, const int64_t* r_off,
                   int32_t* status, const uint32_t* u, const int64_t* u_off, int nu,
                   const uint32_t* v, const int64_t* v_off, int nv, const int32_t* queue,
-                  int64_t nitems, void* ws, int cap_u, int cap_v, int grid, int h_inv,
+                  int64_t nitems, void* ws, int cap_u, int cap_v, int chunk, int h_inv,
                   int32_t* adjust, hipStream_t s);
 
 }  // namespace bi
