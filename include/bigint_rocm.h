@@ -152,9 +152,10 @@ int bigint_mul(uint32_t* out, const uint32_t* a, int64_t na, const uint32_t* b,
  *   is BIGINT_EINVAL.
  * bigint_poly: the Poly benchmark (Table tab-mul) in the paper's fixed
  *   precision: out[i] = ((a a + b)(b b + b) + a b) mod B^n, four products
- *   mod B^n and three additions per instance in one persistent launch; the
- *   call allocates 2n limbs of workspace per work-group on `stream`
- *   (stream-ordered) and frees it the same way.  1 <= n <=
+ *   mod B^n and three additions per instance, one work-group per instance;
+ *   the call allocates 2n limbs of workspace for each work-group of a
+ *   launch (at most eight times the resident work-groups per launch) on
+ *   `stream` (stream-ordered) and frees it the same way.  1 <= n <=
  *   BIGINT_MFMA_MAX_LIMBS; out must not overlap a or b. */
 int bigint_mullo(uint32_t* out, const uint32_t* a, const uint32_t* b, int64_t n,
                  int64_t batch, void* stream);

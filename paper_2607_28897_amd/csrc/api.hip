@@ -232,8 +232,8 @@ int bigint_poly(uint32_t* out, const uint32_t* a, const uint32_t* b, int64_t n, 
   cfg.dw = 8;
   if (poly_lds((int)n, cfg) > 163840) return BIGINT_EUNSUPPORTED;
   if (batch == 0) return BIGINT_OK;
-  // a persistent grid of resident work-groups, each owning 2n limbs of workspace
-  const int grid = poly_grid((int)n, batch, cfg);
+  // launches of `grid` work-groups, each owning 2n limbs of workspace
+  const int grid = poly_chunk((int)n, batch, cfg);
   hipStream_t s = (hipStream_t)stream;
   void* ws = nullptr;
   hipError_t e = hipMallocAsync(&ws, (size_t)grid * 2 * n * 4, s);
@@ -331,14 +331,26 @@ static int plan_build_mul(bigint_plan_s* p) {
     struct It {
       int64_t i;
       MfmaCfg c;
-      int lpc;  // work-groups per CU its LDS allows
+      int lpc;  // work-groups per CU its LDS and the kernel's registers allow
+    };
+    // work-groups per CU the registers allow, per (configuration, waves)
+    std::vector<std::pair<int, int>> occ_key;
+    std::vector<int> occ_val;
+    auto reg_occ = [&](int id, int waves) {
+      for (size_t j = 0; j < occ_key.size(); ++j)
+        if (occ_key[j] == std::make_pair(id, waves)) return occ_val[j];
+      const int v = std::max(1, ragged_slots(id, waves, 1024) / std::max(1, num_cus()));
+      occ_key.emplace_back(id, waves);
+      occ_val.push_back(v);
+      return v;
     };
     std::vector<It> it(B);
     for (int64_t t = 0; t < B; ++t) {
       const int64_t i = idx[t];
       const MfmaCfg c = default_mfma_cfg((int)p->la[i], (int)p->lb[i]);
       const size_t l = mfma_lds((int)p->la[i], (int)p->lb[i], c);
-      it[t] = It{i, c, (int)std::min<size_t>(4, 163840 / std::max<size_t>(l, 1))};
+      const int by_lds = (int)std::min<size_t>(4, 163840 / std::max<size_t>(l, 1));
+      it[t] = It{i, c, std::min(by_lds, reg_occ(ragged_cfg_id(c), c.waves))};
     }
     std::vector<RaggedClass> cls;
     int64_t pos = 0;

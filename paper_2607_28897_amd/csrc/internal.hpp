@@ -34,9 +34,9 @@ int launch_mul_kara(uint32_t* out, const uint32_t* a, const uint32_t* b, int64_t
 int launch_add6(uint32_t* out, uint32_t* ovf, const uint32_t* a, const uint32_t* b, int64_t n,
                 int64_t batch, hipStream_t s);
 size_t poly_lds(int n, MfmaCfg cfg);
-int poly_grid(int n, int64_t batch, MfmaCfg cfg);
+int poly_chunk(int n, int64_t batch, MfmaCfg cfg);  // work-groups (workspace slots) per launch
 int launch_poly(uint32_t* out, const uint32_t* a, const uint32_t* b, int64_t n, int64_t batch,
-                uint32_t* ws, int grid, MfmaCfg cfg, hipStream_t s);
+                uint32_t* ws, int chunk, MfmaCfg cfg, hipStream_t s);
 int launch_digits7(uint8_t* out, const uint32_t* a, int64_t n, int64_t D, int64_t batch,
                    hipStream_t s);
 

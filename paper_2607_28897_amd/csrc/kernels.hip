@@ -292,21 +292,25 @@ int launch_add6(uint32_t* out, uint32_t* ovf, const uint32_t* a, const uint32_t*
   return BIGINT_EUNSUPPORTED;
 }
 
-// Poly: ((a*a + b) * (b*b + b) + a*b) mod B^n.  A persistent grid walks the
-// instances; per instance the four products mod B^n run one after another on
-// the MFMA-split multiply (a single call site, so its code is emitted once)
-// with two n-limb temporaries in a global workspace, each followed by its
-// addition on the whole work-group.
+// Poly: ((a*a + b) * (b*b + b) + a*b) mod B^n.  One work-group per instance
+// (instance first + g for work-group g of a launch, workspace slot g): the
+// four products mod B^n run one after another on the MFMA-split multiply (a
+// single call site, so its code is emitted once) with two n-limb temporaries
+// in a global workspace, each followed by its addition on the whole
+// work-group.  (A persistent grid looping over instances was 5-16% slower at
+// 2^15-2^18 bits: the loop kept loop-invariant values live in registers.)
 // Two work-groups per CU need 128 registers (4 waves per SIMD); the 16-strip
 // tiles do not fit that, so they keep one.
 template <int P>
 __global__ __launch_bounds__(512, P == 16 ? 2 : 4) void k_poly(uint32_t* out, const uint32_t* a, const uint32_t* b,
-                                              int n, int64_t batch, uint32_t* ws) {
+                                              int n, int64_t first, int64_t batch, uint32_t* ws) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
   __shared__ uint32_t scratch[32];
   uint32_t* t1 = ws + (int64_t)blockIdx.x * 2 * n;
   uint32_t* t2 = t1 + n;
-  for (int64_t inst = blockIdx.x; inst < batch; inst += gridDim.x) {
+  {
+    const int64_t inst = first + blockIdx.x;
+    if (inst >= batch) return;
     const uint32_t* pa = a + inst * n;
     const uint32_t* pb = b + inst * n;
     uint32_t* po = out + inst * n;
@@ -334,30 +338,38 @@ static const void* poly_kernel(int P) {
   return P == 4 ? (const void*)k_poly<4> : (P == 8 ? (const void*)k_poly<8> : (const void*)k_poly<16>);
 }
 
-// work-groups of the persistent Poly grid: as many as stay resident together
-int poly_grid(int n, int64_t batch, MfmaCfg cfg) {
+// work-groups per Poly launch (one workspace slot each): eight times as many
+// as stay resident together, at most the batch
+int poly_chunk(int n, int64_t batch, MfmaCfg cfg) {
   int per_cu = 1;
   const size_t lds = mfma::lds_bytes<8>(n, n, cfg.waves, cfg.P);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, poly_kernel(cfg.P), 64 * cfg.waves,
+  if (hipFuncSetAttribute(poly_kernel(cfg.P), hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)lds) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, poly_kernel(cfg.P), 64 * cfg.waves,
                                                    lds) != hipSuccess ||
       per_cu < 1)
     per_cu = 1;
-  return (int)std::max<int64_t>(1, std::min<int64_t>(batch, (int64_t)num_cus() * per_cu));
+  return (int)std::max<int64_t>(1, std::min<int64_t>(batch, 8 * (int64_t)num_cus() * per_cu));
 }
 
 int launch_poly(uint32_t* out, const uint32_t* a, const uint32_t* b, int64_t n, int64_t batch,
-                uint32_t* ws, int grid, MfmaCfg cfg, hipStream_t s) {
+                uint32_t* ws, int chunk, MfmaCfg cfg, hipStream_t s) {
   const size_t lds = mfma::lds_bytes<8>((int)n, (int)n, cfg.waves, cfg.P);
   if (lds + 256 > 163840) return BIGINT_EUNSUPPORTED;
+  if (chunk < 1) return BIGINT_EINVAL;
   BI_HIP(hipFuncSetAttribute(poly_kernel(cfg.P), hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)lds));
-  const dim3 gd(grid), bd(64 * cfg.waves);
-  switch (cfg.P) {
-    case 4: hipLaunchKernelGGL(k_poly<4>, gd, bd, lds, s, out, a, b, (int)n, batch, ws); break;
-    case 8: hipLaunchKernelGGL(k_poly<8>, gd, bd, lds, s, out, a, b, (int)n, batch, ws); break;
-    default: hipLaunchKernelGGL(k_poly<16>, gd, bd, lds, s, out, a, b, (int)n, batch, ws); break;
+  // chunks run one after another on the stream, so a workspace slot is never
+  // held by two live work-groups
+  for (int64_t first = 0; first < batch; first += chunk) {
+    const dim3 gd((unsigned)std::min<int64_t>(chunk, batch - first)), bd(64 * cfg.waves);
+    switch (cfg.P) {
+      case 4: hipLaunchKernelGGL(k_poly<4>, gd, bd, lds, s, out, a, b, (int)n, first, batch, ws); break;
+      case 8: hipLaunchKernelGGL(k_poly<8>, gd, bd, lds, s, out, a, b, (int)n, first, batch, ws); break;
+      default: hipLaunchKernelGGL(k_poly<16>, gd, bd, lds, s, out, a, b, (int)n, first, batch, ws); break;
+    }
+    BI_LAUNCH_CHECK();
   }
-  BI_LAUNCH_CHECK();
   return BIGINT_OK;
 }
 
