@@ -338,10 +338,22 @@ def divmod_mode(torch, bi, inputs, args):
     mtotal, _ = time_launches(lambda: mplan(tu, tuo, tu, tuo, out=out, out_off=oo), steps,
                               args.warmup, torch)
     mms = mtotal / steps
+    # per-division counters of the procedure (outside the timed region)
+    _, _, st, cnt = plan.counters(tu, tuo, tv, tvo)
+    cnt = cnt.cpu().numpy()
+
+    def hist(col):
+        vals, counts = np.unique(cnt[:, col], return_counts=True)
+        return {str(int(v)): int(c) for v, c in zip(vals, counts)}
+
     print(json.dumps({"mode": "divmod", "workload": "512 divisions, dividend bits log-uniform in "
                       "[2^16, 2^18], divisor half the limbs", "ms": round(ms, 4),
                       "divs_per_s": round(512 / ms * 1e3, 1),
-                      "same_size_products_ms": round(mms, 4), "div_over_mul": round(ms / mms, 3)}))
+                      "same_size_products_ms": round(mms, 4), "div_over_mul": round(ms / mms, 3),
+                      "all_status_ok": bool((st == 0).all().item()),
+                      "newton_steps_histogram": hist(0),
+                      "fixup_corrections_histogram": hist(1),
+                      "quotient_corrections_histogram": hist(2)}))
     plan.close()
     mplan.close()
 

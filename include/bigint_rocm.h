@@ -244,6 +244,20 @@ int bigint_conv7(int32_t* c, const uint32_t* a, int64_t na, const uint32_t* b,
 int bigint_shinv(uint32_t* w, const uint32_t* v, int64_t nv, int64_t h,
                  int64_t batch, void* stream);
 
+/* bigint_diag_divmod_ragged: bigint_divmod_ragged (same arguments, same
+ * results) that also writes, per division, three counters of the procedure
+ * of Section 5.3 to counts[3*i .. 3*i+2] (device int32, 3*batch, must not
+ * overlap q or r): the Newton steps (`step`) taken, the unit corrections the
+ * exact fix-ups applied to the inverse at every scale, and the corrections
+ * of the final quotient (at most 3; a fourth marks the division
+ * BIGINT_DIV_FAILED).  Divisions that need no Newton iteration (v < B, u < v,
+ * v = 0) report zeros.  Launches directly (no graph). */
+int bigint_diag_divmod_ragged(int32_t* counts, uint32_t* q, const int64_t* q_off,
+                              uint32_t* r, const int64_t* r_off, int32_t* status,
+                              const uint32_t* u, const int64_t* u_off,
+                              const uint32_t* v, const int64_t* v_off,
+                              int64_t batch, bigint_plan_t plan, void* stream);
+
 /* Register-only int8 MFMA rate probe: `blocks` work-groups of 4 waves, each
  * wave issuing 64 v_mfma_i32_16x16x64_i8 per iteration (8 independent
  * accumulators, 16384 multiply-accumulates each) for `iters` iterations, no

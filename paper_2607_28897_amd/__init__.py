@@ -89,6 +89,8 @@ def lib() -> ctypes.CDLL:
             "bigint_add6": ([_vp, _vp, _vp, _vp, _i64, _i64, _vp], _int),
             "bigint_poly": ([_vp, _vp, _vp, _i64, _i64, _vp], _int),
             "bigint_diag_mfma_rate": ([_vp, _i64, _i64, _int, _vp], _int),
+            "bigint_diag_divmod_ragged": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64,
+                                           _vp, _vp], _int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -380,3 +382,16 @@ class DivPlan(_Plan):
                                           _p(u_off), _p(v), _p(v_off), self.batch, self._h,
                                           _stream()), "bigint_divmod_ragged")
         return q, r, st
+
+    def counters(self, u, u_off, v, v_off):
+        """The same division, plus per division [Newton steps, fix-up unit
+        corrections, quotient corrections] as an int32 [batch, 3] tensor."""
+        torch = _torch()
+        q = torch.empty(int(self.len_a.sum()), dtype=u.dtype, device=u.device)
+        r = torch.empty(int(self.len_b.sum()), dtype=u.dtype, device=u.device)
+        st = torch.empty(self.batch, dtype=torch.int32, device=u.device)
+        cnt = torch.empty((self.batch, 3), dtype=torch.int32, device=u.device)
+        _check(lib().bigint_diag_divmod_ragged(_p(cnt), _p(q), _p(u_off), _p(r), _p(v_off), _p(st),
+                                               _p(u), _p(u_off), _p(v), _p(v_off), self.batch,
+                                               self._h, _stream()), "bigint_diag_divmod_ragged")
+        return q, r, st, cnt

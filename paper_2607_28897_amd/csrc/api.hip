@@ -578,10 +578,10 @@ int bigint_shinv(uint32_t* w, const uint32_t* v, int64_t nv, int64_t h, int64_t 
                              (hipStream_t)stream);
 }
 
-int bigint_divmod_ragged(uint32_t* q, const int64_t* q_off, uint32_t* r, const int64_t* r_off,
+static int divmod_ragged(uint32_t* q, const int64_t* q_off, uint32_t* r, const int64_t* r_off,
                          int32_t* status, const uint32_t* u, const int64_t* u_off,
                          const uint32_t* v, const int64_t* v_off, int64_t batch,
-                         bigint_plan_t plan, void* stream) {
+                         bigint_plan_t plan, int32_t* counts, hipStream_t s) {
   if (!plan || plan->op != BIGINT_OP_DIVMOD || batch != plan->batch) return BIGINT_EINVAL;
   if (batch == 0) return BIGINT_OK;
   if (!q || !q_off || !r || !r_off || !u || !u_off || !v || !v_off) return BIGINT_EINVAL;
@@ -590,7 +590,9 @@ int bigint_divmod_ragged(uint32_t* q, const int64_t* q_off, uint32_t* r, const i
   if (overlap(q, tu * 4, u, tu * 4) || overlap(q, tu * 4, v, tv * 4) || overlap(r, tv * 4, u, tu * 4) ||
       overlap(r, tv * 4, v, tv * 4) || overlap(q, tu * 4, r, tv * 4))
     return BIGINT_EINVAL;
-  hipStream_t s = (hipStream_t)stream;
+  if (counts && (overlap(counts, (size_t)batch * 12, q, tu * 4) ||
+                 overlap(counts, (size_t)batch * 12, r, tv * 4)))
+    return BIGINT_EINVAL;
   if (!plan->ws) {
     BI_HIP(hipMalloc(&plan->ws, plan->ws_need));
     plan->ws_bytes = plan->ws_need;
@@ -598,7 +600,24 @@ int bigint_divmod_ragged(uint32_t* q, const int64_t* q_off, uint32_t* r, const i
   }
   return launch_divmod(q, q_off, r, r_off, status, u, u_off, 0, v, v_off, 0,
                        reinterpret_cast<const int32_t*>(plan->d_queue), batch, plan->ws,
-                       plan->cap_u, plan->cap_v, plan->grid, -1, nullptr, s);
+                       plan->cap_u, plan->cap_v, plan->grid, -1, counts, s);
+}
+
+int bigint_divmod_ragged(uint32_t* q, const int64_t* q_off, uint32_t* r, const int64_t* r_off,
+                         int32_t* status, const uint32_t* u, const int64_t* u_off,
+                         const uint32_t* v, const int64_t* v_off, int64_t batch,
+                         bigint_plan_t plan, void* stream) {
+  return divmod_ragged(q, q_off, r, r_off, status, u, u_off, v, v_off, batch, plan, nullptr,
+                       (hipStream_t)stream);
+}
+
+int bigint_diag_divmod_ragged(int32_t* counts, uint32_t* q, const int64_t* q_off, uint32_t* r,
+                              const int64_t* r_off, int32_t* status, const uint32_t* u,
+                              const int64_t* u_off, const uint32_t* v, const int64_t* v_off,
+                              int64_t batch, bigint_plan_t plan, void* stream) {
+  if (!counts) return BIGINT_EINVAL;
+  return divmod_ragged(q, q_off, r, r_off, status, u, u_off, v, v_off, batch, plan, counts,
+                       (hipStream_t)stream);
 }
 
 int bigint_diag_mfma_rate(int32_t* scratch, int64_t blocks, int64_t iters, int toggle,

@@ -198,6 +198,7 @@ __host__ __device__ inline Bufs carve_bufs(uint32_t* ws, int nu, int nv) {
 
 // Exact fix-up at scale c: given w (lw limbs, approximately floor(B^c / v)),
 // make w = floor(B^c / v) and E = B^c - v w in [0, v).  Returns the new lw.
+// adjust (nullable): diagnostic counters; adjust[1] += the unit steps of w.
 __device__ inline int fixup(const uint32_t* v, int k1, int c, Bufs& bf, int lw, Shared* sh,
                             char* smem, int* adjust) {
   // P = v * w
@@ -262,7 +263,7 @@ __device__ inline int fixup(const uint32_t* v, int k1, int c, Bufs& bf, int lw, 
       wg_arith<true>(bf.E, le, v, k1, bf.E, le, sh);
       neg = false;
       ++adj;
-      if (adjust) *adjust += adj;
+      if (adjust) adjust[1] += adj;
       return lw;
     }
   }
@@ -293,7 +294,7 @@ __device__ inline int fixup(const uint32_t* v, int k1, int c, Bufs& bf, int lw, 
     }
     ++adj;
   }
-  if (adjust) *adjust += adj;
+  if (adjust) adjust[1] += adj;
   if (adj >= kMaxAdjust) sh->failed = 1u;
   // lw stays an upper bound of w's length (a leading zero limb after w -= 1
   // is harmless to every later operation)
@@ -302,6 +303,7 @@ __device__ inline int fixup(const uint32_t* v, int k1, int c, Bufs& bf, int lw, 
 
 // w = floor(B^h / v) for a divisor with k1 >= 2 significant limbs and h >= k1.
 // Leaves w in bf.W and returns its limb count; E = B^h - v w.
+// adjust (nullable): adjust[0] += Newton steps, adjust[1] += fix-up unit steps.
 __device__ inline int shifted_inverse(const uint32_t* v, int k1, int h, Bufs& bf, Shared* sh,
                                       char* smem, int* adjust) {
   const int k = k1 - 1;
@@ -357,6 +359,7 @@ __device__ inline int shifted_inverse(const uint32_t* v, int k1, int h, Bufs& bf
     const int c = cur - sdrop;
     lw = fixup(V, t, c, bf, lw, sh, smem, adjust);
     if (cur == h) break;
+    if (adjust) adjust[0] += 1;
     // Y = w * e (e < V has at most t limbs; a zero e costs one product of zeros)
     const int le = t;
     int lnew;
@@ -391,6 +394,8 @@ __device__ inline int shifted_inverse(const uint32_t* v, int k1, int h, Bufs& bf
 
 // q[0..nq), r[0..nr) = divmod(u[0..nu), v[0..nv)); returns the status.
 // With inverse_only, writes floor(B^h_inv / v) into q[0..nq) instead.
+// adjust (nullable, 3 ints): Newton steps, fix-up unit steps, quotient
+// corrections, each added to.
 __device__ inline int wg_divmod(uint32_t* q, int nq, uint32_t* r, int nr, const uint32_t* u, int nu,
                                 const uint32_t* v, int nv, Bufs bf, Shared* sh, char* smem,
                                 bool inverse_only, int h_inv, int* adjust) {
@@ -457,7 +462,7 @@ __device__ inline int wg_divmod(uint32_t* q, int nq, uint32_t* r, int nr, const 
     if (wg_cmp(bf.E, lr, v, k1, lr, sh) < 0) break;
     wg_arith<true>(bf.E, lr, bf.E, lr, v, k1, sh);
     wg_arith1<false>(bf.U2, lq2 + 1, bf.U2, lq2 + 1, 1u, sh);
-    if (adjust) *adjust += 1;
+    if (adjust) adjust[2] += 1;
     if (rounds == 3 && threadIdx.x == 0) sh->failed = 1u;
   }
   wg_shr_copy(q, nq, bf.U2, lq2 + 1, 0);

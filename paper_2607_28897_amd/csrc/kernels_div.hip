@@ -18,6 +18,8 @@ constexpr int kDivThreads = 512;
 // measured 11% slower on 512 ragged divisions: the loop made the compiler
 // keep loop-invariant values live across the whole division.)
 // h_inv >= 0 selects the shifted-inverse diagnostic: q[i] = floor(B^h_inv / v).
+// adjust (nullable): 3 int32 per instance, the division's counters (Newton
+// steps, fix-up unit steps, quotient corrections).
 __global__ __launch_bounds__(kDivThreads, 4) void k_divmod(uint32_t* q, const int64_t* q_off, uint32_t* r,
                                                 const int64_t* r_off, int32_t* status,
                                                 const uint32_t* u, const int64_t* u_off, int nu,
@@ -45,12 +47,16 @@ __global__ __launch_bounds__(kDivThreads, 4) void k_divmod(uint32_t* q, const in
     lq = h_inv >= 0 ? h_inv + 1 : nu; qo = i * (int64_t)lq;
     lr = nv; ro = i * (int64_t)nv;
   }
-  int adj = 0;
+  int cnt[3] = {0, 0, 0};
   const int st = div::wg_divmod(q + qo, lq, r ? r + ro : nullptr, lr, u ? u + uo : nullptr, lu,
-                                v + vo, lv, bf, &sh, smem, h_inv >= 0, h_inv, &adj);
+                                v + vo, lv, bf, &sh, smem, h_inv >= 0, h_inv, cnt);
   if (threadIdx.x == 0) {
     if (status) status[i] = st;
-    if (adjust) adjust[i] = adj;
+    if (adjust) {
+      adjust[3 * i] = cnt[0];
+      adjust[3 * i + 1] = cnt[1];
+      adjust[3 * i + 2] = cnt[2];
+    }
   }
 }
 

@@ -137,3 +137,62 @@ def test_divisor_structures(bi, orc, nu, nv):
     u[5, :] = 0
     u[5, -1] = 1                                   # u = B^(nu-1)
     _check_batch(bi, orc, u, v)
+
+
+def _newton_steps(k1, h):
+    """Steps of the shifted-inverse schedule (start at scale k1 + 1, grow by
+    m = min(h - cur, cur - k1) limbs per step until the scale reaches h)."""
+    cur = min(k1 + 1, h)
+    steps = 0
+    while cur < h:
+        cur += min(h - cur, cur - k1)
+        steps += 1
+    return steps
+
+
+def _prec(x):
+    nz = np.nonzero(x)[0]
+    return int(nz[-1]) + 1 if len(nz) else 0
+
+
+def test_ragged_counters(bi, orc):
+    """The diagnostic entry point gives the same bytes as the plain ragged
+    call, Newton step counts that follow the schedule, bounded fix-up and
+    quotient corrections, and zeros where no Newton iteration runs."""
+    import torch
+    g = np.random.default_rng(77)
+    shapes = [(3, 2), (5, 2), (40, 20), (100, 3), (257, 128), (1000, 500), (2000, 1000),
+              (64, 64), (9, 1), (30, 4), (300, 299)]
+    us, vs = [], []
+    for nu, nv in shapes:
+        us.append(rand_limbs(g, 1, nu)[0])
+        v = rand_limbs(g, 1, nv)[0]
+        v[-1] = max(v[-1], 1)
+        vs.append(v)
+    us[7][-1] = 0                      # u < v (same limb count, smaller top limb)
+    vs[7][-1] = 0xFFFFFFFF
+    vs[9][:] = 0                       # v = 0
+    nu = np.array([len(x) for x in us], np.int64)
+    nv = np.array([len(x) for x in vs], np.int64)
+    u_off = np.concatenate([[0], np.cumsum(nu)]).astype(np.int64)
+    v_off = np.concatenate([[0], np.cumsum(nv)]).astype(np.int64)
+    U, V = np.concatenate(us), np.concatenate(vs)
+    tuo, tvo = torch.from_numpy(u_off).cuda(), torch.from_numpy(v_off).cuda()
+    plan = bi.DivPlan(nu, nv)
+    q0, r0, s0 = plan(dev(U), tuo, dev(V), tvo)
+    q1, r1, s1, cnt = plan.counters(dev(U), tuo, dev(V), tvo)
+    assert torch.equal(q0, q1) and torch.equal(r0, r1) and torch.equal(s0, s1)
+    q, r, st, cnt = host(q1), host(r1), s1.cpu().numpy(), cnt.cpu().numpy()
+    for i in range(len(shapes)):
+        wq, wr, ws = orc.divmod1(us[i], vs[i])
+        assert st[i] == ws, i
+        assert np.array_equal(q[u_off[i]:u_off[i + 1]], wq), i
+        assert np.array_equal(r[v_off[i]:v_off[i + 1]], wr), i
+        k1, h = _prec(vs[i]), _prec(us[i])
+        if k1 <= 1 or h < k1:
+            assert cnt[i].tolist() == [0, 0, 0], i
+            continue
+        assert cnt[i, 0] == _newton_steps(k1, h), (i, cnt[i])
+        assert 0 <= cnt[i, 1] <= 4 * (cnt[i, 0] + 1), (i, cnt[i])
+        assert 0 <= cnt[i, 2] <= 3, (i, cnt[i])
+    plan.close()
