@@ -26,6 +26,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "2^19-bit muls/s on 1 GPU, MFMA-split vs plain u64 kernel, bit-exact"
+# one v_mad_u64_u32 (32x32-bit product added to 64 bits) per lane per cycle:
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (the register-only probe of
+# --mode mfma-peak reaches 34.8 of it at about 2.1 GHz)
+MAD_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 INT8_PEAK_TOPS = 5000.0      # MI355X dense int8 MFMA, TOP/s (2 ops per MAC)
 HBM_PEAK_GBS = 8000.0
 
@@ -229,6 +233,14 @@ def main():
             "unit": "muls/s",
             "ms_per_step": round(p_total / p_steps, 4),
             "steps": p_steps,
+            "roofline": {
+                "bound": "alu",
+                "achieved": round(batch * n * n / (p_total / p_steps * 1e-3) / 1e12, 2),
+                "peak": round(MAD_PEAK_TOPS, 1),
+                "unit": "10^12 v_mad_u64_u32/s",
+                "frac": round(batch * n * n / (p_total / p_steps * 1e-3) / 1e12 / MAD_PEAK_TOPS, 4),
+                "algorithmic_unit": "n^2 = 16384^2 32x32-bit products (4 per 64x64-bit digit product) per 2^19-bit product",
+            },
         },
         "mfma_equals_plain": same,
         "karatsuba": {
@@ -264,7 +276,8 @@ def peak_mode(torch, bi):
     """Achievable int8 MFMA rate with no memory traffic (v_mfma_i32_16x16x64_i8,
     8 independent accumulators per wave, 64 per loop round), for 4..32 waves
     per CU, with constant operands and with operands whose bits change every
-    round (as random digits do), and the shader clock that goes with it."""
+    round (as random digits do); then the rate of the plain kernel's
+    v_mad_u64_u32 (8 independent chains per lane), in 10^12 operations/s."""
     import ctypes
     L = bi.lib()
     out = torch.empty(8192 * 256, dtype=torch.int32, device="cuda")
@@ -287,6 +300,21 @@ def peak_mode(torch, bi):
             macs = blocks * 4 * iters * 64 * 16384
             key = ("toggling" if toggle else "constant") + f"_{4 * per_cu}_waves_per_cu_TOPs"
             res[key] = round(2 * macs / ms / 1e9, 1)
+    # the plain kernel's inner operation: 32x32-bit products added to 64 bits
+    out64 = torch.empty(8192 * 256, dtype=torch.int64, device="cuda")
+    for per_cu in (1, 2, 4, 8):
+        blocks, iters = ncu * per_cu, 1000
+        L.bigint_diag_mad_rate(ctypes.c_void_p(out64.data_ptr()), blocks, 20, s)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        rc = L.bigint_diag_mad_rate(ctypes.c_void_p(out64.data_ptr()), blocks, iters, s)
+        e1.record()
+        torch.cuda.synchronize()
+        if rc:
+            raise bi.BigIntError(rc, "bigint_diag_mad_rate")
+        ms = e0.elapsed_time(e1)
+        res[f"mad_u64_u32_{4 * per_cu}_waves_per_cu_Tops"] = round(blocks * 256 * iters * 64 / ms / 1e9, 2)
     print(json.dumps({"mode": "mfma-peak", "cus": ncu, **res}))
 
 
@@ -368,7 +396,9 @@ def addsub_mode(torch, bi, inputs, args):
     """1-Add, 1-Sub and 6-Add in GB/s on the paper's addition datasets
     (NumBits x NumInsts = 2^32, Table tab-add; bytes = 3 NumInsts NumBits / 8,
     each input and the result once), and on the 2^17-bit configuration
-    (1024 pairs, half carry-adversarial)."""
+    (1024 pairs, half carry-adversarial; 48 MiB, which fits the 256 MB
+    Infinity Cache: hot = back-to-back launches, cold = each launch after
+    512 MiB of other writes)."""
     g = torch.Generator(device="cuda")
     g.manual_seed(1005)
     res = {"mode": "addsub", "unit": "GB/s", "rows": []}
@@ -397,6 +427,22 @@ def addsub_mode(torch, bi, inputs, args):
                      ("add6", lambda: bi.add6(a, b, out=out))):
         total, _ = time_launches(fn, steps * 5, args.warmup, torch)
         cfg[name] = round(byts / (total / (steps * 5) * 1e-3) / 1e9, 1)
+    # cold: 512 MiB written before every launch (twice the 256 MB Infinity
+    # Cache), each launch timed alone with events
+    flush = torch.empty(2**27, dtype=torch.int32, device="cuda")
+    for name, fn in (("add", lambda: bi.add(a, b, out=out)), ("sub", lambda: bi.sub(a, b, out=out))):
+        fn()
+        t = 0.0
+        for i in range(steps * 5):
+            flush.fill_(i)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            t += e0.elapsed_time(e1)
+        cfg[name + "_cold"] = round(byts / (t / (steps * 5) * 1e-3) / 1e9, 1)
+    del flush
     res["pairs_2e17_mixed"] = cfg
     print(json.dumps(res))
 
@@ -424,14 +470,20 @@ def poly_mode(torch, bi, args):
 
 
 def kernel_sha():
-    """Hash of the sources of the MFMA multiply (to know whether counters
-    taken earlier still describe the current kernel)."""
+    """Hash of the sources of the uniform MFMA multiply kernel k_mul_mfma (its
+    device headers and its own definition and launcher in kernels.hip), to
+    know whether counters taken earlier still describe the current kernel."""
     import hashlib
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2607_28897_amd", "csrc")
-    for f in ("common.hpp", "dev_addsub.hpp", "dev_mul_mfma.hpp", "kernels.hip"):
+    for f in ("common.hpp", "dev_addsub.hpp", "dev_mul_mfma.hpp"):
         with open(os.path.join(d, f), "rb") as fh:
             h.update(fh.read())
+    with open(os.path.join(d, "kernels.hip"), "r") as fh:
+        src = fh.read()
+    i = src.index("__global__ __launch_bounds__(512) void k_mul_mfma(")
+    j = src.index("// coef != nullptr (raw coefficients)", i)
+    h.update(src[i:j].encode())
     return h.hexdigest()[:16]
 
 

@@ -268,6 +268,14 @@ int bigint_diag_divmod_ragged(int32_t* counts, uint32_t* q, const int64_t* q_off
 int bigint_diag_mfma_rate(int32_t* scratch, int64_t blocks, int64_t iters, int toggle,
                           void* stream);
 
+/* Register-only rate probe of the plain multiply's inner operation, the
+ * 32x32-bit product added to a 64-bit value (v_mad_u64_u32): `blocks`
+ * work-groups of 4 waves, each lane running 8 independent chains of 64 such
+ * operations per iteration for `iters` iterations, no memory traffic.
+ * scratch: blocks*256 uint64 (results kept so the work is not removed).
+ * Time it with events on `stream`: blocks*256*iters*64 operations. */
+int bigint_diag_mad_rate(uint64_t* scratch, int64_t blocks, int64_t iters, void* stream);
+
 /* Tile parameters of the MFMA multiply used by the next calls on this thread
  * (strips per wave band: 4, 8 or 16; waves per work-group: 4 or 8; digit
  * width: 7 or 8 bits); 0 keeps the tuned default.  Plans read the tuned

@@ -89,6 +89,7 @@ def lib() -> ctypes.CDLL:
             "bigint_add6": ([_vp, _vp, _vp, _vp, _i64, _i64, _vp], _int),
             "bigint_poly": ([_vp, _vp, _vp, _i64, _i64, _vp], _int),
             "bigint_diag_mfma_rate": ([_vp, _i64, _i64, _int, _vp], _int),
+            "bigint_diag_mad_rate": ([_vp, _i64, _i64, _vp], _int),
             "bigint_diag_divmod_ragged": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64,
                                            _vp, _vp], _int),
         }

@@ -627,6 +627,12 @@ int bigint_diag_mfma_rate(int32_t* scratch, int64_t blocks, int64_t iters, int t
   return launch_mfma_rate(scratch, (int)blocks, (int)iters, toggle, (hipStream_t)stream);
 }
 
+int bigint_diag_mad_rate(uint64_t* scratch, int64_t blocks, int64_t iters, void* stream) {
+  if (!scratch || blocks <= 0 || iters <= 0) return BIGINT_EINVAL;
+  if (blocks > (1 << 20) || iters > (1 << 24)) return BIGINT_EUNSUPPORTED;
+  return launch_mad_rate(scratch, (int)blocks, (int)iters, (hipStream_t)stream);
+}
+
 // ---- autotuning ------------------------------------------------------------------
 // For each size bin, every tile configuration (strips per band P, waves per
 // work-group, digit width) multiplies the same random batch; the fastest is

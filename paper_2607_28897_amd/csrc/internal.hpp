@@ -75,6 +75,7 @@ int launch_mul_plain_ragged(uint32_t* out, const int64_t* out_off, const uint32_
                             int grid, hipStream_t s);
 
 int launch_mfma_rate(int32_t* out, int blocks, int iters, int toggle, hipStream_t s);
+int launch_mad_rate(uint64_t* out, int blocks, int iters, hipStream_t s);
 
 // ---- division -------------------------------------------------------------------
 // A division launch runs at most `chunk` work-groups at once (one workspace

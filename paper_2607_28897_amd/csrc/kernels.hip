@@ -489,6 +489,40 @@ __global__ __launch_bounds__(256) void k_mfma_rate(int32_t* out, int iters, int 
   out[blockIdx.x * blockDim.x + threadIdx.x] = t;
 }
 
+// ============================================================================
+// register-only 32x32+64 -> 64-bit multiply-add rate probe (diagnostic): the
+// plain kernel's inner operation (v_mad_u64_u32).  Every lane runs 8
+// independent chains acc = a_j * lo32(acc) + acc, 64 per loop round; the
+// multiplier changes every step, so nothing can be hoisted.
+// ============================================================================
+__global__ __launch_bounds__(256) void k_mad_rate(uint64_t* out, int iters) {
+  const uint32_t lane = threadIdx.x;
+  uint64_t acc[8];
+  uint32_t m[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    acc[j] = ((uint64_t)(lane + j) << 32) | (0x9e3779b9u * (lane + 1) + j);
+    m[j] = 0x85ebca6bu + 2654435761u * (uint32_t)j + lane;
+  }
+  for (int i = 0; i < iters; ++i) {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) acc[j] = (uint64_t)m[j] * (uint32_t)acc[j] + acc[j];
+    }
+  }
+  uint64_t t = 0;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) t ^= acc[j];
+  out[blockIdx.x * blockDim.x + threadIdx.x] = t;
+}
+
+int launch_mad_rate(uint64_t* out, int blocks, int iters, hipStream_t s) {
+  hipLaunchKernelGGL(k_mad_rate, dim3(blocks), dim3(256), 0, s, out, iters);
+  BI_LAUNCH_CHECK();
+  return BIGINT_OK;
+}
+
 int launch_mfma_rate(int32_t* out, int blocks, int iters, int toggle, hipStream_t s) {
   hipLaunchKernelGGL(k_mfma_rate, dim3(blocks), dim3(256), 0, s, out, iters, toggle);
   BI_LAUNCH_CHECK();
