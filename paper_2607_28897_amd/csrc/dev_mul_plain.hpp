@@ -5,8 +5,10 @@
 // loop over the index range common to all Q outputs, whose inner loop of
 // count Q reuses a sliding window of Q digits of B held in registers, plus
 // the two small triangles that only some outputs need.  Every partial sum is
-// a (low, high, carry) triple of u64 (oneConvMul), and combineQ folds the Q
-// triples into Q digits plus two spill digits.  The low digits of all blocks
+// kept as column sums of 32 x 32-bit products with carry counts (AccCol) and
+// folded at the end into the (low, high, carry) triple of u64 that
+// oneConvMul keeps; combineQ folds the Q triples into Q digits plus two spill
+// digits.  The low digits of all blocks
 // tile the product; the spills, shifted by Q, are added to them with one
 // work-group carry scan -- the Lsh + Hsh addition of bmulReg.
 //
@@ -25,14 +27,53 @@ struct Acc3 {
   uint64_t lo, hi, cc;
 };
 
-// acc += x * y (64 x 64 -> 128 bits, plus an overflow count)
-__device__ __forceinline__ void mac64(Acc3& a, uint64_t x, uint64_t y) {
-  const uint64_t plo = x * y;
-  const uint64_t phi = __umul64hi(x, y);
-  unsigned long long c1, c2;
-  a.lo = __builtin_addcll(a.lo, plo, 0ull, &c1);
-  a.hi = __builtin_addcll(a.hi, phi, c1, &c2);
-  a.cc += c2;
+// Sum of 64 x 64 -> 128-bit digit products, kept as column sums of 32 x
+// 32-bit products: value = s0 + s1 2^32 + s2 2^64 + c0 2^64 + c1 2^96 +
+// c2 2^128, where c0..c2 count the carries out of bit 63 of s0..s2.  One
+// digit product is four v_mad_u64_u32 (32 x 32 + 64 bits, carry out to a
+// lane mask; x0 y1 and x1 y0 both go to s1) and four carry additions.
+struct AccCol {
+  uint64_t s0, s1, s2;  // column sums at bits 0, 32, 64
+  uint32_t c0, c1, c2;  // carries out of bit 63 of each
+};
+
+__device__ __forceinline__ void acc_zero(AccCol& a) {
+  a.s0 = a.s1 = a.s2 = 0;
+  a.c0 = a.c1 = a.c2 = 0;
+}
+
+// a += x * y.  The four multiply-adds go first and the carry additions after
+// them, so every carry mask is read three or more instructions after it is
+// written.
+__device__ __forceinline__ void mac64(AccCol& a, uint64_t x, uint64_t y) {
+  const uint32_t x0 = (uint32_t)x, x1 = (uint32_t)(x >> 32);
+  const uint32_t y0 = (uint32_t)y, y1 = (uint32_t)(y >> 32);
+  uint64_t k0, k1, k2, k3;
+  asm("v_mad_u64_u32 %0, %6, %10, %12, %0\n\t"
+      "v_mad_u64_u32 %1, %7, %10, %13, %1\n\t"
+      "v_mad_u64_u32 %2, %8, %11, %13, %2\n\t"
+      "v_mad_u64_u32 %1, %9, %11, %12, %1\n\t"
+      "v_addc_co_u32_e64 %3, %6, 0, %3, %6\n\t"
+      "v_addc_co_u32_e64 %4, %7, 0, %4, %7\n\t"
+      "v_addc_co_u32_e64 %5, %8, 0, %5, %8\n\t"
+      "v_addc_co_u32_e64 %4, %9, 0, %4, %9"
+      : "+v"(a.s0), "+v"(a.s1), "+v"(a.s2), "+v"(a.c0), "+v"(a.c1), "+v"(a.c2),
+        "=&s"(k0), "=&s"(k1), "=&s"(k2), "=&s"(k3)
+      : "v"(x0), "v"(x1), "v"(y0), "v"(y1));
+}
+
+// the (lo, hi, carry) triple of 64-bit digits that an AccCol stands for
+__device__ __forceinline__ Acc3 acc_fold(const AccCol& a) {
+  // value = s0 + s1 2^32 + (s2 + c0) 2^64 + c1 2^96 + c2 2^128
+  unsigned long long k1, k2, k3, k4;
+  Acc3 r;
+  r.lo = __builtin_addcll(a.s0, a.s1 << 32, 0ull, &k1);
+  uint64_t hi = __builtin_addcll(a.s2, (a.s1 >> 32) + k1, 0ull, &k2);  // (s1>>32)+k1 < 2^32+1
+  hi = __builtin_addcll(hi, (uint64_t)a.c0, 0ull, &k3);
+  hi = __builtin_addcll(hi, (uint64_t)a.c1 << 32, 0ull, &k4);
+  r.hi = hi;
+  r.cc = (uint64_t)a.c2 + k2 + k3 + k4;
+  return r;
 }
 
 __device__ __forceinline__ void add_into(uint64_t& tl, uint64_t& th, uint64_t v) {
@@ -80,9 +121,9 @@ __device__ __forceinline__ void wg_mul_plain(uint32_t* out, const uint32_t* __re
     sp0[r] = 0; sp1[r] = 0;
     if (blk >= NBLK) continue;
     const int k0 = blk * Q;
-    Acc3 acc[Q];
+    AccCol col[Q];
 #pragma unroll
-    for (int q = 0; q < Q; ++q) acc[q] = Acc3{0, 0, 0};
+    for (int q = 0; q < Q; ++q) acc_zero(col[q]);
 
     // index range common to all Q outputs
     const int I_lo = max(0, k0 + Q - mb);
@@ -96,7 +137,7 @@ __device__ __forceinline__ void wg_mul_plain(uint32_t* out, const uint32_t* __re
       for (int i = I_hi; i >= I_lo; --i) {
         const uint64_t x = A[i];
 #pragma unroll
-        for (int q = 0; q < Q; ++q) mac64(acc[q], x, w[q]);
+        for (int q = 0; q < Q; ++q) mac64(col[q], x, w[q]);
         if (i > I_lo) {
 #pragma unroll
           for (int q = 0; q < Q - 1; ++q) w[q] = w[q + 1];
@@ -110,13 +151,16 @@ __device__ __forceinline__ void wg_mul_plain(uint32_t* out, const uint32_t* __re
       const int k = k0 + q;
       const int lo = max(0, k - mb + 1), hi = min(k, ma - 1);
       if (!common) {
-        for (int i = lo; i <= hi; ++i) mac64(acc[q], A[i], Bd[k - i]);
+        for (int i = lo; i <= hi; ++i) mac64(col[q], A[i], Bd[k - i]);
       } else {
-        for (int i = lo; i < I_lo; ++i) mac64(acc[q], A[i], Bd[k - i]);
-        for (int i = I_hi + 1; i <= hi; ++i) mac64(acc[q], A[i], Bd[k - i]);
+        for (int i = lo; i < I_lo; ++i) mac64(col[q], A[i], Bd[k - i]);
+        for (int i = I_hi + 1; i <= hi; ++i) mac64(col[q], A[i], Bd[k - i]);
       }
     }
     // combineQ: Q triples -> Q digits + 2 spill digits
+    Acc3 acc[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) acc[q] = acc_fold(col[q]);
     uint64_t tl = 0, th = 0;
 #pragma unroll
     for (int j = 0; j < Q + 2; ++j) {
