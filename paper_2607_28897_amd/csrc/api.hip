@@ -277,13 +277,12 @@ struct bigint_plan_s {
   int op = 0, flags = 0;
   int64_t batch = 0;
   std::vector<int64_t> la, lb;
-  // multiplication schedule
+  // schedule: the queue (largest first; division: int32 instance indices)
   bi::QueueItem* d_queue = nullptr;
-  uint32_t* d_counter = nullptr;
-  std::vector<bi::RaggedClass> cls;  // MFMA: one launch per tile configuration
-  size_t lds = 0;                    // plain
-  int grid = 0;
+  std::vector<bi::RaggedClass> cls;  // MFMA multiply: one launch per segment
+  size_t lds = 0;                    // plain multiply
   bool plain = false;
+  int grid = 0;               // division: work-groups (workspace slots) per launch
   int cap_u = 0, cap_v = 0;   // division: largest dividend / divisor
   // workspace
   void* ws = nullptr;
@@ -319,7 +318,6 @@ static int plan_build_mul(bigint_plan_s* p) {
       lds = std::max(lds, plain_lds((int)p->la[idx[t]], (int)p->lb[idx[t]]));
     }
     p->lds = lds;
-    p->grid = (int)std::max<int64_t>(1, std::min<int64_t>(B, (int64_t)num_cus()));
   } else {
     // Segments, one launch each.  A segment starts with the largest remaining
     // instance; its core is the run of instances with the same tile
@@ -397,10 +395,6 @@ static int plan_build_mul(bigint_plan_s* p) {
     BI_HIP(hipMalloc(&p->d_queue, sizeof(QueueItem) * B));
     BI_HIP(hipMemcpy(p->d_queue, q.data(), sizeof(QueueItem) * B, hipMemcpyHostToDevice));
   }
-  if (plain) {  // the plain kernel's queue head
-    BI_HIP(hipMalloc(&p->d_counter, 64));
-    BI_HIP(hipMemset(p->d_counter, 0, 64));
-  }
   p->ws_need = 0;  // the multiply needs no workspace beyond LDS
   return BIGINT_OK;
 }
@@ -440,7 +434,6 @@ static void plan_free(bigint_plan_s* p) {
   if (p->graph) hipGraphDestroy(p->graph);
   if (p->cap_stream) hipStreamDestroy(p->cap_stream);
   if (p->d_queue) hipFree(p->d_queue);
-  if (p->d_counter) hipFree(p->d_counter);
   if (p->ws_owned && p->ws) hipFree(p->ws);
   delete p;
 }
@@ -508,7 +501,7 @@ int bigint_mul_ragged(uint32_t* out, const int64_t* out_off, const uint32_t* a,
   auto launch = [&](hipStream_t ls) {
     if (plan->plain)
       return launch_mul_plain_ragged(out, out_off, a, a_off, b, b_off, plan->d_queue, batch,
-                                     plan->d_counter, plan->lds, plan->grid, ls);
+                                     plan->lds, ls);
     return launch_mul_ragged(out, out_off, a, a_off, b, b_off, plan->d_queue, plan->cls.data(),
                              (int)plan->cls.size(), ls);
   };

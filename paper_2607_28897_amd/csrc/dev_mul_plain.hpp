@@ -136,13 +136,14 @@ __device__ __forceinline__ void wg_mul_plain(uint32_t* out, const uint32_t* __re
       for (int q = 0; q < Q; ++q) w[q] = Bd[k0 - I_hi + q];
       for (int i = I_hi; i >= I_lo; --i) {
         const uint64_t x = A[i];
+        // the window's next digit, read before it is needed (clamped: the
+        // value read after the last step is not used)
+        const uint64_t nxt = Bd[min(k0 - i + Q, mb - 1)];
 #pragma unroll
         for (int q = 0; q < Q; ++q) mac64(col[q], x, w[q]);
-        if (i > I_lo) {
 #pragma unroll
-          for (int q = 0; q < Q - 1; ++q) w[q] = w[q + 1];
-          w[Q - 1] = Bd[k0 - i + Q];
-        }
+        for (int q = 0; q < Q - 1; ++q) w[q] = w[q + 1];
+        w[Q - 1] = nxt;
       }
     }
     // the triangles (or the whole range when nothing is common)

@@ -44,8 +44,9 @@ size_t mfma_lds(int na, int nb, MfmaCfg cfg);
 size_t plain_lds(int na, int nb);
 
 // ---- ragged (persistent, queue-fed) -------------------------------------------
-// One queue entry per instance, largest first.  MFMA plans cut the queue
-// into segments, one launch each (see RaggedClass); the plain plan has one.
+// One queue entry per instance, largest first, one work-group each.  MFMA
+// plans cut the queue into segments, one launch each (see RaggedClass); the
+// plain plan is one launch.
 struct QueueItem {
   int32_t inst;
   int32_t cfg;   // MFMA: strips per band (4, 8, 16) of the instance; plain: 0
@@ -71,8 +72,7 @@ int launch_mul_ragged(uint32_t* out, const int64_t* out_off, const uint32_t* a,
                       const QueueItem* queue, const RaggedClass* cls, int ncls, hipStream_t s);
 int launch_mul_plain_ragged(uint32_t* out, const int64_t* out_off, const uint32_t* a,
                             const int64_t* a_off, const uint32_t* b, const int64_t* b_off,
-                            const QueueItem* queue, int64_t nitems, uint32_t* counter, size_t lds,
-                            int grid, hipStream_t s);
+                            const QueueItem* queue, int64_t nitems, size_t lds, hipStream_t s);
 
 int launch_mfma_rate(int32_t* out, int blocks, int iters, int toggle, hipStream_t s);
 int launch_mad_rate(uint64_t* out, int blocks, int iters, hipStream_t s);

@@ -441,22 +441,14 @@ __global__ __launch_bounds__(512) void k_mul_mfma_ragged(uint32_t* out, const in
 __global__ __launch_bounds__(1024) void k_mul_plain_ragged(uint32_t* out, const int64_t* out_off,
                                                            const uint32_t* a, const int64_t* a_off,
                                                            const uint32_t* b, const int64_t* b_off,
-                                                           const QueueItem* queue, int nitems,
-                                                           uint32_t* counter) {
+                                                           const QueueItem* queue, int nitems) {
   extern __shared__ uint64_t sm64[];
-  __shared__ int item;
-  for (;;) {
-    if (threadIdx.x == 0) item = (int)atomicAdd(counter, 1u);
-    __syncthreads();
-    const int t = __builtin_amdgcn_readfirstlane(item);
-    __syncthreads();
-    if (t >= nitems) break;
-    const int64_t i = __builtin_amdgcn_readfirstlane(queue[t].inst);
-    const int na = (int)(a_off[i + 1] - a_off[i]);
-    const int nb = (int)(b_off[i + 1] - b_off[i]);
-    wg_mul_plain<kPlainQ, kPlainR>(out + out_off[i], a + a_off[i], na, b + b_off[i], nb, sm64);
-    __syncthreads();
-  }
+  const int t = blockIdx.x;
+  if (t >= nitems) return;
+  const int64_t i = __builtin_amdgcn_readfirstlane(queue[t].inst);
+  const int na = (int)(a_off[i + 1] - a_off[i]);
+  const int nb = (int)(b_off[i + 1] - b_off[i]);
+  wg_mul_plain<kPlainQ, kPlainR>(out + out_off[i], a + a_off[i], na, b + b_off[i], nb, sm64);
 }
 
 // ============================================================================
@@ -529,10 +521,6 @@ int launch_mfma_rate(int32_t* out, int blocks, int iters, int toggle, hipStream_
   return BIGINT_OK;
 }
 
-__global__ void k_zero_u32(uint32_t* p, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0u;
-}
 
 template <int DW, int P>
 static const void* ragged_kernel_p() {
@@ -594,14 +582,11 @@ int launch_mul_ragged(uint32_t* out, const int64_t* out_off, const uint32_t* a,
 
 int launch_mul_plain_ragged(uint32_t* out, const int64_t* out_off, const uint32_t* a,
                             const int64_t* a_off, const uint32_t* b, const int64_t* b_off,
-                            const QueueItem* queue, int64_t nitems, uint32_t* counter, size_t lds,
-                            int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, counter, 1);
-  BI_LAUNCH_CHECK();
+                            const QueueItem* queue, int64_t nitems, size_t lds, hipStream_t s) {
   BI_HIP(hipFuncSetAttribute((const void*)k_mul_plain_ragged,
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  hipLaunchKernelGGL(k_mul_plain_ragged, dim3(grid), dim3(1024), lds, s, out, out_off, a, a_off,
-                     b, b_off, queue, (int)nitems, counter);
+  hipLaunchKernelGGL(k_mul_plain_ragged, dim3((unsigned)nitems), dim3(1024), lds, s, out, out_off,
+                     a, a_off, b, b_off, queue, (int)nitems);
   BI_LAUNCH_CHECK();
   return BIGINT_OK;
 }
