@@ -152,12 +152,70 @@ __device__ __forceinline__ uint32_t wg_arith1(uint32_t* dst, int n, const uint32
   return wg_addsub<16, SUB>(dst, n, X, Y, 0u, sh->scan);
 }
 
-// dst[0 .. nout) = a * b mod B^nout (nout < 0: all na+nb limbs; MFMA-split
-// multiply; dst must not overlap a, b).  One out-of-line copy serves every
-// call site of the division, so the kernel's code stays small enough for the
-// instruction cache.
+constexpr int kSmallMul = 64;  // operands up to this many limbs: column-sum product
+// LDS bytes of the column-sum product
+constexpr size_t kSmallMulLds = (size_t)2 * kSmallMul * 8 + 2 * kSmallMul * 4 * 3 +
+                                2 * kSmallMul * 4 + 128;
+
+// dst[0 .. n) = a * b mod B^n with n = na + nb (nout < 0) or min(nout, na + nb),
+// for na, nb <= kSmallMul.  The MFMA multiply's fixed steps (digit staging,
+// prefix sums, band scheduling) cost several microseconds of latency even for
+// a few limbs, which the early Newton steps would pay twice per step.  Here
+// the operands go to LDS, thread k forms column k, C_k = sum a_i b_(k-i) of
+// 32 x 32-bit products, as a 64-bit sum s_k plus a count c_k of its carries,
+// and limb k of the product receives lo32(s_k) + hi32(s_(k-1)) + c_(k-2)
+// (< 3 * 2^32), whose own overflow (at most 2) goes one limb up through a
+// work-group carry scan.
+__device__ inline void wg_mul_small(uint32_t* dst, const uint32_t* a, int na, const uint32_t* b,
+                                    int nb, char* smem, int nout) {
+  constexpr int M = 2 * kSmallMul;
+  uint64_t* cs = reinterpret_cast<uint64_t*>(smem);   // M column sums
+  uint32_t* cc = reinterpret_cast<uint32_t*>(cs + M);  // M carry counts
+  uint32_t* sa = cc + M;                               // kSmallMul
+  uint32_t* sb = sa + kSmallMul;                       // kSmallMul
+  uint32_t* tl = sb + kSmallMul;                       // M
+  uint32_t* th = tl + M;                               // M
+  uint32_t* scan = th + M;                             // 32
+  const int K = na + nb;
+  const int n = nout < 0 ? K : min(nout, K);
+  for (int i = threadIdx.x; i < na; i += blockDim.x) sa[i] = a[i];
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) sb[i] = b[i];
+  __syncthreads();
+  for (int k = threadIdx.x; k < n; k += blockDim.x) {
+    uint64_t sum = 0;
+    uint32_t c = 0;
+    const int lo = max(0, k - nb + 1), hi = min(k, na - 1);
+    for (int i = lo; i <= hi; ++i) {
+      const uint64_t t = (uint64_t)sa[i] * sb[k - i] + sum;
+      c += t < sum;
+      sum = t;
+    }
+    cs[k] = sum;
+    cc[k] = c;
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < n; k += blockDim.x) {
+    const uint64_t t = (uint64_t)(uint32_t)cs[k] + (k >= 1 ? cs[k - 1] >> 32 : 0ull) +
+                       (k >= 2 ? cc[k - 2] : 0u);
+    tl[k] = (uint32_t)t;
+    th[k] = (uint32_t)(t >> 32);
+  }
+  __syncthreads();
+  auto X = [&](int j) -> uint32_t { return tl[j]; };
+  auto Y = [&](int j) -> uint32_t { return j >= 1 ? th[j - 1] : 0u; };
+  wg_addsub<4, false>(dst, n, X, Y, 0u, scan);
+}
+
+// dst[0 .. nout) = a * b mod B^nout (nout < 0: all na+nb limbs; dst must not
+// overlap a, b): small operands by column sums, the rest on the MFMA-split
+// multiply.  One out-of-line copy serves every call site of the division, so
+// the kernel's code stays small enough for the instruction cache.
 __device__ __noinline__ void wg_mul(uint32_t* dst, const uint32_t* a, int na, const uint32_t* b,
                                        int nb, char* smem, int nout) {
+  if (na <= kSmallMul && nb <= kSmallMul) {
+    wg_mul_small(dst, a, na, b, nb, smem, nout);
+    return;
+  }
   mfma::wg_mul_mfma<kDW, kP>(dst, nullptr, a, na, b, nb, smem, nout);
 }
 

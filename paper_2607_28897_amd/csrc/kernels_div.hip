@@ -68,7 +68,9 @@ size_t div_lds_bytes(int cap_u, int cap_v) {
   // the largest product of a division has two factors of at most cap_u + 8 limbs
   const int m = cap_u + 8;
   (void)cap_v;
-  return mfma::lds_bytes<div::kDW>(m, m, kDivThreads / 64, div::kP);
+  // (and at least what the small-operand product needs)
+  return std::max<size_t>(mfma::lds_bytes<div::kDW>(m, m, kDivThreads / 64, div::kP),
+                          div::kSmallMulLds);
 }
 
 // Work-groups that fit one CU: the kernel is built for 4 waves per SIMD (16
