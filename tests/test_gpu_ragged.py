@@ -1,5 +1,6 @@
-"""GPU parity: ragged batches in one persistent launch (work queue ordered
-largest first, hipGraph replay), against the oracle."""
+"""GPU parity: ragged batches (work queue ordered largest first, one launch
+per segment of tile configuration and occupancy with smaller instances filling
+each segment's end, hipGraph replay), against the oracle."""
 import numpy as np
 import pytest
 
@@ -110,3 +111,34 @@ def test_ragged_with_loaded_table(bi, orc, tmp_path, dw):
             assert np.array_equal(res[oo[i]:oo[i + 1]], want), i
     finally:
         bi.autotune_load(None)
+
+
+@pytest.mark.parametrize("flags", [0, 2])
+def test_ragged_segments_and_fillers(bi, orc, flags):
+    """Sizes spread over every tile configuration (1 to 18432 limbs, unequal
+    operand lengths), so the plan cuts several segments and fills their ends
+    with smaller instances; every product checked."""
+    g = np.random.default_rng(91 + flags)
+    B = 160
+    la = np.exp(g.uniform(0, np.log(12000), B)).astype(np.int64) + 1
+    lb = np.maximum(1, (la * g.uniform(0.3, 1.0, B)).astype(np.int64))
+    la[:4] = [18432, 1, 5000, 11585]
+    lb[:4] = [18432, 18432, 1, 11586]
+    a, a_off = _ragged(g, la)
+    b, b_off = _ragged(g, lb)
+    res, oo = _run(bi, la, lb, a, a_off, b, b_off, flags)
+    for i in range(B):
+        want = orc.mul1(a[a_off[i]:a_off[i + 1]], b[b_off[i]:b_off[i + 1]])
+        assert np.array_equal(res[oo[i]:oo[i + 1]], want), (i, la[i], lb[i])
+
+
+@pytest.mark.parametrize("n", [1, 700, 16384])
+def test_ragged_single_instance(bi, orc, n):
+    g = np.random.default_rng(n)
+    la = np.array([n], np.int64)
+    lb = np.array([max(1, n // 3)], np.int64)
+    a, a_off = _ragged(g, la)
+    b, b_off = _ragged(g, lb)
+    for flags in (0, 2, 1):
+        res, oo = _run(bi, la, lb, a, a_off, b, b_off, flags)
+        assert np.array_equal(res, orc.mul1(a, b)), flags
