@@ -67,7 +67,28 @@ __device__ __forceinline__ void wg_shr_copy(uint32_t* dst, int n, const uint32_t
 }
 
 // number of significant limbs of x[0..n)
+// Short operands (n <= 64 * kWaveRounds limbs) are reduced inside every wave
+// from per-round ballots (limb 64 r + lane in round r), which needs no LDS
+// reduction and no barrier between waves; one closing barrier keeps a later
+// in-place write from overtaking a slower wave's reads.
+constexpr int kWaveRounds = 2;
+
 __device__ __forceinline__ int wg_prec(const uint32_t* x, int n, Shared* sh) {
+  if (n <= 64 * kWaveRounds) {
+    int top = 0;
+    uint64_t mk[kWaveRounds];
+#pragma unroll
+    for (int r = 0; r < kWaveRounds; ++r) {
+      const int i = 64 * r + lane_id();
+      const uint32_t v = n > 0 ? x[min(i, n - 1)] : 0u;
+      mk[r] = __ballot(i < n && v != 0u);
+    }
+#pragma unroll
+    for (int r = kWaveRounds - 1; r >= 0; --r)
+      if (top == 0 && mk[r] != 0ull) top = 64 * r + 64 - __clzll(mk[r]);
+    __syncthreads();
+    return top;
+  }
   if (threadIdx.x == 0) sh->red[0] = 0;
   __syncthreads();
   int m = 0;
@@ -84,8 +105,39 @@ __device__ __forceinline__ int wg_prec(const uint32_t* x, int n, Shared* sh) {
 // in one pass
 struct Cmp { int sign; bool xzero; };
 
+// x - y over n <= 64 * kWaveRounds limbs inside every wave: sign of the
+// highest differing limb, and whether x is zero
+__device__ __forceinline__ Cmp wave_cmp_z(const uint32_t* x, int nx, const uint32_t* y, int ny,
+                                          int n) {
+  uint32_t av[kWaveRounds], bv[kWaveRounds];
+  uint64_t dk[kWaveRounds], zk = 0;
+#pragma unroll
+  for (int r = 0; r < kWaveRounds; ++r) {
+    const int i = 64 * r + lane_id();
+    const uint32_t a = nx > 0 ? x[min(i, nx - 1)] : 0u, b = ny > 0 ? y[min(i, ny - 1)] : 0u;
+    av[r] = (i < nx && i < n) ? a : 0u;
+    bv[r] = (i < ny && i < n) ? b : 0u;
+    dk[r] = __ballot(av[r] != bv[r]);
+    zk |= __ballot(av[r] != 0u);
+  }
+  Cmp res{0, zk == 0ull};
+  bool found = false;
+#pragma unroll
+  for (int r = kWaveRounds - 1; r >= 0; --r) {
+    if (!found && dk[r] != 0ull) {
+      const int bit = 63 - __clzll(dk[r]);
+      const uint32_t a = __shfl(av[r], bit), b = __shfl(bv[r], bit);
+      res.sign = a > b ? 1 : -1;
+      found = true;
+    }
+  }
+  __syncthreads();
+  return res;
+}
+
 __device__ __forceinline__ Cmp wg_cmp_z(const uint32_t* x, int nx, const uint32_t* y, int ny, int n,
                                         Shared* sh) {
+  if (n <= 64 * kWaveRounds) return wave_cmp_z(x, nx, y, ny, n);
   if (threadIdx.x == 0) { sh->red[1] = 0; sh->red[2] = 0; }
   __syncthreads();
   int m = 0, z = 0;
@@ -112,6 +164,7 @@ __device__ __forceinline__ Cmp wg_cmp_z(const uint32_t* x, int nx, const uint32_
 // sign of x - y over n limbs (both zero-extended to n)
 __device__ __forceinline__ int wg_cmp(const uint32_t* x, int nx, const uint32_t* y, int ny, int n,
                                       Shared* sh) {
+  if (n <= 64 * kWaveRounds) return wave_cmp_z(x, nx, y, ny, n).sign;
   if (threadIdx.x == 0) sh->red[1] = 0;
   __syncthreads();
   int m = 0;
@@ -133,14 +186,23 @@ __device__ __forceinline__ int wg_cmp(const uint32_t* x, int nx, const uint32_t*
   return r;
 }
 
+// addition / subtraction for the division on the whole work-group.  (Running
+// short ranges inside every wave instead, with two barriers, raised the
+// kernel's register spills from 180 to 388 bytes per lane and made divisions
+// 9% slower.)
+template <bool SUB, class FX, class FY>
+__device__ __forceinline__ uint32_t div_addsub(uint32_t* out, int n, FX X, FY Y, Shared* sh,
+                                               uint32_t* top = nullptr) {
+  return wg_addsub<16, SUB>(out, n, X, Y, 0u, sh->scan, top);
+}
+
 // dst[0..n) = x + y (or x - y), operands zero-extended; returns carry/borrow
 template <bool SUB>
 __device__ __forceinline__ uint32_t wg_arith(uint32_t* dst, int n, const uint32_t* x, int nx,
                                              const uint32_t* y, int ny, Shared* sh) {
   auto X = [&](int j) -> uint32_t { return (j < nx) ? x[min(j, nx - 1)] : 0u; };
   auto Y = [&](int j) -> uint32_t { return (j < ny) ? y[min(j, ny - 1)] : 0u; };
-  const uint32_t c = wg_addsub<16, SUB>(dst, n, X, Y, 0u, sh->scan);
-  return c;
+  return div_addsub<SUB>(dst, n, X, Y, sh);
 }
 
 // dst[0..n) = x +/- small (a one-limb value), x zero-extended
@@ -149,61 +211,85 @@ __device__ __forceinline__ uint32_t wg_arith1(uint32_t* dst, int n, const uint32
                                               uint32_t small, Shared* sh) {
   auto X = [&](int j) -> uint32_t { return (j < nx) ? x[min(j, nx - 1)] : 0u; };
   auto Y = [&](int j) -> uint32_t { return j == 0 ? small : 0u; };
-  return wg_addsub<16, SUB>(dst, n, X, Y, 0u, sh->scan);
+  return div_addsub<SUB>(dst, n, X, Y, sh);
 }
 
 constexpr int kSmallMul = 64;  // operands up to this many limbs: column-sum product
-// LDS bytes of the column-sum product
-constexpr size_t kSmallMulLds = (size_t)2 * kSmallMul * 8 + 2 * kSmallMul * 4 * 3 +
-                                2 * kSmallMul * 4 + 128;
+// LDS bytes of the column-sum product (both operands staged)
+constexpr size_t kSmallMulLds = (size_t)2 * kSmallMul * 4;
 
 // dst[0 .. n) = a * b mod B^n with n = na + nb (nout < 0) or min(nout, na + nb),
-// for na, nb <= kSmallMul.  The MFMA multiply's fixed steps (digit staging,
-// prefix sums, band scheduling) cost several microseconds of latency even for
-// a few limbs, which the early Newton steps would pay twice per step.  Here
-// the operands go to LDS, thread k forms column k, C_k = sum a_i b_(k-i) of
-// 32 x 32-bit products, as a 64-bit sum s_k plus a count c_k of its carries,
-// and limb k of the product receives lo32(s_k) + hi32(s_(k-1)) + c_(k-2)
-// (< 3 * 2^32), whose own overflow (at most 2) goes one limb up through a
-// work-group carry scan.
+// for 1 <= na, nb <= kSmallMul, on wave 0 alone (the other waves wait at the
+// closing barrier).  The MFMA multiply's fixed steps (digit staging, prefix
+// sums, band scheduling, barriers) cost several microseconds even for a few
+// limbs, which the early Newton steps would pay twice per step.  Wave 0
+// stages both operands in LDS; lane l forms columns k = l and l + 64,
+// C_k = sum a_i b_(k-i) of 32 x 32-bit products, as a 64-bit sum s_k plus a
+// count c_k of its carries.  Limb k of the product then receives
+// lo32(s_k) + hi32(s_(k-1)) + c_(k-2) (< 3 * 2^32), whose overflow (at most 2)
+// goes one limb up through two wave-level carry scans (limbs 0..63, then
+// 64..127).
 __device__ inline void wg_mul_small(uint32_t* dst, const uint32_t* a, int na, const uint32_t* b,
                                     int nb, char* smem, int nout) {
-  constexpr int M = 2 * kSmallMul;
-  uint64_t* cs = reinterpret_cast<uint64_t*>(smem);   // M column sums
-  uint32_t* cc = reinterpret_cast<uint32_t*>(cs + M);  // M carry counts
-  uint32_t* sa = cc + M;                               // kSmallMul
-  uint32_t* sb = sa + kSmallMul;                       // kSmallMul
-  uint32_t* tl = sb + kSmallMul;                       // M
-  uint32_t* th = tl + M;                               // M
-  uint32_t* scan = th + M;                             // 32
-  const int K = na + nb;
-  const int n = nout < 0 ? K : min(nout, K);
-  for (int i = threadIdx.x; i < na; i += blockDim.x) sa[i] = a[i];
-  for (int i = threadIdx.x; i < nb; i += blockDim.x) sb[i] = b[i];
-  __syncthreads();
-  for (int k = threadIdx.x; k < n; k += blockDim.x) {
-    uint64_t sum = 0;
-    uint32_t c = 0;
-    const int lo = max(0, k - nb + 1), hi = min(k, na - 1);
-    for (int i = lo; i <= hi; ++i) {
-      const uint64_t t = (uint64_t)sa[i] * sb[k - i] + sum;
-      c += t < sum;
-      sum = t;
+  if (wave_id() == 0) {
+    uint32_t* sa = reinterpret_cast<uint32_t*>(smem);
+    uint32_t* sb = sa + kSmallMul;
+    const int l = lane_id();
+    const int K = na + nb;
+    const int n = nout < 0 ? K : min(nout, K);
+    if (l < na) sa[l] = a[l];
+    if (l < nb) sb[l] = b[l];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    uint64_t s[2];
+    uint32_t c[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int k = l + 64 * h;
+      uint64_t sum = 0;
+      uint32_t cnt = 0;
+      const int lo = max(0, k - nb + 1), hi = min(k, na - 1);
+      for (int i = lo; i <= hi; ++i) {
+        const uint64_t t = (uint64_t)sa[i] * sb[k - i] + sum;
+        cnt += t < sum;
+        sum = t;
+      }
+      s[h] = sum;
+      c[h] = cnt;
     }
-    cs[k] = sum;
-    cc[k] = c;
+    // neighbours: column k-1 and k-2 (lane l-1 / l-2 of the same half, or of
+    // the lower half across the lane-0 boundary)
+    const int l1 = (l + 63) & 63, l2 = (l + 62) & 63;
+    const uint32_t sh0 = __shfl((uint32_t)(s[0] >> 32), l1), sh1 = __shfl((uint32_t)(s[1] >> 32), l1);
+    const uint32_t c0 = __shfl(c[0], l2), c1 = __shfl(c[1], l2);
+    uint32_t tl[2], th[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int k = l + 64 * h;
+      const uint32_t hi1 = k >= 1 ? (l >= 1 ? (h ? sh1 : sh0) : sh0) : 0u;
+      const uint32_t cc2 = k >= 2 ? (l >= 2 ? (h ? c1 : c0) : c0) : 0u;
+      const uint64_t t = (uint64_t)(uint32_t)s[h] + hi1 + cc2;
+      tl[h] = (uint32_t)t;
+      th[h] = (uint32_t)(t >> 32);
+    }
+    // limb k = tl_k + th_(k-1), carries rippling up
+    const uint32_t t0 = __shfl(th[0], l1), t1 = __shfl(th[1], l1);
+    uint32_t carry = 0u;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int k = l + 64 * h;
+      const uint32_t y = k >= 1 ? (l >= 1 ? (h ? t1 : t0) : t0) : 0u;
+      const uint32_t x = tl[h];
+      const uint32_t r = x + y;
+      const bool g = r < x, p = r == 0xffffffffu;
+      const WaveCarry w = wave_carry_masks(g, p);
+      const uint32_t ci = wave_carry_in(w, carry);
+      carry = wave_carry_out(w, carry);
+      if (k < n) dst[k] = r + ci;
+    }
   }
   __syncthreads();
-  for (int k = threadIdx.x; k < n; k += blockDim.x) {
-    const uint64_t t = (uint64_t)(uint32_t)cs[k] + (k >= 1 ? cs[k - 1] >> 32 : 0ull) +
-                       (k >= 2 ? cc[k - 2] : 0u);
-    tl[k] = (uint32_t)t;
-    th[k] = (uint32_t)(t >> 32);
-  }
-  __syncthreads();
-  auto X = [&](int j) -> uint32_t { return tl[j]; };
-  auto Y = [&](int j) -> uint32_t { return j >= 1 ? th[j - 1] : 0u; };
-  wg_addsub<4, false>(dst, n, X, Y, 0u, scan);
 }
 
 // dst[0 .. nout) = a * b mod B^nout (nout < 0: all na+nb limbs; dst must not
@@ -280,7 +366,7 @@ __device__ inline int fixup(const uint32_t* v, int k1, int c, Bufs& bf, int lw, 
       neg = false;
       auto X = [&](int) -> uint32_t { return 0u; };
       auto Y = [&](int j) -> uint32_t { return bf.T[j]; };
-      wg_addsub<16, true>(bf.E, le, X, Y, 0u, sh->scan);
+      div_addsub<true>(bf.E, le, X, Y, sh);
       have_e = true;
     }
   }
@@ -293,7 +379,7 @@ __device__ inline int fixup(const uint32_t* v, int k1, int c, Bufs& bf, int lw, 
       neg = false;
       auto X = [&](int) -> uint32_t { return 0u; };
       auto Y = [&](int j) -> uint32_t { return j < lp ? bf.T[j] : 0u; };
-      wg_addsub<16, true>(bf.T, min(c, lp), X, Y, 0u, sh->scan);  // in place
+      div_addsub<true>(bf.T, min(c, lp), X, Y, sh);  // in place
       // limbs [min(c,lp), c) of 0 - P are all ones only if P == 0, which w >= 1 rules out
       wg_shr_copy(bf.E, le, bf.T, min(c, lp), 0);
       if (c > lp) {
@@ -436,7 +522,7 @@ __device__ inline int shifted_inverse(const uint32_t* v, int k1, int h, Bufs& bf
         return s2 < ly ? bf.T[s2] : 0u;
       };
       if (threadIdx.x == 0) sh->red[3] = 0;
-      wg_addsub<16, false>(bf.U2, lnew, X, Y, 0u, sh->scan, &sh->red[3]);
+      div_addsub<false>(bf.U2, lnew, X, Y, sh, &sh->red[3]);
     }
     {  // the new w is in U2: swap the two buffers instead of copying
       uint32_t* tmp = bf.W;
