@@ -331,6 +331,16 @@ def ragged_mode(torch, bi, inputs, args):
     ops = 2.0 * float((Nd * Nd).sum())
     res = {"mode": "ragged", "workload": "4096 products, operand bits log-uniform in [2^15, 2^19]",
            "int8_ops_per_launch_7bit_digits": ops}
+    # tuned tile configuration per octave of operand bits, with its share of the work
+    bins = []
+    for lo in (15, 16, 17, 18):
+        sel = (32 * lens > 2**lo) & (32 * lens <= 2**(lo + 1)) if lo > 15 else (32 * lens <= 2**16)
+        n_hi = int(lens[sel].max())
+        P, waves, dbits = bi.mfma_config(n_hi, n_hi)
+        bins.append({"bits": f"2^{lo}-2^{lo + 1}", "instances": int(sel.sum()),
+                     "work_share": round(float((Nd[sel] ** 2).sum() / (Nd ** 2).sum()), 3),
+                     "config_at_largest": {"strips_per_band": P, "waves": waves, "digit_bits": dbits}})
+    res["bins"] = bins
     for flags, name in ((0, "mfma_graph"), (2, "mfma_direct"), (1, "plain")):
         plan = bi.MulPlan(lens, lens, flags)
         out, oo = plan(ta, tao, tb, tbo)
