@@ -6,8 +6,8 @@
 //   p0 = a0 b0, p2 = a1 b1, pm = |a0 - a1| |b1 - b0|,
 //   s = sign(a0 - a1) sign(b1 - b0),
 // since a0 b1 + a1 b0 = (a0 - a1)(b1 - b0) + a0 b0 + a1 b1.  Three products
-// of half the size replace one: 3/4 of the multiply-accumulates, for two
-// linear passes before and three after.
+// of half the size replace one: 3/4 of the multiply-accumulates, for one
+// linear pass before (both differences) and one after.
 #include "internal.hpp"
 #include "dev_addsub.hpp"
 #include "dev_mul_mfma.hpp"
@@ -85,46 +85,118 @@ __global__ __launch_bounds__(512) void k_kara_mul(KaraJobs jobs) {
                            J.b + inst * J.b_stride, J.nb, smem, J.na + J.nb);
 }
 
-// out (2n limbs) = p0 + p2 B^(2h) + (p0 + p2 + s pm) B^h.
+// out (2n limbs) = p0 + p2 B^(2h) + (p0 + p2 + s pm) B^h.  With s < 0 the
+// subtraction of pm B^h becomes additions modulo B^(2n):
+// -pm B^h = ~pm B^h + B^h - B^(3h), where ~pm complements the 2h limbs of pm
+// and -B^(3h) is the all-ones limbs [3h, 2n).  Limb k then sums at most six
+// non-negative 32-bit terms and a 1: t_k = L_k + 2^32 H_k with H_k <= 5, and
+// out = sum L_k B^k + sum H_k B^(k+1) mod B^(2n), an addition whose limbs
+// carry at most one.  (3h <= 2n for every n >= 2.)
+//
+// The output is cut into chunks of kCombChunk limbs, one work-group each, so
+// that the pass runs on the whole chip: every chunk adds with carry-in 0 and
+// records its carry out and whether it came out all ones; k_kara_carry then
+// walks the chunks of an instance and ripples each incoming carry through the
+// chunk's leading all-ones limbs.
+constexpr int kCombQ = 4;
+constexpr int kCombChunk = 1024 * kCombQ;
+constexpr int kCombMaxChunks = 16;   // 2n <= 16 * 4096 limbs (h <= 16384)
+
 __global__ __launch_bounds__(1024) void k_kara_combine(uint32_t* out, const uint32_t* ws,
                                                        int64_t ws_stride, const int32_t* sgn,
-                                                       int n, int h) {
+                                                       uint32_t* summ, int n, int h) {
   __shared__ uint32_t scratch[32];
   const int64_t inst = blockIdx.x;
+  const int chunk = blockIdx.y;
+  const int k0 = chunk * kCombChunk;
+  const int len = min(kCombChunk, 2 * n - k0);
+  if (len <= 0) return;
   const uint32_t* w = ws + inst * ws_stride;
   const uint32_t* p0 = w + 2 * h;                 // 2h limbs
   const uint32_t* p2 = w + 4 * h;                 // 2(n-h) limbs
   const uint32_t* pm = w + 6 * h;                 // 2h limbs
-  uint32_t* M = const_cast<uint32_t*>(w) + 8 * h; // 2h+1 limbs
-  uint32_t* o = out + inst * (int64_t)(2 * n);
+  uint32_t* o = out + inst * (int64_t)(2 * n) + k0;
   const int l2 = 2 * (n - h);
   const int s = sgn[2 * inst] * sgn[2 * inst + 1];
-  {  // M = p0 + p2
-    auto X = [&](int j) -> uint32_t { return j < 2 * h ? p0[j] : 0u; };
-    auto Y = [&](int j) -> uint32_t { return j < l2 ? p2[min(j, l2 - 1)] : 0u; };
-    wg_addsub<16, false>(M, 2 * h + 1, X, Y, 0u, scratch);
-  }
-  if (s != 0) {  // M += s pm (the result is a0 b1 + a1 b0 >= 0)
-    auto X = [&](int j) -> uint32_t { return M[j]; };
-    auto Y = [&](int j) -> uint32_t { return j < 2 * h ? pm[j] : 0u; };
-    if (s > 0)
-      wg_addsub<16, false>(M, 2 * h + 1, X, Y, 0u, scratch);
-    else
-      wg_addsub<16, true>(M, 2 * h + 1, X, Y, 0u, scratch);
-  }
-  // o[0..h) = p0[0..h); o[h..2n) = (p0 B^0 + p2 B^(2h))[h..2n) + M
-  for (int j = threadIdx.x; j < h; j += blockDim.x) o[j] = p0[j];
-  auto X = [&](int j) -> uint32_t {
-    const int k = h + j;
-    return k < 2 * h ? p0[k] : p2[min(k - 2 * h, l2 - 1)];
+  auto t = [&](int k) -> uint64_t {
+    uint64_t v = k < 2 * h ? p0[k] : p2[k - 2 * h];
+    const int j = k - h;
+    if (j >= 0 && j < 2 * h) {
+      v += p0[j];
+      if (s > 0) v += pm[j];
+      else if (s < 0) v += (uint32_t)~pm[j];
+    }
+    if (j >= 0 && j < l2) v += p2[j];
+    if (s < 0) {
+      if (k == h) v += 1u;
+      if (k >= 3 * h) v += 0xffffffffu;
+    }
+    return v;
   };
-  auto Y = [&](int j) -> uint32_t { return j <= 2 * h ? M[min(j, 2 * h)] : 0u; };
-  wg_addsub<16, false>(o + h, 2 * n - h, X, Y, 0u, scratch);
+  // thread i: limbs [i Q, i Q + Q) of the chunk, from the Q + 1 sums
+  // t(k - 1) .. t(k + Q - 1) (each computed once); one round, one scan
+  const int j0 = threadIdx.x * kCombQ;
+  const int valid = min(kCombQ, max(0, len - j0));
+  uint64_t tv[kCombQ + 1];
+#pragma unroll
+  for (int i = 0; i <= kCombQ; ++i) {
+    const int k = k0 + j0 + i - 1;
+    tv[i] = (k >= 0 && k < 2 * n) ? t(k) : 0ull;
+  }
+  uint32_t x[kCombQ], y[kCombQ];
+#pragma unroll
+  for (int i = 0; i < kCombQ; ++i) {
+    x[i] = i < valid ? (uint32_t)tv[i + 1] : 0u;
+    y[i] = i < valid ? (uint32_t)(tv[i] >> 32) : 0u;
+  }
+  LimbRun<kCombQ, false> run;
+  run.build(x, y, valid);
+  uint32_t c;
+  const uint32_t cin = wg_carry_scan(run.G, run.P, 0u, scratch, &c);
+  run.apply(cin);
+  bool ones = true;
+#pragma unroll
+  for (int i = 0; i < kCombQ; ++i)
+    if (i < valid) {
+      o[j0 + i] = run.s[i];
+      ones = ones && run.s[i] == 0xffffffffu;
+    }
+  const bool all = __syncthreads_and(ones);
+  if (threadIdx.x == 0) summ[inst * kCombMaxChunks + chunk] = c | (all ? 2u : 0u);
+}
+
+// One wave per instance: carries between the chunks of k_kara_combine.
+__global__ __launch_bounds__(64) void k_kara_carry(uint32_t* out, const uint32_t* summ, int n) {
+  const int64_t inst = blockIdx.x;
+  uint32_t* o = out + inst * (int64_t)(2 * n);
+  const int lane = lane_id();
+  const int nch = (2 * n + kCombChunk - 1) / kCombChunk;
+  uint32_t c = 0;
+  for (int ch = 0; ch < nch; ++ch) {
+    const uint32_t sm = summ[inst * kCombMaxChunks + ch];
+    if (c) {  // + 1 at the chunk's first limb
+      const int k1 = min((ch + 1) * kCombChunk, 2 * n);
+      for (int base = ch * kCombChunk; base < k1; base += 64) {
+        const int k = base + lane;
+        const uint32_t v = k < k1 ? o[k] : 0u;
+        const uint64_t m = __ballot(k < k1 && v != 0xffffffffu);
+        if (m) {
+          const int f = __ffsll((unsigned long long)m) - 1;  // first limb that absorbs the carry
+          if (lane < f) o[k] = 0u;
+          else if (lane == f) o[k] = v + 1u;
+          break;
+        }
+        if (k < k1) o[k] = 0u;
+      }
+    }
+    c = (sm & 1u) | ((sm >> 1) & c);
+  }
 }
 
 size_t kara_ws_bytes(int n, int64_t batch) {
   const int h = (n + 1) / 2;
-  return (size_t)batch * (10 * (size_t)h + 16) * 4 + (size_t)batch * 8 + 256;
+  return (size_t)batch * (10 * (size_t)h + 16) * 4 + (size_t)batch * 8 +
+         (size_t)batch * kCombMaxChunks * 4 + 256;
 }
 
 int launch_mul_kara(uint32_t* out, const uint32_t* a, const uint32_t* b, int64_t n, int64_t batch,
@@ -133,7 +205,10 @@ int launch_mul_kara(uint32_t* out, const uint32_t* a, const uint32_t* b, int64_t
   const int64_t ws_stride = 10 * (int64_t)h + 16;
   uint32_t* ws = reinterpret_cast<uint32_t*>(ws_v);
   int32_t* sgn = reinterpret_cast<int32_t*>(ws + batch * ws_stride);
+  uint32_t* summ = reinterpret_cast<uint32_t*>(sgn + 2 * batch);
   if (h > kKaraQ * 1024) return BIGINT_EUNSUPPORTED;
+  const int nch = (int)((2 * n + kCombChunk - 1) / kCombChunk);
+  if (nch > kCombMaxChunks) return BIGINT_EUNSUPPORTED;
   // |a0 - a1| at ws[0..h), |b1 - b0| at ws[h..2h), signs
   const int T = (int)((cdiv(h, kKaraQ) + 63) / 64 * 64);
   hipLaunchKernelGGL(k_kara_diff, dim3((unsigned)batch, 2), dim3(T), 0, s, ws, ws_stride, sgn, a,
@@ -166,8 +241,10 @@ int launch_mul_kara(uint32_t* out, const uint32_t* a, const uint32_t* b, int64_t
 #undef BI_KARA_LAUNCH
   BI_LAUNCH_CHECK();
   // the sum
-  hipLaunchKernelGGL(k_kara_combine, dim3((unsigned)batch), dim3(1024), 0, s, out, ws, ws_stride,
-                     sgn, (int)n, h);
+  hipLaunchKernelGGL(k_kara_combine, dim3((unsigned)batch, nch), dim3(1024), 0, s, out, ws,
+                     ws_stride, sgn, summ, (int)n, h);
+  BI_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_kara_carry, dim3((unsigned)batch), dim3(64), 0, s, out, summ, (int)n);
   BI_LAUNCH_CHECK();
   return BIGINT_OK;
 }
