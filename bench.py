@@ -404,7 +404,7 @@ def _rand_dev(torch, g, rows, n):
 
 def addsub_mode(torch, bi, inputs, args):
     """1-Add, 1-Sub and 6-Add in GB/s on the paper's addition datasets
-    (NumBits x NumInsts = 2^32, Table tab-add; bytes = 3 NumInsts NumBits / 8,
+    (NumBits 2^12..2^18, NumBits x NumInsts = 2^32, Table tab-add; bytes = 3 NumInsts NumBits / 8,
     each input and the result once), and on the 2^17-bit configuration
     (1024 pairs, half carry-adversarial; 48 MiB, which fits the 256 MB
     Infinity Cache: hot = back-to-back launches, cold = each launch after
@@ -413,7 +413,7 @@ def addsub_mode(torch, bi, inputs, args):
     g.manual_seed(1005)
     res = {"mode": "addsub", "unit": "GB/s", "rows": []}
     steps = max(3, args.steps // 5)
-    for bits in (2**15, 2**16, 2**17, 2**18):
+    for bits in (2**12, 2**13, 2**14, 2**15, 2**16, 2**17, 2**18):
         n, insts = bits // 32, 2**32 // bits
         a = _rand_dev(torch, g, insts, n)
         b = _rand_dev(torch, g, insts, n)
@@ -459,12 +459,12 @@ def addsub_mode(torch, bi, inputs, args):
 
 def poly_mode(torch, bi, args):
     """Poly = (a a + b)(b b + b) + a b against one product, both mod B^n (the
-    paper's fixed precision, Table tab-mul), on its datasets NumBits x NumInsts
-    = 2^32."""
+    paper's fixed precision, Table tab-mul), on its datasets NumBits 2^12..2^19,
+    NumBits x NumInsts = 2^32."""
     g = torch.Generator(device="cuda")
     g.manual_seed(1006)
     res = {"mode": "poly", "unit": "ms", "rows": []}
-    for bits in (2**15, 2**16, 2**17, 2**18, 2**19):
+    for bits in (2**12, 2**13, 2**14, 2**15, 2**16, 2**17, 2**18, 2**19):
         n, insts = bits // 32, 2**32 // bits
         a = _rand_dev(torch, g, insts, n)
         b = _rand_dev(torch, g, insts, n)

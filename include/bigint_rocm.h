@@ -220,7 +220,7 @@ int bigint_divmod_ragged(uint32_t* q, const int64_t* q_off, uint32_t* r,
 
 /* ---- autotuning ----------------------------------------------------------------
  * Times every candidate tile configuration of the MFMA-split multiply on the
- * current device for each size bin (2^15..2^19 bits), keeps the fastest and
+ * current device for each size bin (2^12..2^19 bits), keeps the fastest and
  * writes the table as JSON to `cache_path` (host path; NULL = do not write).
  * Later plans use the table.  bigint_autotune_load reads such a file (a
  * NULL path restores the built-in table).  All candidates produce identical
@@ -277,7 +277,10 @@ int bigint_diag_mfma_rate(int32_t* scratch, int64_t blocks, int64_t iters, int t
 int bigint_diag_mad_rate(uint64_t* scratch, int64_t blocks, int64_t iters, void* stream);
 
 /* Tile parameters of the MFMA multiply used by the next calls on this thread
- * (strips per wave band: 4, 8 or 16; waves per work-group: 4 or 8; digit
+ * (strips per wave band: 4, 8 or 16; waves per work-group: 4 or 8, or 1 for
+ * one wave per instance with four instances per work-group -- the paper's
+ * ipb instances per block -- which bigint_mul and bigint_mullo use with
+ * 8-bit digits when na + nb <= 4096 limbs and otherwise treat as 4; digit
  * width: 7 or 8 bits); 0 keeps the tuned default.  Plans read the tuned
  * table only.  Exists so tests can check that every configuration gives the
  * same bytes; other values return BIGINT_EINVAL. */

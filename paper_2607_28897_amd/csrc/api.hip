@@ -25,8 +25,9 @@ struct TuneEntry {
   int P, waves, dw;
 };
 static std::mutex g_tune_mu;
+// (waves 1: one wave per instance, four instances per work-group)
 static const std::vector<TuneEntry> kBuiltinTune = {
-    {1448, 4, 4, 8}, {2896, 8, 4, 8}, {5792, 8, 8, 8}, {11585, 8, 8, 8},
+    {512, 4, 1, 8}, {1448, 8, 1, 8}, {2896, 8, 4, 8}, {5792, 8, 8, 8}, {11585, 8, 8, 8},
     {BIGINT_MFMA_MAX_LIMBS, 16, 8, 8}};
 static std::vector<TuneEntry> g_tune = kBuiltinTune;
 
@@ -45,6 +46,14 @@ MfmaCfg default_mfma_cfg(int na, int nb) {
       }
   }
   if (c.dw == 7 && mfma_lds(na, nb, c) > 163840) c.dw = 8;
+  return c;
+}
+
+// Ragged plans run one instance per work-group: a one-wave-per-instance
+// entry of the table becomes 4 waves there.
+static MfmaCfg ragged_mfma_cfg(int na, int nb) {
+  MfmaCfg c = default_mfma_cfg(na, nb);
+  if (c.waves == 1) c.waves = 4;
   return c;
 }
 
@@ -102,7 +111,7 @@ int bigint_set_mfma_config(int strips_per_band, int waves, int digit_bits) {
   if (strips_per_band != 0 && strips_per_band != 4 && strips_per_band != 8 &&
       strips_per_band != 16)
     return BIGINT_EINVAL;
-  if (waves != 0 && waves != 4 && waves != 8) return BIGINT_EINVAL;
+  if (waves != 0 && waves != 1 && waves != 4 && waves != 8) return BIGINT_EINVAL;
   if (digit_bits != 0 && digit_bits != 7 && digit_bits != 8) return BIGINT_EINVAL;
   t_cfg_P = strips_per_band;
   t_cfg_waves = waves;
@@ -166,7 +175,8 @@ int bigint_mul(uint32_t* out, const uint32_t* a, int64_t na, const uint32_t* b, 
   if (algo == BIGINT_MUL_KARATSUBA) {
     if (na != nb || na < 2) return BIGINT_EUNSUPPORTED;
     const int h = (int)((na + 1) / 2);
-    const MfmaCfg hc = current_mfma_cfg(h, h);
+    MfmaCfg hc = current_mfma_cfg(h, h);
+    if (hc.waves == 1) hc.waves = 4;   // the half products run one per work-group
     if (!mfma_fits(h, h, hc)) return BIGINT_EUNSUPPORTED;
     if (batch == 0) return BIGINT_OK;
     hipStream_t s = (hipStream_t)stream;
@@ -230,6 +240,9 @@ int bigint_poly(uint32_t* out, const uint32_t* a, const uint32_t* b, int64_t n, 
   if (overlap(out, bytes, a, bytes) || overlap(out, bytes, b, bytes)) return BIGINT_EINVAL;
   MfmaCfg cfg = default_mfma_cfg((int)n, (int)n);
   cfg.dw = 8;
+  // Poly runs one instance per work-group; where the table runs small
+  // products one wave per instance, 4 strips per band on 4 waves
+  if (cfg.waves == 1) cfg = MfmaCfg{4, 4, 8};
   if (poly_lds((int)n, cfg) > 163840) return BIGINT_EUNSUPPORTED;
   if (batch == 0) return BIGINT_OK;
   // launches of `grid` work-groups, each owning 2n limbs of workspace
@@ -299,7 +312,7 @@ static int plan_build_mul(bigint_plan_s* p) {
   const int64_t B = p->batch;
   bool plain = (p->flags & BIGINT_PLAN_PLAIN) != 0;
   for (int64_t i = 0; i < B && !plain; ++i) {
-    const MfmaCfg c = default_mfma_cfg((int)p->la[i], (int)p->lb[i]);
+    const MfmaCfg c = ragged_mfma_cfg((int)p->la[i], (int)p->lb[i]);
     if (!mfma_fits(p->la[i], p->lb[i], c) || std::min(p->la[i], p->lb[i]) < 1) plain = true;
   }
   for (int64_t i = 0; i < B; ++i)
@@ -345,7 +358,7 @@ static int plan_build_mul(bigint_plan_s* p) {
     std::vector<It> it(B);
     for (int64_t t = 0; t < B; ++t) {
       const int64_t i = idx[t];
-      const MfmaCfg c = default_mfma_cfg((int)p->la[i], (int)p->lb[i]);
+      const MfmaCfg c = ragged_mfma_cfg((int)p->la[i], (int)p->lb[i]);
       const size_t l = mfma_lds((int)p->la[i], (int)p->lb[i], c);
       const int by_lds = (int)std::min<size_t>(4, 163840 / std::max<size_t>(l, 1));
       it[t] = It{i, c, std::min(by_lds, reg_occ(ragged_cfg_id(c), c.waves))};
@@ -634,9 +647,9 @@ int bigint_diag_mad_rate(uint64_t* scratch, int64_t blocks, int64_t iters, void*
 
 int bigint_autotune(const char* cache_path, int flags) {
   (void)flags;
-  static const int kBins[] = {1024, 2048, 4096, 8192, 16384};
+  static const int kBins[] = {128, 256, 512, 1024, 2048, 4096, 8192, 16384};
   static const int kP[] = {4, 8, 16};
-  static const int kW[] = {4, 8};
+  static const int kW[] = {1, 4, 8};
   static const int kD[] = {7, 8};
   std::vector<TuneEntry> table;
   hipStream_t s = nullptr;
@@ -679,6 +692,8 @@ int bigint_autotune(const char* cache_path, int flags) {
         if (rc != BIGINT_OK) break;
         const MfmaCfg cfg{P, W, D};
         if (mfma_lds(n, n, cfg) > 163840) continue;
+        // one wave per instance: 8-bit digits, 4 or 8 strips per band, small sizes
+        if (W == 1 && (D != 8 || P == 16 || !mfma_wave_fits(n, n))) continue;
         rc = launch_mul_mfma(out, nullptr, a, n, b, n, nb, cfg, s);  // warm-up
         if (rc != BIGINT_OK) break;
         if (hipEventRecord(e0, s) != hipSuccess) { rc = BIGINT_EHIP; break; }
@@ -765,7 +780,7 @@ int bigint_autotune_load(const char* cache_path) {
     if (!field("\"strips_per_band\"", &e.P) || !field("\"waves\"", &e.waves) ||
         !field("\"digit_bits\"", &e.dw))
       return BIGINT_EINVAL;
-    if ((e.P != 4 && e.P != 8 && e.P != 16) || (e.waves != 4 && e.waves != 8) ||
+    if ((e.P != 4 && e.P != 8 && e.P != 16) || (e.waves != 1 && e.waves != 4 && e.waves != 8) ||
         (e.dw != 7 && e.dw != 8) || e.max_limbs <= 0)
       return BIGINT_EINVAL;
     table.push_back(e);

@@ -176,10 +176,12 @@ __device__ __forceinline__ uint32_t limb8(const uint32_t* __restrict__ a, int n,
 
 // Stage the reversed digits of a and the digits of b into LDS (zero padded).
 // Abuf[q] = alpha[QA - q]: dword d holds digits QA-4d-3 .. QA-4d, byte-reversed.
+// (tid, T): this thread's index and the number of threads taking part
+// (the whole work-group by default, one wave for the wave-level multiply)
 template <int DW>
 __device__ __forceinline__ void stage(const Lds& s, const Geo& g, const uint32_t* __restrict__ a,
-                                      const uint32_t* __restrict__ b) {
-  const int T = blockDim.x;
+                                      const uint32_t* __restrict__ b, int tid = -1, int T = 0) {
+  if (T == 0) { tid = threadIdx.x; T = blockDim.x; }
   uint32_t* A32 = reinterpret_cast<uint32_t*>(s.A);
   uint32_t* B32 = reinterpret_cast<uint32_t*>(s.B);
   const int nA = g.SA / 4, nB = g.SB / 4;
@@ -187,22 +189,22 @@ __device__ __forceinline__ void stage(const Lds& s, const Geo& g, const uint32_t
     // digits QA-4d-3 .. QA-4d: bytes 1..3 of limb l and byte 0 of limb l+1
     // (QA = 0 mod 16, so QA-4d-4 = 4l)
 #pragma unroll 8
-    for (int d = threadIdx.x; d < nA; d += T) {
+    for (int d = tid; d < nA; d += T) {
       const int l = (g.QA - 4 * d - 4) >> 2;
       const uint32_t v = __builtin_amdgcn_alignbyte(limb8(a, g.na, l + 1), limb8(a, g.na, l), 1);
       A32[d] = __builtin_bswap32(v);
     }
 #pragma unroll 8
-    for (int d = threadIdx.x; d < nB; d += T) B32[d] = limb8(b, g.nb, d - kPadB / 4);
+    for (int d = tid; d < nB; d += T) B32[d] = limb8(b, g.nb, d - kPadB / 4);
   } else {
 #pragma unroll 8
-    for (int d = threadIdx.x; d < nA; d += T) {
+    for (int d = tid; d < nA; d += T) {
       const int k0 = g.QA - 4 * d - 3;
       // digits at index >= Na come out 0 because the bits past the top limb are 0
       A32[d] = __builtin_bswap32(digits4(a, g.na, k0));
     }
 #pragma unroll 8
-    for (int d = threadIdx.x; d < nB; d += T) B32[d] = digits4(b, g.nb, 4 * d - kPadB);
+    for (int d = tid; d < nB; d += T) B32[d] = digits4(b, g.nb, 4 * d - kPadB);
   }
 }
 
@@ -254,12 +256,13 @@ __device__ __forceinline__ int wave_sum(int x) {
 // bsa[b] = sum of alpha'_i over i < 256 b for b = 0..NBa (bsa[NBa] is the
 // whole sum); likewise bsb.  Reads the staged buffers; the caller
 // synchronises before and after.
-__device__ __forceinline__ void block_sums(const Lds& s, const Geo& g) {
+__device__ __forceinline__ void block_sums(const Lds& s, const Geo& g, int wid = -1, int nw = 0) {
+  if (nw == 0) { wid = wave_id(); nw = num_waves(); }
   // a row of 16 lanes per block, four consecutive groups per lane (no LDS
   // bank conflicts); the row total by DPP shifts inside the row
   const int nblk = g.NBa + g.NBb;
   const int lane = lane_id(), row = lane >> 4, col = lane & 15;
-  for (int t0 = 4 * wave_id(); t0 < nblk; t0 += 4 * num_waves()) {
+  for (int t0 = 4 * wid; t0 < nblk; t0 += 4 * nw) {
     const int t = t0 + row;
     const bool isA = t < g.NBa;
     const int blk = isA ? t : t - g.NBa;
@@ -276,10 +279,10 @@ __device__ __forceinline__ void block_sums(const Lds& s, const Geo& g) {
 }
 
 // exclusive prefix over the block totals (wave 0: alpha', wave 1 or 0: beta')
-__device__ __forceinline__ void block_prefix(const Lds& s, const Geo& g) {
-  const int wid = wave_id();
+__device__ __forceinline__ void block_prefix(const Lds& s, const Geo& g, int wid = -1, int nw = 0) {
+  if (nw == 0) { wid = wave_id(); nw = num_waves(); }
   for (int op = 0; op < 2; ++op) {
-    if (wid != (num_waves() > 1 ? op : 0)) continue;
+    if (wid != (nw > 1 ? op : 0)) continue;
     int32_t* bs = op == 0 ? s.bsa : s.bsb;
     const int nb = op == 0 ? g.NBa : g.NBb;
     int carry = 0;
@@ -725,6 +728,96 @@ __device__ __forceinline__ void wg_mul_mfma(uint32_t* out, int32_t* coef, const 
     }
   }
   __syncthreads();
+}
+
+// ---- one wave per instance (small operands) ----------------------------------------
+// For operands of a few hundred limbs the work-group phases (staging, block
+// sums, band scheduling, the strip carry scan) and their barriers cost more
+// than the MFMA work, so several instances share a work-group, one wave each
+// (the paper's ipb instances per block), and every phase runs inside the
+// wave: the same staging, block sums and bands, and the strip carry scan on
+// one lane per strip.  Needs W <= 64 strips (na + nb <= 4096 limbs).
+
+// LDS bytes of one wave's instance (8-bit digits): operands, the wave's
+// scratch, strip carries, misc, block prefix sums
+__host__ __device__ inline size_t wave_lds_bytes(int na, int nb) {
+  const Geo g = make_geo<8>(na, nb);
+  return (((size_t)g.SA + g.SB + 1024 + (size_t)8 * g.W + 128 + bs_bytes(g)) + 15) & ~(size_t)15;
+}
+
+__device__ __forceinline__ Lds carve_wave(char* smem, const Geo& g) {
+  Lds s;
+  char* p = smem;
+  s.A = reinterpret_cast<uint8_t*>(p); p += g.SA;
+  s.B = reinterpret_cast<uint8_t*>(p); p += g.SB;
+  s.scr = s.wscr = reinterpret_cast<int32_t*>(p); p += 1024;
+  s.carry = reinterpret_cast<uint64_t*>(p); p += 8 * g.W;
+  s.order = nullptr;
+  s.misc = reinterpret_cast<uint32_t*>(p); p += 128;
+  s.bsa = reinterpret_cast<int32_t*>(p);
+  s.bsb = s.bsa + g.NBa + 1;
+  return s;
+}
+
+// LDS writes of this wave visible to its later LDS reads
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// out[0 .. nout) = a * b mod B^nout on the calling wave alone (offset 8-bit
+// digits; nout < 0: the whole na+nb limbs); smem: wave_lds_bytes(na, nb)
+// bytes of this wave's own LDS.
+template <int P>
+__device__ __forceinline__ void wave_mul_mfma(uint32_t* out, const uint32_t* __restrict__ a, int na,
+                                              const uint32_t* __restrict__ b, int nb, char* smem,
+                                              int nout = -1) {
+  const Geo g = make_geo<8>(na, nb, nout);
+  const Lds s = carve_wave(smem, g);
+  const int lane = lane_id();
+  stage<8>(s, g, a, b, lane, 64);
+  wave_sync();
+  block_sums(s, g, 0, 1);
+  wave_sync();
+  block_prefix(s, g, 0, 1);
+  wave_sync();
+  const int NB = (g.W + P - 1) / P;
+#pragma unroll 1
+  for (int band = 0; band < NB; ++band) run_band<8, P>(band, s, g, out, nullptr);
+  wave_sync();
+  // strip carries (one lane per strip), as in wg_mul_mfma's closing scan
+  constexpr int kStripLimbs = strip_limbs<8>();
+  const uint64_t kC = (1ull << 63) - 1;
+  const int w = lane;
+  const bool valid = w < g.W;
+  const int j0 = kStripLimbs * (valid ? w : 0);
+  const uint32_t l0 = (valid && j0 < g.nout) ? out[j0] : 0u;
+  const uint32_t l1 = (valid && j0 + 1 < g.nout) ? out[j0 + 1] : 0u;
+  const uint64_t d = (valid && w > 0) ? (s.carry[w - 1] & kC) : 0ull;
+  const bool ones = valid && (s.carry[w] >> 63);
+  const uint64_t x0 = ((uint64_t)l1 << 32) | l0;
+  const uint64_t x = x0 + d;
+  const bool xh = x < x0;
+  const bool gen = valid && xh && ones;
+  const bool prop = valid && !xh && x == ~0ull && ones;
+  const WaveCarry wc = wave_carry_masks(gen, prop);
+  const uint32_t c = wave_carry_in(wc, 0u);
+  if (valid) {
+    const uint64_t y = x + c;
+    const bool yh = xh || (y < x);
+    if (y != x0) {
+      if (j0 < g.nout) out[j0] = (uint32_t)y;
+      if (j0 + 1 < g.nout) out[j0 + 1] = (uint32_t)(y >> 32);
+    }
+    if (yh) {
+      for (int j = j0 + 2; j < min(j0 + kStripLimbs, g.nout); ++j) {
+        const uint32_t v = out[j];
+        out[j] = v + 1u;
+        if (v != 0xffffffffu) break;
+      }
+    }
+  }
 }
 
 }  // namespace mfma

@@ -8,7 +8,8 @@ namespace bi {
 // tile configuration of the MFMA multiply
 struct MfmaCfg {
   int P;       // strips per wave band (4, 8, 16)
-  int waves;   // waves per work-group (4, 8)
+  int waves;   // waves per work-group (4, 8); 1: one wave per instance, 4 instances
+               // per work-group (8-bit digits, na + nb <= 4096 limbs)
   int dw;      // digit width: 7 (plain 7-bit digits) or 8 (offset 8-bit digits)
 };
 
@@ -41,6 +42,7 @@ int launch_digits7(uint8_t* out, const uint32_t* a, int64_t n, int64_t D, int64_
                    hipStream_t s);
 
 size_t mfma_lds(int na, int nb, MfmaCfg cfg);
+bool mfma_wave_fits(int64_t na, int64_t nb);   // the one-wave-per-instance kernel takes it
 size_t plain_lds(int na, int nb);
 
 // ---- ragged (persistent, queue-fed) -------------------------------------------

@@ -164,7 +164,10 @@ __global__ __launch_bounds__(512) void k_mul_mfma(uint32_t* out, int32_t* coef, 
                            b + inst * (int64_t)nb, nb, smem, nout);
 }
 
+// LDS of the work-group kernel (waves == 1, one wave per instance, is sized
+// as its 4-wave fallback, which covers it)
 size_t mfma_lds(int na, int nb, MfmaCfg cfg) {
+  if (cfg.waves == 1) cfg.waves = 4;
   return cfg.dw == 8 ? mfma::lds_bytes<8>(na, nb, cfg.waves, cfg.P)
                      : mfma::lds_bytes<7>(na, nb, cfg.waves, cfg.P);
 }
@@ -197,10 +200,56 @@ static int launch_mfma_dw(uint32_t* out, int32_t* coef, const uint32_t* a, int64
 
 // coef != nullptr (raw coefficients) is served with 7-bit digits only.
 // nout < 0: the whole na+nb limbs; else the product mod B^nout per instance.
+// Small operands: one wave per instance, kWaveInst instances per work-group
+// (cfg.waves == 1); every phase runs inside the wave (mfma::wave_mul_mfma).
+constexpr int kWaveInst = 4;
+
+template <int P>
+__global__ __launch_bounds__(64 * kWaveInst) void k_mul_mfma_wave(uint32_t* out, const uint32_t* a,
+                                                                  int na, const uint32_t* b, int nb,
+                                                                  int nout, int64_t batch,
+                                                                  int wave_lds) {
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  const int64_t inst = (int64_t)blockIdx.x * kWaveInst + wave_id();
+  if (inst >= batch) return;   // the whole wave: no work-group barrier follows
+  mfma::wave_mul_mfma<P>(out + inst * (int64_t)nout, a + inst * (int64_t)na, na,
+                         b + inst * (int64_t)nb, nb, smem + (size_t)wave_id() * wave_lds, nout);
+}
+
+bool mfma_wave_fits(int64_t na, int64_t nb) {
+  return na + nb <= 64 * mfma::strip_limbs<8>() &&
+         (size_t)kWaveInst * mfma::wave_lds_bytes((int)na, (int)nb) <= 163840;
+}
+
+static int launch_mfma_wave(uint32_t* out, const uint32_t* a, int64_t na, const uint32_t* b,
+                            int64_t nb, int64_t batch, int P, int nout, hipStream_t s) {
+  const int wl = (int)mfma::wave_lds_bytes((int)na, (int)nb);
+  const size_t lds = (size_t)kWaveInst * wl;
+  const dim3 gd((unsigned)((batch + kWaveInst - 1) / kWaveInst)), bd(64 * kWaveInst);
+  if (P == 4) {
+    BI_HIP(hipFuncSetAttribute((const void*)k_mul_mfma_wave<4>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(k_mul_mfma_wave<4>, gd, bd, lds, s, out, a, (int)na, b, (int)nb, nout,
+                       batch, wl);
+  } else {
+    BI_HIP(hipFuncSetAttribute((const void*)k_mul_mfma_wave<8>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(k_mul_mfma_wave<8>, gd, bd, lds, s, out, a, (int)na, b, (int)nb, nout,
+                       batch, wl);
+  }
+  BI_LAUNCH_CHECK();
+  return BIGINT_OK;
+}
+
 int launch_mul_mfma(uint32_t* out, int32_t* coef, const uint32_t* a, int64_t na,
                     const uint32_t* b, int64_t nb, int64_t batch, MfmaCfg cfg, hipStream_t s,
                     int nout) {
   if (nout < 0 || nout > na + nb) nout = (int)(na + nb);
+  if (cfg.waves == 1) {
+    if (cfg.dw == 8 && coef == nullptr && mfma_wave_fits(na, nb))
+      return launch_mfma_wave(out, a, na, b, nb, batch, cfg.P == 4 ? 4 : 8, nout, s);
+    cfg.waves = 4;   // otherwise the work-group kernel
+  }
   if (cfg.dw == 8 && coef == nullptr)
     return launch_mfma_dw<8>(out, nullptr, a, na, b, nb, batch, cfg, nout, s);
   if (cfg.dw != 7 && cfg.dw != 8) return BIGINT_EINVAL;

@@ -98,7 +98,9 @@ def test_binding_fails_loudly_without_library(monkeypatch):
 def test_mfma_config_query(bi):
     # host-side only: the tuned table, the LDS fit and the thread overrides
     assert bi.mfma_config(16384, 16384) == (16, 8, 8)
-    assert bi.mfma_config(1024, 1024) == (4, 4, 8)
+    assert bi.mfma_config(1024, 1024) == (8, 1, 8)   # one wave per instance
+    assert bi.mfma_config(512, 512) == (4, 1, 8)
+    assert bi.mfma_config(2048, 2048) == (8, 4, 8)
     bi.set_mfma_config(0, 0, 7)
     try:
         assert bi.mfma_config(16384, 16384) == (16, 8, 7)

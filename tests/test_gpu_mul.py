@@ -166,18 +166,21 @@ def test_autotune_table_roundtrip(bi, orc, tmp_path):
     path = str(tmp_path / "tune.json")
     bi.autotune(path)
     t = json.load(open(path))
-    assert t["op"] == "mul_mfma" and len(t["bins"]) == 5
+    assert t["op"] == "mul_mfma" and len(t["bins"]) == 8
     for e in t["bins"]:
-        assert e["strips_per_band"] in (4, 8, 16) and e["waves"] in (4, 8)
+        assert e["strips_per_band"] in (4, 8, 16) and e["waves"] in (1, 4, 8)
         assert e["digit_bits"] in (7, 8)
+        if e["waves"] == 1:
+            assert e["digit_bits"] == 8 and e["strips_per_band"] in (4, 8)
     bi.autotune_load(path)
     try:
         g = np.random.default_rng(9)
-        a = rand_limbs(g, 3, 5000)
-        b = rand_limbs(g, 3, 5000)
-        p = host(bi.mul(dev(a), dev(b), bi.MUL_MFMA))
-        for i in range(3):
-            assert np.array_equal(p[i], orc.mul1(a[i], b[i]))
+        for n in (5000, 300):
+            a = rand_limbs(g, 3, n)
+            b = rand_limbs(g, 3, n)
+            p = host(bi.mul(dev(a), dev(b), bi.MUL_MFMA))
+            for i in range(3):
+                assert np.array_equal(p[i], orc.mul1(a[i], b[i]))
     finally:
         bi.autotune_load(None)          # the built-in table again
     assert bi.mfma_config(16384, 16384) == (16, 8, 8)
@@ -276,3 +279,31 @@ def test_karatsuba_unsupported_shapes(bi):
         bi.mul(dev(rand_limbs(g, 1, 10)), dev(rand_limbs(g, 1, 11)), bi.MUL_KARATSUBA)
     with pytest.raises(bi.BigIntError):
         bi.mul(dev(rand_limbs(g, 1, 1)), dev(rand_limbs(g, 1, 1)), bi.MUL_KARATSUBA)
+
+
+@pytest.mark.parametrize("P", [4, 8])
+@pytest.mark.parametrize("na,nb,B", [(1, 1, 7), (2, 3, 5), (17, 5, 9), (64, 64, 13), (128, 128, 33),
+                                     (256, 200, 10), (512, 512, 9), (700, 1, 3), (2048, 2048, 2),
+                                     (3000, 1096, 2)])
+def test_one_wave_per_instance(bi, orc, P, na, nb, B):
+    """Several instances per work-group, one wave each (waves = 1), including
+    a batch that does not fill the last work-group, unequal operands, the
+    size limit (na + nb = 4096 limbs), all-ones rows and the low product."""
+    g = np.random.default_rng(na * 7 + nb + P)
+    a = rand_limbs(g, B, na)
+    b = rand_limbs(g, B, nb)
+    a[0] = 0xFFFFFFFF
+    b[0] = 0xFFFFFFFF
+    if B > 1:
+        a[1] = 0
+    bi.set_mfma_config(P, 1, 8)
+    try:
+        assert bi.mfma_config(na, nb) == (P, 1, 8)
+        p = host(bi.mul(dev(a), dev(b), bi.MUL_MFMA))
+        lo = host(bi.mullo(dev(a), dev(a))) if na <= 2048 else None
+    finally:
+        bi.set_mfma_config(0, 0, 0)
+    for i in range(B):
+        assert np.array_equal(p[i], orc.mul1(a[i], b[i])), i
+        if lo is not None:
+            assert np.array_equal(lo[i], orc.mul1(a[i], a[i])[:na]), i
