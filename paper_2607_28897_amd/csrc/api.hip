@@ -240,9 +240,22 @@ int bigint_poly(uint32_t* out, const uint32_t* a, const uint32_t* b, int64_t n, 
   if (overlap(out, bytes, a, bytes) || overlap(out, bytes, b, bytes)) return BIGINT_EINVAL;
   MfmaCfg cfg = default_mfma_cfg((int)n, (int)n);
   cfg.dw = 8;
-  // Poly runs one instance per work-group; where the table runs small
-  // products one wave per instance, 4 strips per band on 4 waves
-  if (cfg.waves == 1) cfg = MfmaCfg{4, 4, 8};
+  if (cfg.waves == 1 && mfma_wave_fits(n, n)) {
+    // small operands: one wave per instance, like the products of the table
+    if (batch == 0) return BIGINT_OK;
+    const int P = cfg.P == 4 ? 4 : 8;
+    const int chunk = poly_wave_chunk((int)n, batch, P);
+    hipStream_t s = (hipStream_t)stream;
+    void* ws = nullptr;
+    hipError_t e = hipMallocAsync(&ws, (size_t)chunk * 2 * n * 4, s);
+    if (e != hipSuccess) { set_hip_error(e); return BIGINT_ENOMEM; }
+    const int rc = launch_poly_wave(out, a, b, n, batch, (uint32_t*)ws, chunk, P, s);
+    e = hipFreeAsync(ws, s);
+    if (rc != BIGINT_OK) return rc;
+    if (e != hipSuccess) { set_hip_error(e); return BIGINT_EHIP; }
+    return BIGINT_OK;
+  }
+  if (cfg.waves == 1) cfg = MfmaCfg{4, 4, 8};   // the work-group kernel
   if (poly_lds((int)n, cfg) > 163840) return BIGINT_EUNSUPPORTED;
   if (batch == 0) return BIGINT_OK;
   // launches of `grid` work-groups, each owning 2n limbs of workspace

@@ -36,6 +36,10 @@ int launch_add6(uint32_t* out, uint32_t* ovf, const uint32_t* a, const uint32_t*
                 int64_t batch, hipStream_t s);
 size_t poly_lds(int n, MfmaCfg cfg);
 int poly_chunk(int n, int64_t batch, MfmaCfg cfg);  // work-groups (workspace slots) per launch
+// Poly on the one-wave-per-instance multiply (8-bit digits, P = 4 or 8)
+int poly_wave_chunk(int n, int64_t batch, int P);   // instances (workspace slots) per launch
+int launch_poly_wave(uint32_t* out, const uint32_t* a, const uint32_t* b, int64_t n, int64_t batch,
+                     uint32_t* ws, int chunk, int P, hipStream_t s);
 int launch_poly(uint32_t* out, const uint32_t* a, const uint32_t* b, int64_t n, int64_t batch,
                 uint32_t* ws, int chunk, MfmaCfg cfg, hipStream_t s);
 int launch_digits7(uint8_t* out, const uint32_t* a, int64_t n, int64_t D, int64_t batch,

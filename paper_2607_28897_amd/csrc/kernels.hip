@@ -381,6 +381,89 @@ __global__ __launch_bounds__(512, P == 16 ? 2 : 4) void k_poly(uint32_t* out, co
   }
 }
 
+// Poly for small operands on the one-wave-per-instance multiply: wave g of
+// a launch takes instance first + g and workspace slot g (2n limbs), the
+// four products mod B^n run on mfma::wave_mul_mfma and the three additions
+// on the same wave (64 limbs per step, carries by ballot).
+__device__ __forceinline__ void wave_add_into(uint32_t* acc, const uint32_t* add, int n) {
+  uint32_t carry = 0u;
+  for (int base = 0; base < n; base += 64) {
+    const int j = base + lane_id();
+    const uint32_t x = j < n ? acc[j] : 0u, y = j < n ? add[j] : 0u;
+    const uint32_t r = x + y;
+    const WaveCarry w = wave_carry_masks(j < n && r < x, j < n && r == 0xffffffffu);
+    const uint32_t c = wave_carry_in(w, carry);
+    carry = wave_carry_out(w, carry);
+    if (j < n) acc[j] = r + c;
+  }
+}
+
+template <int P>
+__global__ __launch_bounds__(64 * kWaveInst) void k_poly_wave(uint32_t* out, const uint32_t* a,
+                                                              const uint32_t* b, int n,
+                                                              int64_t first, int64_t batch,
+                                                              uint32_t* ws, int wave_lds) {
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  const int64_t slot = (int64_t)blockIdx.x * kWaveInst + wave_id();
+  const int64_t inst = first + slot;
+  if (inst >= batch) return;   // the whole wave
+  char* sm = smem + (size_t)wave_id() * wave_lds;
+  uint32_t* t1 = ws + slot * 2 * n;
+  uint32_t* t2 = t1 + n;
+  const uint32_t* pa = a + inst * n;
+  const uint32_t* pb = b + inst * n;
+  uint32_t* po = out + inst * n;
+#pragma unroll 1
+  for (int op = 0; op < 4; ++op) {
+    // products: t1 = a a, t2 = b b, out = t1 t2, t1 = a b
+    const uint32_t* x = op == 0 ? pa : (op == 1 ? pb : (op == 2 ? t1 : pa));
+    const uint32_t* y = op == 0 ? pa : (op == 1 ? pb : (op == 2 ? t2 : pb));
+    uint32_t* dst = op == 0 ? t1 : (op == 1 ? t2 : (op == 2 ? po : t1));
+    mfma::wave_mul_mfma<P>(dst, x, n, y, n, sm, n);
+    mfma::wave_sync();
+    if (op == 2) continue;
+    // sums: t1 += b, t2 += b, out += t1
+    wave_add_into(op == 3 ? po : dst, op == 3 ? t1 : pb, n);
+    mfma::wave_sync();
+  }
+}
+
+// instances per Poly wave launch (one workspace slot each): eight times as
+// many as stay resident, at most the batch
+int poly_wave_chunk(int n, int64_t batch, int P) {
+  const size_t lds = (size_t)kWaveInst * mfma::wave_lds_bytes(n, n);
+  const void* k = P == 4 ? (const void*)k_poly_wave<4> : (const void*)k_poly_wave<8>;
+  int per_cu = 1;
+  if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 64 * kWaveInst, lds) != hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  return (int)std::max<int64_t>(
+      1, std::min<int64_t>(batch, 8 * (int64_t)num_cus() * per_cu * kWaveInst));
+}
+
+int launch_poly_wave(uint32_t* out, const uint32_t* a, const uint32_t* b, int64_t n, int64_t batch,
+                     uint32_t* ws, int chunk, int P, hipStream_t s) {
+  const int wl = (int)mfma::wave_lds_bytes((int)n, (int)n);
+  const size_t lds = (size_t)kWaveInst * wl;
+  if (lds > 163840) return BIGINT_EUNSUPPORTED;
+  if (chunk < 1) return BIGINT_EINVAL;
+  const void* k = P == 4 ? (const void*)k_poly_wave<4> : (const void*)k_poly_wave<8>;
+  BI_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  for (int64_t first = 0; first < batch; first += chunk) {
+    const int64_t cnt = std::min<int64_t>(chunk, batch - first);
+    const dim3 gd((unsigned)((cnt + kWaveInst - 1) / kWaveInst)), bd(64 * kWaveInst);
+    if (P == 4)
+      hipLaunchKernelGGL(k_poly_wave<4>, gd, bd, lds, s, out, a, b, (int)n, first,
+                         first + cnt, ws, wl);
+    else
+      hipLaunchKernelGGL(k_poly_wave<8>, gd, bd, lds, s, out, a, b, (int)n, first,
+                         first + cnt, ws, wl);
+    BI_LAUNCH_CHECK();
+  }
+  return BIGINT_OK;
+}
+
 size_t poly_lds(int n, MfmaCfg cfg) { return mfma::lds_bytes<8>(n, n, cfg.waves, cfg.P) + 256; }
 
 static const void* poly_kernel(int P) {

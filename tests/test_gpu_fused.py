@@ -65,7 +65,9 @@ def test_add6_in_place(bi, orc):
         assert np.array_equal(host(ta)[i], orc.add6_1(a[i], b[i])[0])
 
 
-@pytest.mark.parametrize("n,batch", [(1, 5), (2, 3), (33, 4), (1024, 8), (4096, 4), (16384, 2)])
+# up to 1448 limbs Poly runs one wave per instance, beyond on one work-group each
+@pytest.mark.parametrize("n,batch", [(1, 5), (2, 3), (33, 4), (128, 9), (700, 5), (1024, 8),
+                                     (1448, 3), (1449, 3), (4096, 4), (16384, 2)])
 def test_poly(bi, orc, n, batch):
     g = np.random.default_rng(n * 3 + batch)
     a = rand_limbs(g, batch, n)
@@ -76,10 +78,11 @@ def test_poly(bi, orc, n, batch):
         assert np.array_equal(p[i], orc.poly1(a[i], b[i])), i
 
 
-def test_poly_more_instances_than_work_groups(bi, orc):
-    # a persistent grid walks the batch: several instances per work-group
+@pytest.mark.parametrize("n,batch", [(64, 3000), (256, 20000)])
+def test_poly_more_instances_than_work_groups(bi, orc, n, batch):
+    # four instances per work-group, a batch that is not a multiple of four
     g = np.random.default_rng(5)
-    n, batch = 64, 3000
+    batch += 1
     a = rand_limbs(g, batch, n)
     b = rand_limbs(g, batch, n)
     p = host(bi.poly(dev(a), dev(b)))
