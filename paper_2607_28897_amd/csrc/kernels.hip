@@ -87,12 +87,100 @@ static int launch_addsub_q(uint32_t* out, uint32_t* cout, const uint32_t* a, con
   return BIGINT_OK;
 }
 
+// ---- several instances per wave (the paper's ipb) for short operands --------
+// Lanes [k L, (k+1) L) of a wave hold instance k of that wave (L = ceil(n/Q)
+// lanes of Q limbs; ipw = 64 / L instances per wave, 4 waves per
+// work-group).  The carry scan is segmented: the generate and propagate bits
+// of each instance's last lane are left out of the ballots, so no carry
+// crosses into the next instance, and that lane's own carry out (the
+// instance's) comes from its run summary and its carry in.  STEPS = 1: one
+// addition (or subtraction); STEPS = 6: the 6-Add chain a+b+a+b+a+b+a with
+// the carries out counted.
+template <int Q, bool SUB, int STEPS, bool VEC>
+__global__ __launch_bounds__(256) void k_addsub_ipb(uint32_t* out, uint32_t* cout, const uint32_t* a,
+                                                    const uint32_t* b, int n, int L, int ipw,
+                                                    int64_t batch) {
+  const int lane = lane_id();
+  const int k = lane / L, li = lane - k * L;
+  const int64_t inst = ((int64_t)blockIdx.x * 4 + wave_id()) * ipw + k;
+  const bool live = k < ipw && inst < batch;
+  const int j0 = li * Q;
+  const int valid = live ? min(Q, max(0, n - j0)) : 0;
+  const int64_t base = live ? inst * (int64_t)n : 0;
+  uint32_t av[Q], bv[Q], x[Q];
+  if (VEC && valid == Q) {
+#pragma unroll
+    for (int i = 0; i < Q; i += 4) {
+      const uint4 va = *reinterpret_cast<const uint4*>(a + base + j0 + i);
+      const uint4 vb = *reinterpret_cast<const uint4*>(b + base + j0 + i);
+      av[i] = va.x; av[i + 1] = va.y; av[i + 2] = va.z; av[i + 3] = va.w;
+      bv[i] = vb.x; bv[i + 1] = vb.y; bv[i + 2] = vb.z; bv[i + 3] = vb.w;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const int64_t jj = base + min(j0 + i, n - 1);
+      av[i] = i < valid ? a[jj] : 0u;
+      bv[i] = i < valid ? b[jj] : 0u;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < Q; ++i) x[i] = av[i];
+  const bool last = live && li == L - 1;
+  uint32_t total = 0;
+#pragma unroll
+  for (int step = 0; step < STEPS; ++step) {
+    LimbRun<Q, SUB> run;
+    run.build(x, (step & 1) ? av : bv, valid);
+    const WaveCarry w = wave_carry_masks(run.G && !last, run.P && !last);
+    const uint32_t c = wave_carry_in(w, 0u);
+    run.apply(c);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) x[i] = run.s[i];
+    total += (uint32_t)(run.G | (run.P & (c != 0u)));
+  }
+  if (VEC && valid == Q) {
+#pragma unroll
+    for (int i = 0; i < Q; i += 4)
+      *reinterpret_cast<uint4*>(out + base + j0 + i) = make_uint4(x[i], x[i + 1], x[i + 2], x[i + 3]);
+  } else {
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+      if (i < valid) out[base + j0 + i] = x[i];
+  }
+  if (cout && last) cout[inst] = total;
+}
+
+constexpr int kIpbQ = 4;
+constexpr int kIpbMax = 64 * kIpbQ;   // limbs: one instance fills at most one wave
+
+template <bool SUB, int STEPS>
+static int launch_addsub_ipb(uint32_t* out, uint32_t* cout, const uint32_t* a, const uint32_t* b,
+                             int64_t n, int64_t batch, hipStream_t s) {
+  const int L = (int)cdiv(n, kIpbQ);
+  const int ipw = 64 / L;
+  const int64_t per_wg = 4 * (int64_t)ipw;
+  const dim3 gd((unsigned)((batch + per_wg - 1) / per_wg)), bd(256);
+  const bool vec = (n % 4 == 0) && ((uintptr_t)a % 16 == 0) && ((uintptr_t)b % 16 == 0) &&
+                   ((uintptr_t)out % 16 == 0);
+  if (vec)
+    hipLaunchKernelGGL((k_addsub_ipb<kIpbQ, SUB, STEPS, true>), gd, bd, 0, s, out, cout, a, b,
+                       (int)n, L, ipw, batch);
+  else
+    hipLaunchKernelGGL((k_addsub_ipb<kIpbQ, SUB, STEPS, false>), gd, bd, 0, s, out, cout, a, b,
+                       (int)n, L, ipw, batch);
+  BI_LAUNCH_CHECK();
+  return BIGINT_OK;
+}
+
 template <bool SUB>
 static int launch_addsub_t(uint32_t* out, uint32_t* cout, const uint32_t* a, const uint32_t* b,
                            int64_t n, int64_t batch, hipStream_t s) {
-  // up to 2048 limbs: 256 threads per instance; above: 1024 threads, which
-  // keeps more loads in flight per CU (measured: 5.6 against 4.4 TB/s at 8192
-  // limbs), with 4..32 limbs each
+  // up to 256 limbs: several instances per wave; up to 2048 limbs: 256
+  // threads per instance; above: 1024 threads, which keeps more loads in
+  // flight per CU (measured: 5.6 against 4.4 TB/s at 8192 limbs), with 4..32
+  // limbs each
+  if (n <= kIpbMax) return launch_addsub_ipb<SUB, 1>(out, cout, a, b, n, batch, s);
   if (n <= 1024) return launch_addsub_q<4, SUB>(out, cout, a, b, n, batch, s);
   if (n <= 2048) return launch_addsub_q<8, SUB>(out, cout, a, b, n, batch, s);
   if (n <= 4096) return launch_addsub_q<4, SUB>(out, cout, a, b, n, batch, s);
@@ -335,6 +423,7 @@ int launch_add6(uint32_t* out, uint32_t* ovf, const uint32_t* a, const uint32_t*
                 int64_t batch, hipStream_t s) {
   // six scans per instance: fewer, fuller threads than for one addition pay
   // (measured: 4.4 TB/s at 4096 limbs with 256 threads, 2.2 with 1024)
+  if (n <= kIpbMax) return launch_addsub_ipb<false, 6>(out, ovf, a, b, n, batch, s);
   if (n <= 1024) return launch_add6_q<4>(out, ovf, a, b, n, batch, s);
   if (n <= 2048) return launch_add6_q<8>(out, ovf, a, b, n, batch, s);
   if (n <= 16384) return launch_add6_q<16>(out, ovf, a, b, n, batch, s);

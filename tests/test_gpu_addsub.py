@@ -99,3 +99,27 @@ def test_empty_batch_and_errors(bi):
     # partial overlap between out and a is rejected
     q = ctypes.c_void_p(x.data_ptr() + 4)
     assert L.bigint_add(q, None, p, p, 4, 1, None) == bi.EINVAL
+
+
+@pytest.mark.parametrize("n", [1, 3, 4, 7, 16, 33, 128, 200, 256])
+@pytest.mark.parametrize("batch", [1, 9, 301])
+def test_several_instances_per_wave(bi, orc, n, batch):
+    """Up to 256 limbs several instances share a wave (segmented carry scan):
+    carries must stop at every instance boundary, including all-ones
+    instances next to each other and a last work-group that is not full."""
+    g = np.random.default_rng(n * 1000 + batch)
+    a = rand_limbs(g, batch, n)
+    b = rand_limbs(g, batch, n)
+    a[::3] = 0xFFFFFFFF                  # every third instance: full ripple on add
+    b[::3] = 0
+    b[::3, 0] = 1
+    a[1::3] = 0                          # and borrow ripple on sub
+    b[1::3] = 0
+    b[1::3, 0] = 1
+    _check(bi, orc, a, b)
+    out, ovf = bi.add6(dev(a), dev(b))
+    out, ovf = host(out), ovf.cpu().numpy()
+    for i in range(batch):
+        want, wo = orc.add6_1(a[i], b[i])
+        assert np.array_equal(out[i], want), i
+        assert int(ovf[i]) == int(wo), i
