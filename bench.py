@@ -360,7 +360,8 @@ def ragged_mode(torch, bi, inputs, args):
 
 def divmod_mode(torch, bi, inputs, args):
     """512 divisions (dividend log-uniform in [2^16, 2^18] bits, divisor half
-    as many limbs), and the same-size products for the Div/Mul ratio."""
+    as many limbs), and the same-size products for the Div/Mul ratio; then
+    uniform batches of 2^13..2^18-bit dividends."""
     c = inputs.ragged_div_2e16_2e18()
     nu, nv = c["nu"], c["nv"]
     tu = torch.from_numpy(c["u"].view(np.int32)).cuda()
@@ -384,6 +385,23 @@ def divmod_mode(torch, bi, inputs, args):
         vals, counts = np.unique(cnt[:, col], return_counts=True)
         return {str(int(v)): int(c) for v, c in zip(vals, counts)}
 
+    # uniform batches on the paper's dataset shapes (NumBits x NumInsts = 2^32),
+    # dividend NumBits, divisor half of it; Div/Mul against the product mod B^n
+    # of two dividend-sized operands
+    g = torch.Generator(device="cuda")
+    g.manual_seed(1007)
+    rows = []
+    for bits in (2**13, 2**14, 2**15, 2**16, 2**17, 2**18):
+        n, insts = bits // 32, 2**32 // bits
+        u = _rand_dev(torch, g, insts, n)
+        v = _rand_dev(torch, g, insts, n // 2)
+        v[:, -1] |= 1
+        t_div, _ = time_launches(lambda: bi.divmod(u, v), 3, 1, torch)
+        t_mul, _ = time_launches(lambda: bi.mullo(u, u), 3, 1, torch)
+        rows.append({"num_bits": bits, "num_insts": insts, "divmod_ms": round(t_div / 3, 3),
+                     "mul_ms": round(t_mul / 3, 3), "div_over_mul": round(t_div / t_mul, 2)})
+        del u, v
+        torch.cuda.empty_cache()
     print(json.dumps({"mode": "divmod", "workload": "512 divisions, dividend bits log-uniform in "
                       "[2^16, 2^18], divisor half the limbs", "ms": round(ms, 4),
                       "divs_per_s": round(512 / ms * 1e3, 1),
@@ -391,7 +409,7 @@ def divmod_mode(torch, bi, inputs, args):
                       "all_status_ok": bool((st == 0).all().item()),
                       "newton_steps_histogram": hist(0),
                       "fixup_corrections_histogram": hist(1),
-                      "quotient_corrections_histogram": hist(2)}))
+                      "quotient_corrections_histogram": hist(2), "uniform_rows": rows}))
     plan.close()
     mplan.close()
 
