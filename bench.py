@@ -44,7 +44,8 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=15.0,
                    help="target CPU work (core-seconds) of the oracle sample")
     p.add_argument("--mode", default="bench",
-                   choices=["bench", "copy", "mfma-peak", "ragged", "divmod", "addsub", "poly"],
+                   choices=["bench", "copy", "mfma-peak", "ragged", "divmod", "addsub", "poly",
+                            "configs", "cpu-oracle"],
                    help="copy: a plain copy kernel of known size (counter calibration); "
                         "mfma-peak: register-only int8 MFMA rate probe; ragged / divmod: the "
                         "4096-product ragged batch and the 512-division batch (extra lines)")
@@ -114,6 +115,10 @@ def main():
               "multi-GPU step (instances are independent; see the sharding notes)", file=sys.stderr)
         sys.exit(2)
 
+    if args.mode == "cpu-oracle":
+        from paper_2607_28897_amd import inputs
+        return cpu_oracle_mode(inputs, args)
+
     import torch
     import paper_2607_28897_amd as bi
     from paper_2607_28897_amd import inputs
@@ -130,6 +135,8 @@ def main():
         return addsub_mode(torch, bi, inputs, args)
     if args.mode == "poly":
         return poly_mode(torch, bi, args)
+    if args.mode == "configs":
+        return configs_mode(torch, bi, inputs, args)
 
     cfg = inputs.pairs_2e19(args.batch)
     a_np, b_np, n = cfg["a"], cfg["b"], cfg["n"]
@@ -495,6 +502,119 @@ def poly_mode(torch, bi, args):
         del a, b
         torch.cuda.empty_cache()
     print(json.dumps(res))
+
+
+def configs_mode(torch, bi, inputs, args):
+    """The two smaller uniform configurations, every operation on them:
+    64 pairs of 2^15-bit and 1024 pairs of 2^17-bit integers (half of the
+    latter carry-adversarial).  add / sub (sub on the ordered pairs, a >= b)
+    in GB/s against HBM; full products with the MFMA-split and the plain
+    kernel, compared with each other, against their rooflines."""
+    import ctypes
+    L = bi.lib()
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    res = {"mode": "configs", "rows": []}
+    for name, c in (("64 pairs of 2^15-bit integers, uniform", inputs.pairs_2e15()),
+                    ("1024 pairs of 2^17-bit integers, half carry-adversarial", inputs.pairs_2e17_mixed())):
+        n = c["n"]
+        dev = {k: torch.from_numpy(c[k].view(np.int32)).cuda() for k in ("a", "b", "sub_a", "sub_b")}
+        batch = dev["a"].shape[0]
+        s_out = torch.empty_like(dev["a"])
+        carry = torch.empty(batch, dtype=torch.int32, device="cuda")
+        out_m = torch.empty((batch, 2 * n), dtype=torch.int32, device="cuda")
+        out_p = torch.empty_like(out_m)
+        P = {k: ctypes.c_void_p(v.data_ptr()) for k, v in dev.items()}
+        po, pc = ctypes.c_void_p(s_out.data_ptr()), ctypes.c_void_p(carry.data_ptr())
+
+        def call(rc, what):
+            if rc:
+                raise bi.BigIntError(rc, what)
+
+        runs = {
+            "add": lambda: call(L.bigint_add(po, pc, P["a"], P["b"], n, batch, stream), "bigint_add"),
+            "sub": lambda: call(L.bigint_sub(po, pc, P["sub_a"], P["sub_b"], n, batch, stream), "bigint_sub"),
+            "mul_mfma": lambda: call(L.bigint_mul(ctypes.c_void_p(out_m.data_ptr()), P["a"], n, P["b"], n,
+                                                  batch, bi.MUL_MFMA, stream), "bigint_mul"),
+            "mul_plain": lambda: call(L.bigint_mul(ctypes.c_void_p(out_p.data_ptr()), P["a"], n, P["b"], n,
+                                                   batch, bi.MUL_PLAIN, stream), "bigint_mul"),
+        }
+        row = {"workload": name, "batch": batch, "limbs": n}
+        for k, fn in runs.items():
+            steps = max(5, args.steps // 2) if k != "mul_plain" else 5
+            _, per = time_launches(fn, steps, max(2, args.warmup // 4), torch)
+            row[k + "_ms"] = round(per, 4)
+        byts = 3 * batch * n * 4 + 4 * batch
+        row["add_GBps"] = round(byts / (row["add_ms"] * 1e-3) / 1e9, 1)
+        row["sub_GBps"] = round(byts / (row["sub_ms"] * 1e-3) / 1e9, 1)
+        row["add_frac_hbm"] = round(row["add_GBps"] / HBM_PEAK_GBS, 3)
+        Na = (32 * n + 6) // 7
+        mf = 2.0 * batch * Na * Na / (row["mul_mfma_ms"] * 1e-3) / 1e12
+        row["mul_mfma_TOPs_7bit"] = round(mf, 1)
+        row["mul_mfma_frac"] = round(mf / INT8_PEAK_TOPS, 3)
+        pl = batch * n * n / (row["mul_plain_ms"] * 1e-3) / 1e12
+        row["mul_plain_mads_e12"] = round(pl, 2)
+        row["mul_plain_frac_alu"] = round(pl / MAD_PEAK_TOPS, 3)
+        row["mfma_products_per_s"] = round(batch / (row["mul_mfma_ms"] * 1e-3), 1)
+        row["plain_products_per_s"] = round(batch / (row["mul_plain_ms"] * 1e-3), 1)
+        row["mfma_equals_plain"] = bool(torch.equal(out_m, out_p))
+        res["rows"].append(row)
+        del dev, s_out, carry, out_m, out_p
+        torch.cuda.empty_cache()
+    print(json.dumps(res))
+
+
+def cpu_oracle_mode(inputs, args):
+    """The CPU baseline leg for every operation of every configuration: the
+    oracle as it stands (plain C behind its Python binding, no GPU), on all
+    host cores (every thread takes every cores-th instance) and on one core, each over a bounded sample of the configuration's
+    instances (about --cpu-seconds / 10 of work per line)."""
+    import concurrent.futures as cf
+    import oracle
+    oracle.build()
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    cores = max(1, min(cores, 64))
+    budget = max(0.5, args.cpu_seconds / 10)
+
+    def rows(flat, off):
+        return [flat[off[i]:off[i + 1]] for i in range(len(off) - 1)]
+
+    c1, c2, c3 = inputs.pairs_2e15(), inputs.pairs_2e17_mixed(), inputs.pairs_2e19()
+    c4, c5 = inputs.ragged_mul_2e15_2e19(), inputs.ragged_div_2e16_2e18()
+    work = []
+    for name, c in (("64 x 2^15 bits", c1), ("1024 x 2^17 bits", c2), ("256 x 2^19 bits", c3)):
+        a, b, sa, sb = c["a"], c["b"], c.get("sub_a", c["a"]), c.get("sub_b", c["b"])
+        work.append((name, "add", "adds/s", [lambda i, a=a, b=b: oracle.add1(a[i], b[i])], len(a)))
+        work.append((name, "sub", "subs/s", [lambda i, a=sa, b=sb: oracle.sub1(a[i], b[i])], len(a)))
+        work.append((name, "mul", "muls/s", [lambda i, a=a, b=b: oracle.mul1(a[i], b[i])], len(a)))
+    ra, rb = rows(c4["a"], c4["a_off"]), rows(c4["b"], c4["b_off"])
+    work.append(("4096 ragged, 2^15..2^19 bits", "mul", "muls/s",
+                 [lambda i: oracle.mul1(ra[i], rb[i])], len(ra)))
+    ru, rv = rows(c5["u"], c5["u_off"]), rows(c5["v"], c5["v_off"])
+    work.append(("512 ragged divisions, 2^16..2^18 bits", "divmod", "divs/s",
+                 [lambda i: oracle.divmod1(ru[i], rv[i])], len(ru)))
+    out = []
+    for name, op, unit, (fn,), batch in work:
+        # one core: instances in order until the budget is spent
+        t0 = time.perf_counter()
+        k = 0
+        while k < batch and (k == 0 or time.perf_counter() - t0 < budget):
+            fn(k)
+            k += 1
+        one = (time.perf_counter() - t0) / k
+        # all cores: a sample sized to about the same wall time
+        m = int(min(batch, max(cores, cores * budget / max(one, 1e-7))))
+        with cf.ThreadPoolExecutor(max_workers=cores) as ex:
+            list(ex.map(lambda _: None, range(cores)))     # threads started before the clock
+            t0 = time.perf_counter()
+            futs = [ex.submit(lambda lo: [fn(i) for i in range(lo, m, cores)], w) for w in range(cores)]
+            for f in futs:
+                f.result()
+            wall = time.perf_counter() - t0
+        out.append({"workload": name, "op": op, "unit": unit, "cores": cores,
+                    "value": round(m / wall, 2), "one_core": round(1.0 / one, 2),
+                    "sample": f"{m} of {batch} (all cores), {k} (one core)"})
+        print(json.dumps(out[-1]), flush=True)
+    return out
 
 
 def kernel_sha():
