@@ -288,7 +288,12 @@ int bigint_set_mfma_config(int strips_per_band, int waves, int digit_bits);
 
 /* The tile configuration bigint_mul would use on this thread for an na x nb
  * product (tuned table, then this thread's overrides), written to the three
- * host ints.  BIGINT_EUNSUPPORTED if the MFMA multiply does not take that
+ * host ints.  Where the table gives one wave per instance, bigint_mul runs
+ * it only for batches of at least na*nb/64 instances, bigint_mullo for at
+ * least n*n/256, bigint_poly for at least n*n/16, and 4 waves per instance
+ * below that (one
+ * wave per instance leaves most CUs idle on small batches); a wave count set
+ * with bigint_set_mfma_config is used at every batch.  BIGINT_EUNSUPPORTED if the MFMA multiply does not take that
  * size with it; BIGINT_EINVAL for null pointers or sizes < 1. */
 int bigint_mfma_config(int64_t na, int64_t nb, int* strips_per_band, int* waves,
                        int* digit_bits);

@@ -65,6 +65,31 @@ MfmaCfg current_mfma_cfg(int na, int nb) {
   return c;
 }
 
+// One wave per instance pays only once the batch keeps every CU busy with
+// several instances, since the latency of one instance on one wave grows
+// with na*nb.  Measured crossovers on MI355X (128..1024 limbs), in instances:
+// about na*nb/64 for full products (256 at 128 limbs, 1024 at 256, 4096 at
+// 512, 16384 at 1024), n*n/256 for products mod B^n (half the strips), and
+// n*n/16 for Poly (its four products and three additions per wave).  Smaller
+// uniform batches run 4 waves per instance: full products with the table's
+// strips per band, products mod B^n and Poly with 4 strips per band, so that
+// their fewer bands still reach all four waves.  At 64 pairs of 1024 limbs
+// that is 2.5x faster.  Settings of bigint_set_mfma_config are kept.
+constexpr int kWaveFull = 64, kWaveLow = 256, kWavePoly = 16;
+
+static bool wave_batch(int64_t na, int64_t nb, int64_t batch, int per) {
+  return batch * per >= na * nb;
+}
+
+static MfmaCfg uniform_mfma_cfg(int na, int nb, int64_t batch, bool low) {
+  MfmaCfg c = current_mfma_cfg(na, nb);
+  if (c.waves == 1 && t_cfg_waves == 0 && !wave_batch(na, nb, batch, low ? kWaveLow : kWaveFull)) {
+    c.waves = 4;
+    if (low && t_cfg_P == 0) c.P = 4;
+  }
+  return c;
+}
+
 int num_cus() {
   static int n = 0;
   if (n == 0) {
@@ -189,7 +214,7 @@ int bigint_mul(uint32_t* out, const uint32_t* a, int64_t na, const uint32_t* b, 
     if (e != hipSuccess) { set_hip_error(e); return BIGINT_EHIP; }
     return BIGINT_OK;
   }
-  const MfmaCfg cfg = current_mfma_cfg((int)na, (int)nb);
+  const MfmaCfg cfg = uniform_mfma_cfg((int)na, (int)nb, batch, false);
   int use = algo;
   if (use == BIGINT_MUL_AUTO)
     use = (mfma_fits(na, nb, cfg) && std::min(na, nb) >= 64) ? BIGINT_MUL_MFMA : BIGINT_MUL_PLAIN;
@@ -209,7 +234,7 @@ int bigint_mullo(uint32_t* out, const uint32_t* a, const uint32_t* b, int64_t n,
   if (batch > 0x7fffffff || n > BIGINT_MFMA_MAX_LIMBS) return BIGINT_EUNSUPPORTED;
   const size_t bytes = (size_t)n * batch * 4;
   if (overlap(out, bytes, a, bytes) || overlap(out, bytes, b, bytes)) return BIGINT_EINVAL;
-  const MfmaCfg cfg = current_mfma_cfg((int)n, (int)n);
+  const MfmaCfg cfg = uniform_mfma_cfg((int)n, (int)n, batch, true);
   if (!mfma_fits(n, n, cfg)) return BIGINT_EUNSUPPORTED;
   if (batch == 0) return BIGINT_OK;
   return launch_mul_mfma(out, nullptr, a, n, b, n, batch, cfg, (hipStream_t)stream, (int)n);
@@ -240,8 +265,8 @@ int bigint_poly(uint32_t* out, const uint32_t* a, const uint32_t* b, int64_t n, 
   if (overlap(out, bytes, a, bytes) || overlap(out, bytes, b, bytes)) return BIGINT_EINVAL;
   MfmaCfg cfg = default_mfma_cfg((int)n, (int)n);
   cfg.dw = 8;
-  if (cfg.waves == 1 && mfma_wave_fits(n, n)) {
-    // small operands: one wave per instance, like the products of the table
+  if (cfg.waves == 1 && mfma_wave_fits(n, n) && wave_batch(n, n, batch, kWavePoly)) {
+    // small operands in large batches: one wave per instance, like the products
     if (batch == 0) return BIGINT_OK;
     const int P = cfg.P == 4 ? 4 : 8;
     const int chunk = poly_wave_chunk((int)n, batch, P);
@@ -255,7 +280,7 @@ int bigint_poly(uint32_t* out, const uint32_t* a, const uint32_t* b, int64_t n, 
     if (e != hipSuccess) { set_hip_error(e); return BIGINT_EHIP; }
     return BIGINT_OK;
   }
-  if (cfg.waves == 1) cfg = MfmaCfg{4, 4, 8};   // the work-group kernel
+  if (cfg.waves == 1) cfg = MfmaCfg{4, 4, 8};   // the work-group kernel, as for products mod B^n
   if (poly_lds((int)n, cfg) > 163840) return BIGINT_EUNSUPPORTED;
   if (batch == 0) return BIGINT_OK;
   // launches of `grid` work-groups, each owning 2n limbs of workspace

@@ -307,3 +307,27 @@ def test_one_wave_per_instance(bi, orc, P, na, nb, B):
         assert np.array_equal(p[i], orc.mul1(a[i], b[i])), i
         if lo is not None:
             assert np.array_equal(lo[i], orc.mul1(a[i], a[i])[:na]), i
+
+
+@pytest.mark.parametrize("n", [128, 256])
+def test_batch_decides_waves(bi, orc, n):
+    """Uniform batches from n*n/64 instances up (products mod B^n: n*n/256,
+    Poly: n*n/16) run the table's one-wave-per-instance kernel, smaller ones
+    4 waves per instance: the rows of a batch at the threshold and of one just
+    below it must be the same bytes, and sampled rows the oracle's."""
+    g = np.random.default_rng(n + 11)
+    assert bi.mfma_config(n, n)[1] == 1
+    for B, ops in ((n * n // 64, ("mul",)), (n * n // 256, ("mullo",)), (n * n // 16, ("poly",))):
+        a = rand_limbs(g, B, n)
+        b = rand_limbs(g, B, n)
+        a[0] = 0xFFFFFFFF
+        b[0] = 0xFFFFFFFF
+        ta, tb = dev(a), dev(b)
+        for op in ops:
+            f = {"mul": lambda x, y: bi.mul(x, y, bi.MUL_MFMA), "mullo": bi.mullo, "poly": bi.poly}[op]
+            ref = {"mul": orc.mul1, "mullo": orc.mullo1, "poly": orc.poly1}[op]
+            big = host(f(ta, tb))
+            small = host(f(ta[:B - 1], tb[:B - 1]))
+            assert np.array_equal(big[:B - 1], small), op
+            for i in (0, 1, B // 2, B - 2, B - 1):
+                assert np.array_equal(big[i], ref(a[i], b[i])), (op, i)
