@@ -54,10 +54,11 @@ def parse():
     return p.parse_args()
 
 
-def time_launches(fn, steps, warmup, torch):
+def time_launches(fn, steps, warmup, torch, per_launch=None):
     """Run fn (one kernel launch on torch's current stream) warmup + steps
     times; returns (total_ms over the timed steps, mean per-launch ms from
-    per-launch event pairs)."""
+    per-launch event pairs).  per_launch (a list), if given, receives every
+    launch's ms."""
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
@@ -75,6 +76,8 @@ def time_launches(fn, steps, warmup, torch):
     torch.cuda.synchronize()
     total = t_start.elapsed_time(t_end)
     per = [e0.elapsed_time(e1) for e0, e1 in ev]
+    if per_launch is not None:
+        per_launch.extend(per)
     return total, float(np.mean(per))
 
 
@@ -162,7 +165,8 @@ def main():
             raise bi.BigIntError(rc, "bigint_mul")
 
     torch.cuda.synchronize()
-    total_ms, kernel_ms = time_launches(run_mfma, args.steps, args.warmup, torch)
+    per = []
+    total_ms, kernel_ms = time_launches(run_mfma, args.steps, args.warmup, torch, per)
     print(f"# mfma: {total_ms / args.steps:.4f} ms/step", file=sys.stderr, flush=True)
     p_steps = max(3, args.steps // 10)
     p_total, p_kernel = time_launches(run_plain, p_steps, 1, torch)
@@ -231,6 +235,8 @@ def main():
             "frac": round(achieved / INT8_PEAK_TOPS, 4),
             "traffic": traffic,
             "kernel_ms": round(kernel_ms, 4),
+            "kernel_ms_median": round(float(np.median(per)), 4),
+            "kernel_ms_min": round(float(np.min(per)), 4),
             "algorithmic_unit": "2 x 74,899^2 int8 ops (7-bit digit products) per 2^19-bit product",
             "executed_TOPs": round(executed, 1),
             "executed_frac": round(executed / INT8_PEAK_TOPS, 4),
