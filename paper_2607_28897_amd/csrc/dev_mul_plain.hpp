@@ -62,6 +62,37 @@ __device__ __forceinline__ void mac64(AccCol& a, uint64_t x, uint64_t y) {
       : "v"(x0), "v"(x1), "v"(y0), "v"(y1));
 }
 
+// a += x * ya and b += x * yb in one block: the compiler separates inline asm
+// blocks with a wait state (it cannot see which carry masks they share), so
+// fewer, longer blocks issue faster.  Carry masks are read four or more
+// instructions after they are written.
+__device__ __forceinline__ void mac64x2(AccCol& a, AccCol& b, uint64_t x, uint64_t ya, uint64_t yb) {
+  const uint32_t x0 = (uint32_t)x, x1 = (uint32_t)(x >> 32);
+  const uint32_t a0 = (uint32_t)ya, a1 = (uint32_t)(ya >> 32);
+  const uint32_t b0 = (uint32_t)yb, b1 = (uint32_t)(yb >> 32);
+  uint64_t k0, k1, k2, k3, k4, k5, k6, k7;
+  asm("v_mad_u64_u32 %0, %12, %20, %22, %0\n\t"
+      "v_mad_u64_u32 %1, %13, %20, %23, %1\n\t"
+      "v_mad_u64_u32 %2, %14, %21, %23, %2\n\t"
+      "v_mad_u64_u32 %1, %15, %21, %22, %1\n\t"
+      "v_mad_u64_u32 %6, %16, %20, %24, %6\n\t"
+      "v_mad_u64_u32 %7, %17, %20, %25, %7\n\t"
+      "v_mad_u64_u32 %8, %18, %21, %25, %8\n\t"
+      "v_mad_u64_u32 %7, %19, %21, %24, %7\n\t"
+      "v_addc_co_u32_e64 %3, %12, 0, %3, %12\n\t"
+      "v_addc_co_u32_e64 %4, %13, 0, %4, %13\n\t"
+      "v_addc_co_u32_e64 %5, %14, 0, %5, %14\n\t"
+      "v_addc_co_u32_e64 %4, %15, 0, %4, %15\n\t"
+      "v_addc_co_u32_e64 %9, %16, 0, %9, %16\n\t"
+      "v_addc_co_u32_e64 %10, %17, 0, %10, %17\n\t"
+      "v_addc_co_u32_e64 %11, %18, 0, %11, %18\n\t"
+      "v_addc_co_u32_e64 %10, %19, 0, %10, %19"
+      : "+v"(a.s0), "+v"(a.s1), "+v"(a.s2), "+v"(a.c0), "+v"(a.c1), "+v"(a.c2),
+        "+v"(b.s0), "+v"(b.s1), "+v"(b.s2), "+v"(b.c0), "+v"(b.c1), "+v"(b.c2),
+        "=&s"(k0), "=&s"(k1), "=&s"(k2), "=&s"(k3), "=&s"(k4), "=&s"(k5), "=&s"(k6), "=&s"(k7)
+      : "v"(x0), "v"(x1), "v"(a0), "v"(a1), "v"(b0), "v"(b1));
+}
+
 // the (lo, hi, carry) triple of 64-bit digits that an AccCol stands for
 __device__ __forceinline__ Acc3 acc_fold(const AccCol& a) {
   // value = s0 + s1 2^32 + (s2 + c0) 2^64 + c1 2^96 + c2 2^128
@@ -134,7 +165,30 @@ __device__ __forceinline__ void wg_mul_plain(uint32_t* out, const uint32_t* __re
       uint64_t w[Q];
 #pragma unroll
       for (int q = 0; q < Q; ++q) w[q] = Bd[k0 - I_hi + q];
-      for (int i = I_hi; i >= I_lo; --i) {
+      int i = I_hi;
+      // rounds of Q steps.  Step j of a round (from i) has the window
+      // B[k0 - i + j + q] = w[q + j], or nx[q + j - Q] past the ring's end,
+      // so the ring turns at compile time and the round's digits of A and
+      // of B are read at its start (the reads past mb - 1 are clamped; their
+      // values are never used)
+      for (; i - (Q - 1) >= I_lo; i -= Q) {
+        uint64_t x[Q], nx[Q];
+#pragma unroll
+        for (int j = 0; j < Q; ++j) x[j] = A[i - j];
+#pragma unroll
+        for (int j = 0; j < Q; ++j) nx[j] = Bd[min(k0 - i + Q + j, mb - 1)];
+        static_assert(Q % 2 == 0, "columns go in pairs");
+#pragma unroll
+        for (int j = 0; j < Q; ++j)
+#pragma unroll
+          for (int q = 0; q < Q; q += 2)
+            mac64x2(col[q], col[q + 1], x[j], q + j < Q ? w[q + j] : nx[q + j - Q],
+                    q + 1 + j < Q ? w[q + 1 + j] : nx[q + 1 + j - Q]);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) w[q] = nx[q];
+      }
+      // the last steps one at a time
+      for (; i >= I_lo; --i) {
         const uint64_t x = A[i];
         // the window's next digit, read before it is needed (clamped: the
         // value read after the last step is not used)
