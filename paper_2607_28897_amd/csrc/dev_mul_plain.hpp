@@ -113,7 +113,9 @@ __device__ __forceinline__ void add_into(uint64_t& tl, uint64_t& th, uint64_t v)
   th += c;
 }
 
-// LDS bytes needed by wg_mul_plain for an (na x nb)-limb product
+// LDS bytes needed by wg_mul_plain for an (na x nb)-limb product: the two
+// operands as u64 digits, then 64 bytes of carry-scan scratch (whose first
+// digit the common loop may read, unused, just past B)
 __host__ __device__ inline size_t plain_lds_bytes(int na, int nb) {
   const int ma = (na + 1) / 2, mb = (nb + 1) / 2;
   return (size_t)(ma + mb) * 8 + 64;
@@ -169,14 +171,17 @@ __device__ __forceinline__ void wg_mul_plain(uint32_t* out, const uint32_t* __re
       // rounds of Q steps.  Step j of a round (from i) has the window
       // B[k0 - i + j + q] = w[q + j], or nx[q + j - Q] past the ring's end,
       // so the ring turns at compile time and the round's digits of A and
-      // of B are read at its start (the reads past mb - 1 are clamped; their
-      // values are never used)
+      // of B are read at its start.  A round reads B up to index
+      // k0 - i + 2Q - 1 <= k0 - I_lo + Q <= mb: at most one digit past B,
+      // the first of the scratch area that follows it in LDS (always
+      // allocated); that value is never used.  Unclamped, the Q reads share
+      // one address.
       for (; i - (Q - 1) >= I_lo; i -= Q) {
         uint64_t x[Q], nx[Q];
 #pragma unroll
         for (int j = 0; j < Q; ++j) x[j] = A[i - j];
 #pragma unroll
-        for (int j = 0; j < Q; ++j) nx[j] = Bd[min(k0 - i + Q + j, mb - 1)];
+        for (int j = 0; j < Q; ++j) nx[j] = Bd[k0 - i + Q + j];
         static_assert(Q % 2 == 0, "columns go in pairs");
 #pragma unroll
         for (int j = 0; j < Q; ++j)
