@@ -176,21 +176,32 @@ __device__ __forceinline__ void wg_mul_plain(uint32_t* out, const uint32_t* __re
       // the first of the scratch area that follows it in LDS (always
       // allocated); that value is never used.  Unclamped, the Q reads share
       // one address.
-      for (; i - (Q - 1) >= I_lo; i -= Q) {
-        uint64_t x[Q], nx[Q];
+      static_assert(Q % 2 == 0, "columns go in pairs");
+      // one round from i with window `win`; the round's new digits go to `nw`
+      auto round = [&](int i0, const uint64_t (&win)[Q], uint64_t (&nw)[Q]) {
+        uint64_t x[Q];
 #pragma unroll
-        for (int j = 0; j < Q; ++j) x[j] = A[i - j];
+        for (int j = 0; j < Q; ++j) x[j] = A[i0 - j];
 #pragma unroll
-        for (int j = 0; j < Q; ++j) nx[j] = Bd[k0 - i + Q + j];
-        static_assert(Q % 2 == 0, "columns go in pairs");
+        for (int j = 0; j < Q; ++j) nw[j] = Bd[k0 - i0 + Q + j];
 #pragma unroll
         for (int j = 0; j < Q; ++j)
 #pragma unroll
           for (int q = 0; q < Q; q += 2)
-            mac64x2(col[q], col[q + 1], x[j], q + j < Q ? w[q + j] : nx[q + j - Q],
-                    q + 1 + j < Q ? w[q + 1 + j] : nx[q + 1 + j - Q]);
+            mac64x2(col[q], col[q + 1], x[j], q + j < Q ? win[q + j] : nw[q + j - Q],
+                    q + 1 + j < Q ? win[q + 1 + j] : nw[q + 1 + j - Q]);
+      };
+      // two rounds per pass, the rings swapping roles (no register moves)
+      uint64_t v[Q];
+      for (; i - (2 * Q - 1) >= I_lo; i -= 2 * Q) {
+        round(i, w, v);
+        round(i - Q, v, w);
+      }
+      if (i - (Q - 1) >= I_lo) {
+        round(i, w, v);
 #pragma unroll
-        for (int q = 0; q < Q; ++q) w[q] = nx[q];
+        for (int q = 0; q < Q; ++q) w[q] = v[q];
+        i -= Q;
       }
       // the last steps one at a time
       for (; i >= I_lo; --i) {
