@@ -481,11 +481,11 @@ static int plan_build_div(bigint_plan_s* p) {
 }
 
 static void plan_free(bigint_plan_s* p) {
-  if (p->exec) hipGraphExecDestroy(p->exec);
-  if (p->graph) hipGraphDestroy(p->graph);
-  if (p->cap_stream) hipStreamDestroy(p->cap_stream);
-  if (p->d_queue) hipFree(p->d_queue);
-  if (p->ws_owned && p->ws) hipFree(p->ws);
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+  if (p->d_queue) (void)hipFree(p->d_queue);
+  if (p->ws_owned && p->ws) (void)hipFree(p->ws);
   delete p;
 }
 
@@ -525,7 +525,7 @@ int bigint_plan_workspace_size(bigint_plan_t plan, size_t* bytes) {
 int bigint_plan_set_workspace(bigint_plan_t plan, void* dev, size_t bytes) {
   if (!plan || (!dev && bytes)) return BIGINT_EINVAL;
   if (bytes < plan->ws_need) return BIGINT_EINVAL;
-  if (plan->ws_owned && plan->ws) hipFree(plan->ws);
+  if (plan->ws_owned && plan->ws) (void)hipFree(plan->ws);
   plan->ws = dev;
   plan->ws_bytes = bytes;
   plan->ws_owned = false;
@@ -559,14 +559,14 @@ int bigint_mul_ragged(uint32_t* out, const int64_t* out_off, const uint32_t* a,
   if ((plan->flags & BIGINT_PLAN_NO_GRAPH) || s == nullptr) return launch(s);
   const void* key[6] = {out, out_off, a, a_off, b, b_off};
   if (!plan->exec || memcmp(key, plan->key, sizeof(key)) != 0) {
-    if (plan->exec) { hipGraphExecDestroy(plan->exec); plan->exec = nullptr; }
-    if (plan->graph) { hipGraphDestroy(plan->graph); plan->graph = nullptr; }
+    if (plan->exec) { (void)hipGraphExecDestroy(plan->exec); plan->exec = nullptr; }
+    if (plan->graph) { (void)hipGraphDestroy(plan->graph); plan->graph = nullptr; }
     if (!plan->cap_stream) BI_HIP(hipStreamCreateWithFlags(&plan->cap_stream, hipStreamNonBlocking));
     BI_HIP(hipStreamBeginCapture(plan->cap_stream, hipStreamCaptureModeThreadLocal));
     const int rc = launch(plan->cap_stream);
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(plan->cap_stream, &g);
-    if (rc != BIGINT_OK) { if (g) hipGraphDestroy(g); return rc; }
+    if (rc != BIGINT_OK) { if (g) (void)hipGraphDestroy(g); return rc; }
     if (e != hipSuccess) { set_hip_error(e); return BIGINT_EHIP; }
     plan->graph = g;
     BI_HIP(hipGraphInstantiate(&plan->exec, g, nullptr, nullptr, 0));

@@ -183,7 +183,14 @@ static int launch_addsub_t(uint32_t* out, uint32_t* cout, const uint32_t* a, con
   if (n <= kIpbMax) return launch_addsub_ipb<SUB, 1>(out, cout, a, b, n, batch, s);
   if (n <= 1024) return launch_addsub_q<4, SUB>(out, cout, a, b, n, batch, s);
   if (n <= 2048) return launch_addsub_q<8, SUB>(out, cout, a, b, n, batch, s);
-  if (n <= 4096) return launch_addsub_q<4, SUB>(out, cout, a, b, n, batch, s);
+  if (n <= 4096) {
+    // 1024-thread groups sit two per CU; when the batch needs a second round
+    // of them but four 512-thread groups per CU hold it at once, the smaller
+    // groups finish in one round (1024 x 2^17 bits: 13.0 -> 11.8 us)
+    const int64_t cus = num_cus();
+    if (batch > 2 * cus && batch <= 4 * cus) return launch_addsub_q<8, SUB>(out, cout, a, b, n, batch, s);
+    return launch_addsub_q<4, SUB>(out, cout, a, b, n, batch, s);
+  }
   if (n <= 8192) return launch_addsub_q<8, SUB>(out, cout, a, b, n, batch, s);
   if (n <= 16384) return launch_addsub_q<16, SUB>(out, cout, a, b, n, batch, s);
   if (n <= 32768) return launch_addsub_q<32, SUB>(out, cout, a, b, n, batch, s);

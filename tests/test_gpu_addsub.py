@@ -123,3 +123,22 @@ def test_several_instances_per_wave(bi, orc, n, batch):
         want, wo = orc.add6_1(a[i], b[i])
         assert np.array_equal(out[i], want), i
         assert int(ovf[i]) == int(wo), i
+
+
+@pytest.mark.parametrize("n", [2049, 3001, 4096])
+def test_batches_of_two_to_four_groups_per_cu(bi, orc, n):
+    """Between 2048 and 4096 limbs a batch of 2..4 instances per CU runs on
+    512-thread work-groups instead of 1024-thread ones."""
+    import torch
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    batch = 3 * cus
+    g = np.random.default_rng(n + 17)
+    a = rand_limbs(g, batch, n)
+    b = rand_limbs(g, batch, n)
+    a[::5] = 0xFFFFFFFF                  # full ripples across every thread
+    b[::5] = 0
+    b[::5, 0] = 1
+    a[1::5] = 0
+    b[1::5] = 0
+    b[1::5, 0] = 1
+    _check(bi, orc, a, b)
