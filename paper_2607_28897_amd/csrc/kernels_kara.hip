@@ -17,9 +17,12 @@ namespace bi {
 // d = |x - y| over n limbs and sgn = sign(x - y) (x: nx limbs, y: ny limbs,
 // zero-extended; n <= 16 * blockDim.x).  Both differences are formed in the
 // same pass; the borrow out of x - y picks one.  blockIdx.y = 0: x = a0,
-// y = a1; = 1: x = b1, y = b0.
+// y = a1; = 1: x = b1, y = b0.  VEC: every run of four limbs is read and
+// written with one 16-byte access (n a multiple of 8, so h, nx and ny are
+// multiples of 4, and the buffers 16-byte aligned).
 constexpr int kKaraQ = 16;
 
+template <bool VEC>
 __global__ __launch_bounds__(1024) void k_kara_diff(uint32_t* ws, int64_t ws_stride, int32_t* sgn,
                                                     const uint32_t* a, const uint32_t* b, int n,
                                                     int h) {
@@ -36,12 +39,24 @@ __global__ __launch_bounds__(1024) void k_kara_diff(uint32_t* ws, int64_t ws_str
   const int j0 = threadIdx.x * kKaraQ;
   const int valid = min(kKaraQ, max(0, h - j0));
   uint32_t xv[kKaraQ], yv[kKaraQ];
+  if (VEC) {
+    const uint4 z = make_uint4(0u, 0u, 0u, 0u);
 #pragma unroll
-  for (int i = 0; i < kKaraQ; ++i) {
-    const int j = j0 + i;
-    const uint32_t xa = x[max(min(j, nx - 1), 0)], ya = y[max(min(j, ny - 1), 0)];
-    xv[i] = (i < valid && j < nx) ? xa : 0u;
-    yv[i] = (i < valid && j < ny) ? ya : 0u;
+    for (int i = 0; i < kKaraQ; i += 4) {
+      const int j = j0 + i;
+      const uint4 xa = (i < valid && j < nx) ? *reinterpret_cast<const uint4*>(x + j) : z;
+      const uint4 ya = (i < valid && j < ny) ? *reinterpret_cast<const uint4*>(y + j) : z;
+      xv[i] = xa.x; xv[i + 1] = xa.y; xv[i + 2] = xa.z; xv[i + 3] = xa.w;
+      yv[i] = ya.x; yv[i + 1] = ya.y; yv[i + 2] = ya.z; yv[i + 3] = ya.w;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < kKaraQ; ++i) {
+      const int j = j0 + i;
+      const uint32_t xa = x[max(min(j, nx - 1), 0)], ya = y[max(min(j, ny - 1), 0)];
+      xv[i] = (i < valid && j < nx) ? xa : 0u;
+      yv[i] = (i < valid && j < ny) ? ya : 0u;
+    }
   }
   LimbRun<kKaraQ, true> r1, r2;
   r1.build(xv, yv, valid);
@@ -56,9 +71,18 @@ __global__ __launch_bounds__(1024) void k_kara_diff(uint32_t* ws, int64_t ws_str
 #pragma unroll
   for (int i = 0; i < kKaraQ; ++i) nz |= r1.s[i] != 0u;
   const bool any = __syncthreads_or(nz);
+  if (VEC) {
 #pragma unroll
-  for (int i = 0; i < kKaraQ; ++i)
-    if (i < valid) d[j0 + i] = borrow ? r2.s[i] : r1.s[i];
+    for (int i = 0; i < kKaraQ; i += 4)
+      if (i < valid)
+        *reinterpret_cast<uint4*>(d + j0 + i) =
+            borrow ? make_uint4(r2.s[i], r2.s[i + 1], r2.s[i + 2], r2.s[i + 3])
+                   : make_uint4(r1.s[i], r1.s[i + 1], r1.s[i + 2], r1.s[i + 3]);
+  } else {
+#pragma unroll
+    for (int i = 0; i < kKaraQ; ++i)
+      if (i < valid) d[j0 + i] = borrow ? r2.s[i] : r1.s[i];
+  }
   if (threadIdx.x == 0) sgn[2 * inst + (side_b ? 1 : 0)] = borrow ? -1 : (any ? 1 : 0);
 }
 
@@ -102,6 +126,13 @@ constexpr int kCombQ = 4;
 constexpr int kCombChunk = 1024 * kCombQ;
 constexpr int kCombMaxChunks = 16;   // 2n <= 16 * 4096 limbs (h <= 16384)
 
+//
+// VEC (n a multiple of 8, buffers 16-byte aligned): the region bounds h, 2h,
+// 3h and h + 2(n - h) are multiples of 4, so each thread's four limbs share
+// one case and every source is read with one 16-byte load per run; the high
+// part of the sum just below a thread's run comes from the lane below (the
+// first lane of a wave evaluates it on its own).
+template <bool VEC>
 __global__ __launch_bounds__(1024) void k_kara_combine(uint32_t* out, const uint32_t* ws,
                                                        int64_t ws_stride, const int32_t* sgn,
                                                        uint32_t* summ, int n, int h) {
@@ -133,21 +164,56 @@ __global__ __launch_bounds__(1024) void k_kara_combine(uint32_t* out, const uint
     }
     return v;
   };
-  // thread i: limbs [i Q, i Q + Q) of the chunk, from the Q + 1 sums
-  // t(k - 1) .. t(k + Q - 1) (each computed once); one round, one scan
+  // thread i: limbs [i Q, i Q + Q) of the chunk; limb k adds the low half of
+  // the sum t(k) and the high half of t(k - 1); one round, one scan
   const int j0 = threadIdx.x * kCombQ;
   const int valid = min(kCombQ, max(0, len - j0));
-  uint64_t tv[kCombQ + 1];
-#pragma unroll
-  for (int i = 0; i <= kCombQ; ++i) {
-    const int k = k0 + j0 + i - 1;
-    tv[i] = (k >= 0 && k < 2 * n) ? t(k) : 0ull;
-  }
   uint32_t x[kCombQ], y[kCombQ];
+  if (VEC) {
+    static_assert(kCombQ == 4, "one 16-byte run per thread");
+    uint64_t v[4] = {0ull, 0ull, 0ull, 0ull};
+    const int k = k0 + j0;
+    if (valid > 0) {
+      auto add4 = [&](const uint32_t* src, bool inv) {
+        const uint4 u = *reinterpret_cast<const uint4*>(src);
+        v[0] += inv ? ~u.x : u.x;
+        v[1] += inv ? ~u.y : u.y;
+        v[2] += inv ? ~u.z : u.z;
+        v[3] += inv ? ~u.w : u.w;
+      };
+      add4(k < 2 * h ? p0 + k : p2 + (k - 2 * h), false);
+      const int j = k - h;
+      if (j >= 0 && j < 2 * h) {
+        add4(p0 + j, false);
+        if (s != 0) add4(pm + j, s < 0);
+      }
+      if (j >= 0 && j < l2) add4(p2 + j, false);
+      if (s < 0) {
+        if (k == h) v[0] += 1u;
+        if (k >= 3 * h) {
+          v[0] += 0xffffffffu; v[1] += 0xffffffffu; v[2] += 0xffffffffu; v[3] += 0xffffffffu;
+        }
+      }
+    }
+    uint32_t below = (uint32_t)__shfl_up((int)(uint32_t)(v[3] >> 32), 1);
+    if (lane_id() == 0) below = (k >= 1 && valid > 0) ? (uint32_t)(t(k - 1) >> 32) : 0u;
 #pragma unroll
-  for (int i = 0; i < kCombQ; ++i) {
-    x[i] = i < valid ? (uint32_t)tv[i + 1] : 0u;
-    y[i] = i < valid ? (uint32_t)(tv[i] >> 32) : 0u;
+    for (int i = 0; i < 4; ++i) {
+      x[i] = (uint32_t)v[i];
+      y[i] = i == 0 ? below : (uint32_t)(v[i - 1] >> 32);
+    }
+  } else {
+    uint64_t tv[kCombQ + 1];
+#pragma unroll
+    for (int i = 0; i <= kCombQ; ++i) {
+      const int k = k0 + j0 + i - 1;
+      tv[i] = (k >= 0 && k < 2 * n) ? t(k) : 0ull;
+    }
+#pragma unroll
+    for (int i = 0; i < kCombQ; ++i) {
+      x[i] = i < valid ? (uint32_t)tv[i + 1] : 0u;
+      y[i] = i < valid ? (uint32_t)(tv[i] >> 32) : 0u;
+    }
   }
   LimbRun<kCombQ, false> run;
   run.build(x, y, valid);
@@ -155,12 +221,18 @@ __global__ __launch_bounds__(1024) void k_kara_combine(uint32_t* out, const uint
   const uint32_t cin = wg_carry_scan(run.G, run.P, 0u, scratch, &c);
   run.apply(cin);
   bool ones = true;
+  if (VEC) {
+    if (valid > 0) *reinterpret_cast<uint4*>(o + j0) = make_uint4(run.s[0], run.s[1], run.s[2], run.s[3]);
 #pragma unroll
-  for (int i = 0; i < kCombQ; ++i)
-    if (i < valid) {
-      o[j0 + i] = run.s[i];
-      ones = ones && run.s[i] == 0xffffffffu;
-    }
+    for (int i = 0; i < kCombQ; ++i) ones = ones && (i >= valid || run.s[i] == 0xffffffffu);
+  } else {
+#pragma unroll
+    for (int i = 0; i < kCombQ; ++i)
+      if (i < valid) {
+        o[j0 + i] = run.s[i];
+        ones = ones && run.s[i] == 0xffffffffu;
+      }
+  }
   const bool all = __syncthreads_and(ones);
   if (threadIdx.x == 0) summ[inst * kCombMaxChunks + chunk] = c | (all ? 2u : 0u);
 }
@@ -211,8 +283,17 @@ int launch_mul_kara(uint32_t* out, const uint32_t* a, const uint32_t* b, int64_t
   if (nch > kCombMaxChunks) return BIGINT_EUNSUPPORTED;
   // |a0 - a1| at ws[0..h), |b1 - b0| at ws[h..2h), signs
   const int T = (int)((cdiv(h, kKaraQ) + 63) / 64 * 64);
-  hipLaunchKernelGGL(k_kara_diff, dim3((unsigned)batch, 2), dim3(T), 0, s, ws, ws_stride, sgn, a,
-                     b, (int)n, h);
+  // 16-byte runs: n a multiple of 8 (h, n - h, 2h, 3h multiples of 4) and
+  // aligned buffers (the workspace stride 10h + 16 keeps each instance's
+  // parts aligned)
+  const bool vec = n % 8 == 0 && (uintptr_t)a % 16 == 0 && (uintptr_t)b % 16 == 0 &&
+                   (uintptr_t)out % 16 == 0 && (uintptr_t)ws % 16 == 0;
+  if (vec)
+    hipLaunchKernelGGL(k_kara_diff<true>, dim3((unsigned)batch, 2), dim3(T), 0, s, ws, ws_stride,
+                       sgn, a, b, (int)n, h);
+  else
+    hipLaunchKernelGGL(k_kara_diff<false>, dim3((unsigned)batch, 2), dim3(T), 0, s, ws, ws_stride,
+                       sgn, a, b, (int)n, h);
   BI_LAUNCH_CHECK();
   // p0 = a0 b0, p2 = a1 b1, pm = |a0 - a1| |b1 - b0|
   KaraJobs J;
@@ -241,8 +322,12 @@ int launch_mul_kara(uint32_t* out, const uint32_t* a, const uint32_t* b, int64_t
 #undef BI_KARA_LAUNCH
   BI_LAUNCH_CHECK();
   // the sum
-  hipLaunchKernelGGL(k_kara_combine, dim3((unsigned)batch, nch), dim3(1024), 0, s, out, ws,
-                     ws_stride, sgn, summ, (int)n, h);
+  if (vec)
+    hipLaunchKernelGGL(k_kara_combine<true>, dim3((unsigned)batch, nch), dim3(1024), 0, s, out, ws,
+                       ws_stride, sgn, summ, (int)n, h);
+  else
+    hipLaunchKernelGGL(k_kara_combine<false>, dim3((unsigned)batch, nch), dim3(1024), 0, s, out,
+                       ws, ws_stride, sgn, summ, (int)n, h);
   BI_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_kara_carry, dim3((unsigned)batch), dim3(64), 0, s, out, summ, (int)n);
   BI_LAUNCH_CHECK();

@@ -247,7 +247,7 @@ def test_offset_digit_extremes(bi, orc, pat):
 
 # ---- one Karatsuba level over the MFMA-split multiply ----------------------------------
 
-@pytest.mark.parametrize("n", [2, 3, 64, 65, 127, 1000, 1001, 4096, 16384, 18432])
+@pytest.mark.parametrize("n", [2, 3, 8, 12, 64, 65, 127, 1000, 1001, 1004, 4096, 8200, 16384, 18432])
 def test_karatsuba(bi, orc, n):
     g = np.random.default_rng(n + 77)
     a = rand_limbs(g, 6, n)
