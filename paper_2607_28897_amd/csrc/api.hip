@@ -90,17 +90,17 @@ static MfmaCfg uniform_mfma_cfg(int na, int nb, int64_t batch, bool low) {
   return c;
 }
 
+// CU count of the device current at the first call (one initialisation,
+// thread-safe; every device the library drives is the same part)
 int num_cus() {
-  static int n = 0;
-  if (n == 0) {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return 256;
-    int cu = 0;
-    if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+  static const int n = [] {
+    int dev = 0, cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         cu <= 0)
       cu = 256;
-    n = cu;
-  }
+    return cu;
+  }();
   return n;
 }
 
