@@ -121,6 +121,140 @@ __host__ __device__ inline size_t plain_lds_bytes(int na, int nb) {
   return (size_t)(ma + mb) * 8 + 64;
 }
 
+// Column sums of the Q outputs of the block starting at digit k0 over the
+// index range i in [lo, hi] of A (every output of the block has all those
+// terms): one loop whose inner loop of count Q reuses a sliding window of Q
+// digits of B held in registers.
+template <int Q>
+__device__ __forceinline__ void plain_common(AccCol (&col)[Q], const uint64_t* A, const uint64_t* Bd,
+                                             int k0, int lo, int hi, int mb) {
+  // window w[q] = B[k0 - i + q], walking i downwards from hi
+  uint64_t w[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) w[q] = Bd[k0 - hi + q];
+  int i = hi;
+  // rounds of Q steps.  Step j of a round (from i) has the window
+  // B[k0 - i + j + q] = w[q + j], or nx[q + j - Q] past the ring's end,
+  // so the ring turns at compile time and the round's digits of A and
+  // of B are read at its start.  A round reads B up to index
+  // k0 - i + 2Q - 1 <= k0 - lo + Q <= mb (lo is at least the block's common
+  // lower bound k0 + Q - mb): at most one digit past B, the first of the
+  // scratch area that follows it in LDS (always allocated); that value is
+  // never used.  Unclamped, the Q reads share one address.
+  static_assert(Q % 2 == 0, "columns go in pairs");
+  // one round from i with window `win`; the round's new digits go to `nw`
+  auto round = [&](int i0, const uint64_t (&win)[Q], uint64_t (&nw)[Q]) {
+    uint64_t x[Q];
+#pragma unroll
+    for (int j = 0; j < Q; ++j) x[j] = A[i0 - j];
+#pragma unroll
+    for (int j = 0; j < Q; ++j) nw[j] = Bd[k0 - i0 + Q + j];
+#pragma unroll
+    for (int j = 0; j < Q; ++j)
+#pragma unroll
+      for (int q = 0; q < Q; q += 2)
+        mac64x2(col[q], col[q + 1], x[j], q + j < Q ? win[q + j] : nw[q + j - Q],
+                q + 1 + j < Q ? win[q + 1 + j] : nw[q + 1 + j - Q]);
+  };
+  // two rounds per pass, the rings swapping roles (no register moves)
+  uint64_t v[Q];
+  for (; i - (2 * Q - 1) >= lo; i -= 2 * Q) {
+    round(i, w, v);
+    round(i - Q, v, w);
+  }
+  if (i - (Q - 1) >= lo) {
+    round(i, w, v);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) w[q] = v[q];
+    i -= Q;
+  }
+  // the last steps one at a time
+  for (; i >= lo; --i) {
+    const uint64_t x = A[i];
+    // the window's next digit, read before it is needed (clamped: the
+    // value read after the last step is not used)
+    const uint64_t nxt = Bd[min(k0 - i + Q, mb - 1)];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) mac64(col[q], x, w[q]);
+#pragma unroll
+    for (int q = 0; q < Q - 1; ++q) w[q] = w[q + 1];
+    w[Q - 1] = nxt;
+  }
+}
+
+// The terms of the block's outputs outside the common range [I_lo, I_hi]
+// (the two triangles), or all of them when nothing is common.
+template <int Q>
+__device__ __forceinline__ void plain_triangles(AccCol (&col)[Q], const uint64_t* A, const uint64_t* Bd,
+                                                int k0, int ma, int mb, int I_lo, int I_hi, bool common) {
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int k = k0 + q;
+    const int lo = max(0, k - mb + 1), hi = min(k, ma - 1);
+    if (!common) {
+      for (int i = lo; i <= hi; ++i) mac64(col[q], A[i], Bd[k - i]);
+    } else {
+      for (int i = lo; i < I_lo; ++i) mac64(col[q], A[i], Bd[k - i]);
+      for (int i = I_hi + 1; i <= hi; ++i) mac64(col[q], A[i], Bd[k - i]);
+    }
+  }
+}
+
+// combineQ: the block's Q triples -> Q output digits (stored) + 2 spill digits
+template <int Q>
+__device__ __forceinline__ void plain_block_out(const Acc3 (&acc)[Q], uint32_t* out, int nout, int k0,
+                                                uint64_t& sp0, uint64_t& sp1) {
+  uint64_t tl = 0, th = 0;
+#pragma unroll
+  for (int j = 0; j < Q + 2; ++j) {
+    if (j < Q) add_into(tl, th, acc[j].lo);
+    if (j >= 1 && j <= Q) add_into(tl, th, acc[j - 1].hi);
+    if (j >= 2) add_into(tl, th, acc[j - 2].cc);
+    const uint64_t d = tl;
+    tl = th; th = 0;
+    if (j < Q) {
+      const int l = 2 * (k0 + j);
+      if (l < nout) out[l] = (uint32_t)d;
+      if (l + 1 < nout) out[l + 1] = (uint32_t)(d >> 32);
+    } else if (j == Q) {
+      sp0 = d;
+    } else {
+      sp1 = d;
+    }
+  }
+}
+
+// out += the spills: block blk's two spill digits sit at digit (blk+1)Q + e;
+// one work-group carry scan (the Lsh + Hsh addition of bmulReg)
+template <int Q>
+__device__ __forceinline__ void plain_add_spills(uint32_t* out, int nout, const uint64_t* Sp,
+                                                 uint32_t* scratch) {
+  auto X = [&](int j) -> uint32_t { return out[j]; };
+  auto Y = [&](int j) -> uint32_t {
+    const int pd = j >> 1;
+    if (pd < Q) return 0u;
+    const int e = pd % Q;
+    if (e >= 2) return 0u;
+    const uint64_t d = Sp[2 * (pd / Q - 1) + e];
+    return (j & 1) ? (uint32_t)(d >> 32) : (uint32_t)d;
+  };
+  wg_addsub<8, false, decltype(X), decltype(Y), true>(out, nout, X, Y, 0u, scratch);
+}
+
+// stage the operands as u64 digits (two u32 limbs each, odd count padded)
+__device__ __forceinline__ void plain_stage(uint64_t* A, uint64_t* Bd, const uint32_t* __restrict__ a,
+                                            int na, const uint32_t* __restrict__ b, int nb) {
+  const int ma = (na + 1) / 2, mb = (nb + 1) / 2;
+  for (int i = threadIdx.x; i < ma; i += blockDim.x) {
+    const uint64_t lo = a[2 * i], hi = (2 * i + 1 < na) ? a[2 * i + 1] : 0u;
+    A[i] = lo | (hi << 32);
+  }
+  for (int i = threadIdx.x; i < mb; i += blockDim.x) {
+    const uint64_t lo = b[2 * i], hi = (2 * i + 1 < nb) ? b[2 * i + 1] : 0u;
+    Bd[i] = lo | (hi << 32);
+  }
+}
+
 // out[0 .. na+nb) = a[0..na) * b[0..nb); one work-group, R blocks of Q
 // output digits per thread (R*blockDim*Q >= ma+mb required).
 template <int Q, int R>
@@ -133,21 +267,12 @@ __device__ __forceinline__ void wg_mul_plain(uint32_t* out, const uint32_t* __re
   uint32_t* scratch = reinterpret_cast<uint32_t*>(sm + ma + mb);
   const int T = blockDim.x, t = threadIdx.x;
 
-  // stage the operands as u64 digits (two u32 limbs each, odd count padded)
-  for (int i = t; i < ma; i += T) {
-    const uint64_t lo = a[2 * i], hi = (2 * i + 1 < na) ? a[2 * i + 1] : 0u;
-    A[i] = lo | (hi << 32);
-  }
-  for (int i = t; i < mb; i += T) {
-    const uint64_t lo = b[2 * i], hi = (2 * i + 1 < nb) ? b[2 * i + 1] : 0u;
-    Bd[i] = lo | (hi << 32);
-  }
+  plain_stage(A, Bd, a, na, b, nb);
   __syncthreads();
 
   const int K = ma + mb;
   const int NBLK = (K + Q - 1) / Q;
   uint64_t sp0[R], sp1[R];
-
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int blk = (r & 1) ? (r + 1) * T - 1 - t : r * T + t;
@@ -157,99 +282,16 @@ __device__ __forceinline__ void wg_mul_plain(uint32_t* out, const uint32_t* __re
     AccCol col[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) acc_zero(col[q]);
-
     // index range common to all Q outputs
     const int I_lo = max(0, k0 + Q - mb);
     const int I_hi = min(k0, ma - 1);
     const bool common = I_lo <= I_hi;
-    if (common) {
-      // window w[q] = B[k0 - i + q], walking i downwards from I_hi
-      uint64_t w[Q];
-#pragma unroll
-      for (int q = 0; q < Q; ++q) w[q] = Bd[k0 - I_hi + q];
-      int i = I_hi;
-      // rounds of Q steps.  Step j of a round (from i) has the window
-      // B[k0 - i + j + q] = w[q + j], or nx[q + j - Q] past the ring's end,
-      // so the ring turns at compile time and the round's digits of A and
-      // of B are read at its start.  A round reads B up to index
-      // k0 - i + 2Q - 1 <= k0 - I_lo + Q <= mb: at most one digit past B,
-      // the first of the scratch area that follows it in LDS (always
-      // allocated); that value is never used.  Unclamped, the Q reads share
-      // one address.
-      static_assert(Q % 2 == 0, "columns go in pairs");
-      // one round from i with window `win`; the round's new digits go to `nw`
-      auto round = [&](int i0, const uint64_t (&win)[Q], uint64_t (&nw)[Q]) {
-        uint64_t x[Q];
-#pragma unroll
-        for (int j = 0; j < Q; ++j) x[j] = A[i0 - j];
-#pragma unroll
-        for (int j = 0; j < Q; ++j) nw[j] = Bd[k0 - i0 + Q + j];
-#pragma unroll
-        for (int j = 0; j < Q; ++j)
-#pragma unroll
-          for (int q = 0; q < Q; q += 2)
-            mac64x2(col[q], col[q + 1], x[j], q + j < Q ? win[q + j] : nw[q + j - Q],
-                    q + 1 + j < Q ? win[q + 1 + j] : nw[q + 1 + j - Q]);
-      };
-      // two rounds per pass, the rings swapping roles (no register moves)
-      uint64_t v[Q];
-      for (; i - (2 * Q - 1) >= I_lo; i -= 2 * Q) {
-        round(i, w, v);
-        round(i - Q, v, w);
-      }
-      if (i - (Q - 1) >= I_lo) {
-        round(i, w, v);
-#pragma unroll
-        for (int q = 0; q < Q; ++q) w[q] = v[q];
-        i -= Q;
-      }
-      // the last steps one at a time
-      for (; i >= I_lo; --i) {
-        const uint64_t x = A[i];
-        // the window's next digit, read before it is needed (clamped: the
-        // value read after the last step is not used)
-        const uint64_t nxt = Bd[min(k0 - i + Q, mb - 1)];
-#pragma unroll
-        for (int q = 0; q < Q; ++q) mac64(col[q], x, w[q]);
-#pragma unroll
-        for (int q = 0; q < Q - 1; ++q) w[q] = w[q + 1];
-        w[Q - 1] = nxt;
-      }
-    }
-    // the triangles (or the whole range when nothing is common)
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const int k = k0 + q;
-      const int lo = max(0, k - mb + 1), hi = min(k, ma - 1);
-      if (!common) {
-        for (int i = lo; i <= hi; ++i) mac64(col[q], A[i], Bd[k - i]);
-      } else {
-        for (int i = lo; i < I_lo; ++i) mac64(col[q], A[i], Bd[k - i]);
-        for (int i = I_hi + 1; i <= hi; ++i) mac64(col[q], A[i], Bd[k - i]);
-      }
-    }
-    // combineQ: Q triples -> Q digits + 2 spill digits
+    if (common) plain_common<Q>(col, A, Bd, k0, I_lo, I_hi, mb);
+    plain_triangles<Q>(col, A, Bd, k0, ma, mb, I_lo, I_hi, common);
     Acc3 acc[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) acc[q] = acc_fold(col[q]);
-    uint64_t tl = 0, th = 0;
-#pragma unroll
-    for (int j = 0; j < Q + 2; ++j) {
-      if (j < Q) add_into(tl, th, acc[j].lo);
-      if (j >= 1 && j <= Q) add_into(tl, th, acc[j - 1].hi);
-      if (j >= 2) add_into(tl, th, acc[j - 2].cc);
-      const uint64_t d = tl;
-      tl = th; th = 0;
-      if (j < Q) {
-        const int l = 2 * (k0 + j);
-        if (l < nout) out[l] = (uint32_t)d;
-        if (l + 1 < nout) out[l + 1] = (uint32_t)(d >> 32);
-      } else if (j == Q) {
-        sp0[r] = d;
-      } else {
-        sp1[r] = d;
-      }
-    }
+    plain_block_out<Q>(acc, out, nout, k0, sp0[r], sp1[r]);
   }
   __syncthreads();  // operands dead: reuse their LDS for the spills
 
@@ -260,18 +302,95 @@ __device__ __forceinline__ void wg_mul_plain(uint32_t* out, const uint32_t* __re
     if (blk < NBLK) { Sp[2 * blk] = sp0[r]; Sp[2 * blk + 1] = sp1[r]; }
   }
   __syncthreads();
+  plain_add_spills<Q>(out, nout, Sp, scratch);
+}
 
-  // out += spills: block blk's two spill digits sit at digit (blk+1)Q + e
-  auto X = [&](int j) -> uint32_t { return out[j]; };
-  auto Y = [&](int j) -> uint32_t {
-    const int pd = j >> 1;
-    if (pd < Q) return 0u;
-    const int e = pd % Q;
-    if (e >= 2) return 0u;
-    const uint64_t d = Sp[2 * (pd / Q - 1) + e];
-    return (j & 1) ? (uint32_t)(d >> 32) : (uint32_t)d;
-  };
-  wg_addsub<8, false, decltype(X), decltype(Y), true>(out, nout, X, Y, 0u, scratch);
+// LDS bytes of wg_mul_plain_split: wg_mul_plain's, then the partial column
+// sums of parts 1..S-1 (threads per part Tp, Q triples each)
+__host__ __device__ inline size_t plain_split_lds_bytes(int na, int nb, int S, int Tp, int Q) {
+  return plain_lds_bytes(na, nb) + (size_t)(S - 1) * Tp * Q * sizeof(Acc3);
+}
+
+// wg_mul_plain with every block's common index range cut into S parts, for
+// batches too small to give every SIMD waves of its own: thread
+// (s, t) = (threadIdx.x / Tp, threadIdx.x % Tp), Tp = blockDim.x / S, sums
+// part s of the blocks thread t has in wg_mul_plain (part 0 also takes the
+// triangles), and part 0 adds the other parts' (lo, hi, carry) triples from
+// LDS before combineQ.  The digits computed are those of wg_mul_plain.
+template <int Q, int R, int S>
+__device__ __forceinline__ void wg_mul_plain_split(uint32_t* out, const uint32_t* __restrict__ a, int na,
+                                                   const uint32_t* __restrict__ b, int nb, uint64_t* sm) {
+  static_assert(S >= 2, "one part is wg_mul_plain");
+  const int ma = (na + 1) / 2, mb = (nb + 1) / 2;
+  const int nout = na + nb;
+  uint64_t* A = sm;
+  uint64_t* Bd = sm + ma;
+  uint32_t* scratch = reinterpret_cast<uint32_t*>(sm + ma + mb);
+  Acc3* part = reinterpret_cast<Acc3*>(sm + ma + mb + 8);  // past the 64-byte scratch
+  const int Tp = blockDim.x / S, t = threadIdx.x % Tp, s = threadIdx.x / Tp;
+
+  plain_stage(A, Bd, a, na, b, nb);
+  __syncthreads();
+
+  const int K = ma + mb;
+  const int NBLK = (K + Q - 1) / Q;
+  uint64_t sp0[R], sp1[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int blk = (r & 1) ? (r + 1) * Tp - 1 - t : r * Tp + t;
+    sp0[r] = 0; sp1[r] = 0;
+    const bool live = blk < NBLK;
+    const int k0 = blk * Q;
+    AccCol col[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) acc_zero(col[q]);
+    if (live) {
+      const int I_lo = max(0, k0 + Q - mb);
+      const int I_hi = min(k0, ma - 1);
+      const bool common = I_lo <= I_hi;
+      if (common) {
+        // part s: indices [hi_s - len + 1, hi_s] of the common range, from the top
+        const int len = (I_hi - I_lo + S) / S;
+        const int hi_s = I_hi - s * len;
+        const int lo_s = max(I_lo, hi_s - len + 1);
+        if (lo_s <= hi_s) plain_common<Q>(col, A, Bd, k0, lo_s, hi_s, mb);
+      }
+      if (s == 0) plain_triangles<Q>(col, A, Bd, k0, ma, mb, I_lo, I_hi, common);
+    }
+    Acc3 acc[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) acc[q] = acc_fold(col[q]);
+    if (s > 0) {
+#pragma unroll
+      for (int q = 0; q < Q; ++q) part[((s - 1) * Tp + t) * Q + q] = acc[q];
+    }
+    __syncthreads();
+    if (s == 0 && live) {
+      for (int p = 1; p < S; ++p) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+          const Acc3 o = part[((p - 1) * Tp + t) * Q + q];
+          unsigned long long c1, c2;
+          acc[q].lo = __builtin_addcll(acc[q].lo, o.lo, 0ull, &c1);
+          acc[q].hi = __builtin_addcll(acc[q].hi, o.hi, c1, &c2);
+          acc[q].cc += o.cc + c2;
+        }
+      }
+      plain_block_out<Q>(acc, out, nout, k0, sp0[r], sp1[r]);
+    }
+    __syncthreads();  // the partials are rewritten by the next block
+  }
+
+  uint64_t* Sp = sm;  // operands dead: their LDS takes the spills
+  if (s == 0) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int blk = (r & 1) ? (r + 1) * Tp - 1 - t : r * Tp + t;
+      if (blk < NBLK) { Sp[2 * blk] = sp0[r]; Sp[2 * blk + 1] = sp1[r]; }
+    }
+  }
+  __syncthreads();
+  plain_add_spills<Q>(out, nout, Sp, scratch);
 }
 
 }  // namespace bi

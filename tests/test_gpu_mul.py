@@ -331,3 +331,23 @@ def test_batch_decides_waves(bi, orc, n):
             assert np.array_equal(big[:B - 1], small), op
             for i in (0, 1, B // 2, B - 2, B - 1):
                 assert np.array_equal(big[i], ref(a[i], b[i])), (op, i)
+
+
+@pytest.mark.parametrize("na,nb", [(1024, 1024), (700, 1500), (1500, 700), (33, 2000), (2048, 2048)])
+def test_plain_split_parts_match_whole_blocks(bi, orc, na, nb):
+    """Small batches run the plain product with every block's common range
+    cut into parts summed by different waves; the same pairs inside a batch
+    large enough to fill the chip run whole blocks.  Both equal the oracle."""
+    g = np.random.default_rng(na * 3 + nb)
+    a = rand_limbs(g, 4, na)
+    b = rand_limbs(g, 4, nb)
+    a[1] = 0xFFFFFFFF                      # every column at its largest
+    b[1] = 0xFFFFFFFF
+    b[2] = 0
+    small = host(bi.mul(dev(a), dev(b), bi.MUL_PLAIN))
+    big_a = np.concatenate([a, rand_limbs(g, 2044, na)])
+    big_b = np.concatenate([b, rand_limbs(g, 2044, nb)])
+    big = host(bi.mul(dev(big_a), dev(big_b), bi.MUL_PLAIN))[:4]
+    assert np.array_equal(small, big)
+    for i in range(4):
+        assert np.array_equal(small[i], orc.mul1(a[i], b[i])), i
