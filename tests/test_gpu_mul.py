@@ -351,3 +351,38 @@ def test_plain_split_parts_match_whole_blocks(bi, orc, na, nb):
     assert np.array_equal(small, big)
     for i in range(4):
         assert np.array_equal(small[i], orc.mul1(a[i], b[i])), i
+
+
+def test_unaligned_buffers_take_the_scalar_paths(bi, orc):
+    """Operands and outputs 4 bytes past a 16-byte boundary: add, sub and the
+    Karatsuba passes fall back from 16-byte accesses to limb-by-limb ones and
+    give the same bytes."""
+    import ctypes
+    import torch
+    L = bi.lib()
+    s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    g = np.random.default_rng(4242)
+    n, B = 1024, 3
+    a = rand_limbs(g, B, n)
+    b = rand_limbs(g, B, n)
+    a[1] = 0xFFFFFFFF
+    b[1] = 0xFFFFFFFF
+    ta = torch.zeros(B * n + 1, dtype=torch.int32, device="cuda")
+    tb = torch.zeros(B * n + 1, dtype=torch.int32, device="cuda")
+    ta[1:] = torch.from_numpy(a.reshape(-1).view(np.int32)).cuda()
+    tb[1:] = torch.from_numpy(b.reshape(-1).view(np.int32)).cuda()
+    out = torch.zeros(B * 2 * n + 1, dtype=torch.int32, device="cuda")
+    cy = torch.zeros(B, dtype=torch.int32, device="cuda")
+    P = lambda t, off=0: ctypes.c_void_p(t.data_ptr() + 4 * off)
+    assert L.bigint_mul(P(out, 1), P(ta, 1), n, P(tb, 1), n, B, bi.MUL_KARATSUBA, s) == 0
+    got = out[1:].cpu().numpy().view(np.uint32).reshape(B, 2 * n)
+    for i in range(B):
+        assert np.array_equal(got[i], orc.mul1(a[i], b[i])), i
+    assert L.bigint_add(P(out, 1), P(cy), P(ta, 1), P(tb, 1), n, B, s) == 0
+    got = out[1:1 + B * n].cpu().numpy().view(np.uint32).reshape(B, n)
+    want, wc = orc.add(a, b)
+    assert np.array_equal(got, want) and np.array_equal(cy.cpu().numpy().view(np.uint32), wc)
+    assert L.bigint_sub(P(out, 1), P(cy), P(ta, 1), P(tb, 1), n, B, s) == 0
+    got = out[1:1 + B * n].cpu().numpy().view(np.uint32).reshape(B, n)
+    want, wc = orc.sub(a, b)
+    assert np.array_equal(got, want) and np.array_equal(cy.cpu().numpy().view(np.uint32), wc)
