@@ -83,9 +83,21 @@ static bool wave_batch(int64_t na, int64_t nb, int64_t batch, int per) {
 
 static MfmaCfg uniform_mfma_cfg(int na, int nb, int64_t batch, bool low) {
   MfmaCfg c = current_mfma_cfg(na, nb);
+  bool one = false;
   if (c.waves == 1 && t_cfg_waves == 0 && !wave_batch(na, nb, batch, low ? kWaveLow : kWaveFull)) {
     c.waves = 4;
+    one = true;
     if (low && t_cfg_P == 0) c.P = 4;
+  }
+  // Full products, fewer instances than CUs: every work-group has a CU to
+  // itself, and 8 waves (two per SIMD) hide more MFMA and LDS latency than 4.
+  // Measured: 64 x 1024 limbs 26.3 -> 22.6 us (4 strips per band), 64 x 2048
+  // limbs 39.7 -> 34.4 us (call times through the Python binding).
+  if (!low && c.waves == 4 && t_cfg_waves == 0 && batch < num_cus()) {
+    MfmaCfg w = c;
+    w.waves = 8;
+    if (one && t_cfg_P == 0) w.P = 4;
+    if (mfma_lds(na, nb, w) <= 163840) c = w;
   }
   return c;
 }
