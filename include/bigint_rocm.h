@@ -292,10 +292,10 @@ int bigint_set_mfma_config(int strips_per_band, int waves, int digit_bits);
  * it only for batches of at least na*nb/64 instances, bigint_mullo for at
  * least n*n/256, bigint_poly for at least n*n/16, and 4 waves per instance
  * below that (one
- * wave per instance leaves most CUs idle on small batches).  bigint_mul on a
- * batch of fewer instances than the device has CUs runs 8 waves where this
- * reports 4 (and 4 strips per band where it reports one wave), if the LDS
- * allows.  A wave count set with bigint_set_mfma_config is used at every
+ * wave per instance leaves most CUs idle on small batches).  bigint_mul and
+ * bigint_mullo on a batch of fewer instances than the device has CUs run 8
+ * waves where this reports 4 (and 4 strips per band where it reports one
+ * wave, and always for bigint_mullo), if the LDS allows.  A wave count set with bigint_set_mfma_config is used at every
  * batch.  BIGINT_EUNSUPPORTED if the MFMA multiply does not take that
  * size with it; BIGINT_EINVAL for null pointers or sizes < 1. */
 int bigint_mfma_config(int64_t na, int64_t nb, int* strips_per_band, int* waves,

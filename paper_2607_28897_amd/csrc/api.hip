@@ -89,14 +89,16 @@ static MfmaCfg uniform_mfma_cfg(int na, int nb, int64_t batch, bool low) {
     one = true;
     if (low && t_cfg_P == 0) c.P = 4;
   }
-  // Full products, fewer instances than CUs: every work-group has a CU to
-  // itself, and 8 waves (two per SIMD) hide more MFMA and LDS latency than 4.
-  // Measured: 64 x 1024 limbs 26.3 -> 22.6 us (4 strips per band), 64 x 2048
-  // limbs 39.7 -> 34.4 us (call times through the Python binding).
-  if (!low && c.waves == 4 && t_cfg_waves == 0 && batch < num_cus()) {
+  // Fewer instances than CUs: every work-group has a CU to itself, and 8
+  // waves (two per SIMD) hide more MFMA and LDS latency than 4.  Measured
+  // (call times through the Python binding): full products of 64 x 1024 limbs
+  // 26.3 -> 22.6 us (4 strips per band), 64 x 2048 limbs 39.7 -> 34.4 us (the
+  // table's 8 strips); products mod B^n of 64 x 2048 limbs 31.2 -> 27.0 us
+  // (4 strips per band; 8 strips gain nothing there).
+  if (c.waves == 4 && t_cfg_waves == 0 && batch < num_cus()) {
     MfmaCfg w = c;
     w.waves = 8;
-    if (one && t_cfg_P == 0) w.P = 4;
+    if ((one || low) && t_cfg_P == 0) w.P = 4;
     if (mfma_lds(na, nb, w) <= 163840) c = w;
   }
   return c;
