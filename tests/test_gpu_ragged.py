@@ -142,3 +142,25 @@ def test_ragged_single_instance(bi, orc, n):
     for flags in (0, 2, 1):
         res, oo = _run(bi, la, lb, a, a_off, b, b_off, flags)
         assert np.array_equal(res, orc.mul1(a, b)), flags
+
+
+@pytest.mark.parametrize("case", ["equal", "unequal"])
+def test_plain_ragged_sizes(bi, orc, case):
+    """The plain ragged multiply (one 1024-thread work-group per instance in
+    queue order) on equal operands spread over 1..16384 limbs, and on unequal
+    operands whose sizes go up and down along the queue."""
+    g = np.random.default_rng(91 if case == "equal" else 92)
+    if case == "equal":
+        la = np.maximum(np.exp(g.uniform(0.0, np.log(16384), 60)).astype(np.int64), 1)
+        lb = la.copy()
+    else:
+        la = np.array([100, 1100, 9000, 3, 2048, 700, 16000, 50] * 3, np.int64)
+        lb = np.array([10000, 1100, 200, 4000, 2048, 700, 16384, 5000] * 3, np.int64)
+    a, a_off = _ragged(g, la)
+    b, b_off = _ragged(g, lb)
+    a[a_off[1]:a_off[2]] = 0xFFFFFFFF
+    b[b_off[1]:b_off[2]] = 0xFFFFFFFF
+    res, oo = _run(bi, la, lb, a, a_off, b, b_off, 1)
+    for i in range(len(la)):
+        want = orc.mul1(a[a_off[i]:a_off[i + 1]], b[b_off[i]:b_off[i + 1]])
+        assert np.array_equal(res[oo[i]:oo[i + 1]], want), i
