@@ -106,9 +106,24 @@ def cpu_baseline(a_np, b_np, gpu_out, target_s):
         "value": round(len(idx) / wall, 3),
         "unit": "muls/s",
         "cores": cores,
+        "cpu_model": cpu_model(),
         "kind": "oracle",
-        "sample": f"{len(idx)} of the {a_np.shape[0]} pairs (2^19 x 2^19 bits), one pair per thread",
+        "sample": f"{len(idx)} of the {a_np.shape[0]} pairs (2^19 x 2^19 bits), one pair per thread, "
+                  f"{cores} threads",
     }, exact, n
+
+
+def cpu_model():
+    """The host CPU's model name (first entry of /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
 
 
 def main():
@@ -147,56 +162,43 @@ def main():
     b = torch.from_numpy(b_np.view(np.int32)).cuda()
     batch = a.shape[0]
     out_m = torch.empty((batch, 2 * n), dtype=torch.int32, device="cuda")
-    out_p = torch.empty_like(out_m)
     L = bi.lib()
     import ctypes
     stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
     pa, pb = ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr())
-    pm, pp = ctypes.c_void_p(out_m.data_ptr()), ctypes.c_void_p(out_p.data_ptr())
 
-    def run_mfma():
-        rc = L.bigint_mul(pm, pa, n, pb, n, batch, bi.MUL_MFMA, stream)
-        if rc:
-            raise bi.BigIntError(rc, "bigint_mul")
+    def mul_call(out, algo):
+        po = ctypes.c_void_p(out.data_ptr())
 
-    def run_plain():
-        rc = L.bigint_mul(pp, pa, n, pb, n, batch, bi.MUL_PLAIN, stream)
-        if rc:
-            raise bi.BigIntError(rc, "bigint_mul")
+        def run():
+            rc = L.bigint_mul(po, pa, n, pb, n, batch, algo, stream)
+            if rc:
+                raise bi.BigIntError(rc, "bigint_mul")
+        return run
 
     torch.cuda.synchronize()
-    per = []
-    total_ms, kernel_ms = time_launches(run_mfma, args.steps, args.warmup, torch, per)
-    print(f"# mfma: {total_ms / args.steps:.4f} ms/step", file=sys.stderr, flush=True)
-    p_steps = max(3, args.steps // 10)
-    p_total, p_kernel = time_launches(run_plain, p_steps, 1, torch)
+    # The plain u64 kernel first (it also brings the clocks up from idle),
+    # then the MFMA-split headline, each after its own warm-up launches.
+    out_p = torch.empty_like(out_m)
+    p_steps = max(10, args.steps // 2)
+    p_total, _ = time_launches(mul_call(out_p, bi.MUL_PLAIN), p_steps, max(1, args.warmup // 5), torch)
     print(f"# plain: {p_total / p_steps:.4f} ms/step", file=sys.stderr, flush=True)
+    per = []
+    total_ms, kernel_ms = time_launches(mul_call(out_m, bi.MUL_MFMA), args.steps, args.warmup, torch, per)
+    print(f"# mfma: {total_ms / args.steps:.4f} ms/step", file=sys.stderr, flush=True)
     same = bool(torch.equal(out_m, out_p))
-    # one Karatsuba level over the same MFMA-split multiply (three launches), beside it
-    out_k = torch.empty_like(out_m)
-    pk = ctypes.c_void_p(out_k.data_ptr())
-
-    def run_kara():
-        rc = L.bigint_mul(pk, pa, n, pb, n, batch, bi.MUL_KARATSUBA, stream)
-        if rc:
-            raise bi.BigIntError(rc, "bigint_mul")
-
-    k_steps = max(3, args.steps // 2)
-    k_total, _ = time_launches(run_kara, k_steps, 2, torch)
-    print(f"# karatsuba: {k_total / k_steps:.4f} ms/step", file=sys.stderr, flush=True)
-    same_k = bool(torch.equal(out_m, out_k))
+    del out_p
 
     ms = total_ms / args.steps
     value = batch / (ms * 1e-3)
-    # algorithmic work of one 2^19 x 2^19-bit product: the 7-bit digit
-    # products Na * Nb of the MFMA-split form (2 int8 ops each); the kernel
-    # executes fewer when the tuned digit width is 8 (Na = 4 n)
-    Na = (32 * n + 6) // 7
-    ops = 2.0 * batch * Na * Na
-    achieved = ops / (kernel_ms * 1e-3) / 1e12      # TOP/s
     P, waves, dbits = bi.mfma_config(n, n)
-    Nx = Na if dbits == 7 else 4 * n
-    executed = 2.0 * batch * Nx * Nx / (kernel_ms * 1e-3) / 1e12
+    # executed work of one launch: the digit products of the tuned digit width
+    # (offset 8-bit digits: Na = 4 n), 2 int8 ops each
+    Nx = (32 * n + 6) // 7 if dbits == 7 else 4 * n
+    ops = 2.0 * batch * Nx * Nx
+    achieved = ops / (kernel_ms * 1e-3) / 1e12      # TOP/s
+    N7 = (32 * n + 6) // 7
+    seven = 2.0 * batch * N7 * N7 / (kernel_ms * 1e-3) / 1e12
     traffic = None
     if os.path.exists(args.traffic_json):
         with open(args.traffic_json) as f:
@@ -237,9 +239,10 @@ def main():
             "kernel_ms": round(kernel_ms, 4),
             "kernel_ms_median": round(float(np.median(per)), 4),
             "kernel_ms_min": round(float(np.min(per)), 4),
-            "algorithmic_unit": "2 x 74,899^2 int8 ops (7-bit digit products) per 2^19-bit product",
-            "executed_TOPs": round(executed, 1),
-            "executed_frac": round(executed / INT8_PEAK_TOPS, 4),
+            "algorithmic_unit": f"2 x {Nx:,}^2 int8 ops ({dbits}-bit digit products) per 2^19-bit product, "
+                                f"{ops:.4g} per launch",
+            "seven_bit_equivalent_TOPs": round(seven, 1),
+            "seven_bit_equivalent_unit": f"2 x {N7:,}^2 int8 ops (7-bit digit products) per 2^19-bit product",
         },
         "plain": {
             "value": round(batch / (p_total / p_steps * 1e-3), 1),
@@ -256,20 +259,132 @@ def main():
             },
         },
         "mfma_equals_plain": same,
-        "karatsuba": {
-            "value": round(batch / (k_total / k_steps * 1e-3), 1),
-            "unit": "muls/s",
-            "ms_per_step": round(k_total / k_steps, 4),
-            "steps": k_steps,
-            "what": "one Karatsuba level (three 2^18-bit products per pair) over the same MFMA-split multiply",
-            "equals_mfma": same_k,
-        },
     }
+    line["mfma_7bit"] = seven_bit_leg(torch, bi, mul_call, out_m, batch, n, args)
+    line["karatsuba"] = karatsuba_leg(torch, bi, mul_call, out_m, batch, args)
+    line["ragged_4096"] = ragged_leg(torch, bi, inputs, args)
+    line["divmod_512"] = divmod_leg(torch, bi, inputs, args)
     if not args.no_cpu:
         cpu, exact, _ = cpu_baseline(a_np, b_np, out_m.cpu().numpy().view(np.uint32), args.cpu_seconds)
         line["cpu_baseline"] = cpu
         line["bit_exact_sample"] = exact
     print(json.dumps(line), flush=True)
+
+
+def mfma_roofline(int8_ops, ms, unit):
+    a = int8_ops / (ms * 1e-3) / 1e12
+    return {"bound": "mfma", "achieved": round(a, 1), "peak": INT8_PEAK_TOPS, "unit": "TOP/s",
+            "frac": round(a / INT8_PEAK_TOPS, 4), "traffic": None, "algorithmic_unit": unit}
+
+
+def seven_bit_leg(torch, bi, mul_call, ref, batch, n, args):
+    """The 2^19-bit batch with the digit width forced to 7 bits (the
+    configuration's tile as written), same inputs, same bytes."""
+    out = torch.empty_like(ref)
+    steps = max(5, args.steps // 2)
+    bi.set_mfma_config(0, 0, 7)
+    try:
+        total, kern = time_launches(mul_call(out, bi.MUL_MFMA), steps, max(2, args.warmup // 2), torch)
+    finally:
+        bi.set_mfma_config(0, 0, 0)
+    print(f"# mfma 7-bit: {total / steps:.4f} ms/step", file=sys.stderr, flush=True)
+    N7 = (32 * n + 6) // 7
+    ms = total / steps
+    return {"value": round(batch / (ms * 1e-3), 1), "unit": "muls/s", "ms_per_step": round(ms, 4),
+            "steps": steps, "digit_bits": 7,
+            "roofline": mfma_roofline(2.0 * batch * N7 * N7, kern,
+                                      f"2 x {N7:,}^2 int8 ops (7-bit digit products) per product"),
+            "equals_8bit": bool(torch.equal(out, ref))}
+
+
+def karatsuba_leg(torch, bi, mul_call, ref, batch, args):
+    """One Karatsuba level (three 2^18-bit half products per pair) over the
+    same MFMA-split multiply, same inputs."""
+    out = torch.empty_like(ref)
+    steps = max(5, args.steps // 2)
+    total, _ = time_launches(mul_call(out, bi.MUL_KARATSUBA), steps, 2, torch)
+    print(f"# karatsuba: {total / steps:.4f} ms/step", file=sys.stderr, flush=True)
+    ms = total / steps
+    return {"value": round(batch / (ms * 1e-3), 1), "unit": "muls/s", "ms_per_step": round(ms, 4),
+            "steps": steps,
+            "what": "one Karatsuba level (three 2^18-bit products per pair) over the same MFMA-split multiply",
+            "equals_mfma": bool(torch.equal(out, ref))}
+
+
+def ragged_leg(torch, bi, inputs, args):
+    """The ragged configuration: 4096 products, operand bits log-uniform in
+    [2^15, 2^19] (seed 1003), one call = the plan's segment launches replayed
+    from its hipGraph.  Roofline on the digit products the tuned digit widths
+    execute."""
+    c = inputs.ragged_mul_2e15_2e19()
+    lens = c["lens"]
+    ta = torch.from_numpy(c["a"].view(np.int32)).cuda()
+    tb = torch.from_numpy(c["b"].view(np.int32)).cuda()
+    tao, tbo = torch.from_numpy(c["a_off"]).cuda(), torch.from_numpy(c["b_off"]).cuda()
+    plan = bi.MulPlan(lens, lens)
+    out, oo = plan(ta, tao, tb, tbo)
+    steps = max(5, args.steps // 2)
+    total, _ = time_launches(lambda: plan(ta, tao, tb, tbo, out=out, out_off=oo), steps, args.warmup, torch)
+    ms = total / steps
+    print(f"# ragged 4096: {ms:.4f} ms/call", file=sys.stderr, flush=True)
+    macs = 0.0
+    for n_ in np.unique(lens):
+        dbits = bi.mfma_config(int(n_), int(n_))[2]
+        N = (32 * int(n_) + 6) // 7 if dbits == 7 else 4 * int(n_)
+        macs += float(N) * N * int((lens == n_).sum())
+    info = plan.info()
+    plan.close()
+    return {"workload": "4096 products, operand bits log-uniform in [2^15, 2^19] (seed 1003)",
+            "value": round(4096 / (ms * 1e-3), 1), "unit": "muls/s", "ms_per_call": round(ms, 4),
+            "steps": steps, "launches_per_call": info["launches_per_call"],
+            "graph_replays": info["graph_replays"],
+            "roofline": mfma_roofline(2.0 * macs, ms, f"sum over pairs of 2 x (digits)^2 int8 ops at the "
+                                                    f"tuned digit width, {2.0 * macs:.4g} per call")}
+
+
+def divmod_leg(torch, bi, inputs, args):
+    """The division configuration: 512 divisions, dividend bits log-uniform in
+    [2^16, 2^18], divisor half the limbs (seed 1004), one call = the plan's
+    launches replayed from its hipGraph.  Roofline on the int8 MACs the
+    division's MFMA products issue (counted per division by the diagnostic
+    entry point, outside the timed region); Div/Mul against one product of
+    every dividend with itself."""
+    c = inputs.ragged_div_2e16_2e18()
+    nu, nv = c["nu"], c["nv"]
+    tu = torch.from_numpy(c["u"].view(np.int32)).cuda()
+    tv = torch.from_numpy(c["v"].view(np.int32)).cuda()
+    tuo, tvo = torch.from_numpy(c["u_off"]).cuda(), torch.from_numpy(c["v_off"]).cuda()
+    plan = bi.DivPlan(nu, nv)
+    steps = max(5, args.steps // 2)
+    total, _ = time_launches(lambda: plan(tu, tuo, tv, tvo), steps, args.warmup, torch)
+    ms = total / steps
+    print(f"# divmod 512: {ms:.4f} ms/call", file=sys.stderr, flush=True)
+    mplan = bi.MulPlan(nu, nu)
+    out, oo = mplan(tu, tuo, tu, tuo)
+    mtotal, _ = time_launches(lambda: mplan(tu, tuo, tu, tuo, out=out, out_off=oo), steps, args.warmup, torch)
+    mms = mtotal / steps
+    _, _, st, cnt = plan.counters(tu, tuo, tv, tvo)
+    cnt = cnt.cpu().numpy()
+    macs = float(cnt[:, 3].sum())
+
+    def hist(col):
+        vals, counts = np.unique(cnt[:, col], return_counts=True)
+        return {str(int(v)): int(k) for v, k in zip(vals, counts)}
+
+    info = plan.info()
+    plan.close()
+    mplan.close()
+    return {"workload": "512 divisions, dividend bits log-uniform in [2^16, 2^18], divisor half the limbs "
+                        "(seed 1004)",
+            "value": round(512 / (ms * 1e-3), 1), "unit": "divs/s", "ms_per_call": round(ms, 4),
+            "steps": steps, "launches_per_call": info["launches_per_call"],
+            "graph_replays": info["graph_replays"],
+            "all_status_ok": bool((st == 0).all().item()),
+            "same_size_products_ms": round(mms, 4), "div_over_mul": round(ms / mms, 3),
+            "roofline": mfma_roofline(2.0 * macs, ms, f"2 int8 ops per digit product the division's MFMA "
+                                                    f"products compute, {2.0 * macs:.4g} per call"),
+            "newton_steps_histogram": hist(0), "fixup_corrections_histogram": hist(1),
+            "quotient_corrections_histogram": hist(2)}
 
 
 def copy_mode(torch):

@@ -196,6 +196,13 @@ int bigint_plan_workspace_size(bigint_plan_t plan, size_t* bytes);
 int bigint_plan_set_workspace(bigint_plan_t plan, void* dev, size_t bytes);
 int bigint_plan_destroy(bigint_plan_t plan);
 
+/* Diagnostic counters of a plan, written to info[0 .. n) (host int64; n <= 3
+ * are defined, further entries are set to 0): [0] kernel launches one call
+ * enqueues, [1] hipGraphs instantiated so far (one per new set of call
+ * pointers), [2] calls so far that launched an already instantiated graph.
+ * Lets a caller confirm that repeated calls replay a captured graph. */
+int bigint_plan_info(bigint_plan_t plan, int64_t* info, int n);
+
 /* Ragged multiplication: out instance i = a instance i * b instance i, with
  * out_off[i+1]-out_off[i] == (a_off[i+1]-a_off[i]) + (b_off[i+1]-b_off[i]);
  * the limb counts must equal those given to bigint_plan_create (not checked
@@ -211,7 +218,10 @@ int bigint_mul_ragged(uint32_t* out, const int64_t* out_off, const uint32_t* a,
                       void* stream);
 
 /* Ragged division: instance i divides u[u_off[i]..) by v[v_off[i]..); q
- * instance i has the dividend's limb count and r the divisor's. */
+ * instance i has the dividend's limb count and r the divisor's.  The
+ * division launches (one or more, each at most eight times the work-groups
+ * that stay resident, one workspace slot each) are captured into a hipGraph
+ * and replayed like the ragged multiply's (unless BIGINT_PLAN_NO_GRAPH). */
 int bigint_divmod_ragged(uint32_t* q, const int64_t* q_off, uint32_t* r,
                          const int64_t* r_off, int32_t* status,
                          const uint32_t* u, const int64_t* u_off,
@@ -245,14 +255,18 @@ int bigint_shinv(uint32_t* w, const uint32_t* v, int64_t nv, int64_t h,
                  int64_t batch, void* stream);
 
 /* bigint_diag_divmod_ragged: bigint_divmod_ragged (same arguments, same
- * results) that also writes, per division, three counters of the procedure
- * of Section 5.3 to counts[3*i .. 3*i+2] (device int32, 3*batch, must not
- * overlap q or r): the Newton steps (`step`) taken, the unit corrections the
- * exact fix-ups applied to the inverse at every scale, and the corrections
- * of the final quotient (at most 3; a fourth marks the division
- * BIGINT_DIV_FAILED).  Divisions that need no Newton iteration (v < B, u < v,
- * v = 0) report zeros.  Launches directly (no graph). */
-int bigint_diag_divmod_ragged(int32_t* counts, uint32_t* q, const int64_t* q_off,
+ * results) that also writes, per division, four counters of the procedure
+ * of Section 5.3 to counts[4*i .. 4*i+3] (device int64, 4*batch, must not
+ * overlap q or r): [0] the Newton steps (`step`) taken, [1] the unit
+ * corrections the exact fix-ups applied to the inverse, [2] the corrections
+ * of the final quotient (a bounded loop; hitting its bound marks the
+ * division BIGINT_DIV_FAILED), [3] the int8 multiply-accumulates of the
+ * division's MFMA products: for each product, the digit pairs (i, j) whose
+ * coefficient i + j lies in the strips it computes (products of operands of
+ * at most 64 limbs run on the vector ALU and add none).  Divisions that need
+ * no Newton iteration (v < B, u < v, v = 0) report zeros.  Launches
+ * directly (no graph). */
+int bigint_diag_divmod_ragged(int64_t* counts, uint32_t* q, const int64_t* q_off,
                               uint32_t* r, const int64_t* r_off, int32_t* status,
                               const uint32_t* u, const int64_t* u_off,
                               const uint32_t* v, const int64_t* v_off,

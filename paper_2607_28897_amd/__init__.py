@@ -76,6 +76,7 @@ def lib() -> ctypes.CDLL:
             "bigint_plan_workspace_size": ([_vp, ctypes.POINTER(ctypes.c_size_t)], _int),
             "bigint_plan_set_workspace": ([_vp, _vp, ctypes.c_size_t], _int),
             "bigint_plan_destroy": ([_vp], _int),
+            "bigint_plan_info": ([_vp, _vp, _int], _int),
             "bigint_mul_ragged": ([_vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp], _int),
             "bigint_divmod_ragged": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp], _int),
             "bigint_autotune": ([ctypes.c_char_p, _int], _int),
@@ -333,6 +334,14 @@ class _Plan:
         _check(lib().bigint_plan_set_workspace(self._h, _p(buf), buf.numel() * buf.element_size()),
                "bigint_plan_set_workspace")
 
+    def info(self) -> dict:
+        """Launches per call, graphs instantiated so far, calls replayed from a graph."""
+        import numpy as np
+        v = np.zeros(3, np.int64)
+        _check(lib().bigint_plan_info(self._h, v.ctypes.data_as(ctypes.c_void_p), 3), "bigint_plan_info")
+        return {"launches_per_call": int(v[0]), "graphs_instantiated": int(v[1]),
+                "graph_replays": int(v[2])}
+
     def close(self):
         if self._h:
             lib().bigint_plan_destroy(self._h)
@@ -360,10 +369,10 @@ class MulPlan(_Plan):
     def __call__(self, a, a_off, b, b_off, out=None, out_off=None):
         torch = _torch()
         if out_off is None:
-            out_off, total = _offsets(self.len_a + self.len_b, a.device)
-        else:
-            total = int(out_off[-1].item())
+            out_off, _ = _offsets(self.len_a + self.len_b, a.device)
         if out is None:
+            # the total comes from the plan's host-side lengths (no device read)
+            total = int(self.len_a.sum() + self.len_b.sum())
             out = torch.empty(total, dtype=a.dtype, device=a.device)
         _check(lib().bigint_mul_ragged(_p(out), _p(out_off), _p(a), _p(a_off), _p(b), _p(b_off),
                                        self.batch, self._h, _stream()), "bigint_mul_ragged")
@@ -386,12 +395,13 @@ class DivPlan(_Plan):
 
     def counters(self, u, u_off, v, v_off):
         """The same division, plus per division [Newton steps, fix-up unit
-        corrections, quotient corrections] as an int32 [batch, 3] tensor."""
+        corrections, quotient corrections, int8 MFMA multiply-accumulates] as
+        an int64 [batch, 4] tensor."""
         torch = _torch()
         q = torch.empty(int(self.len_a.sum()), dtype=u.dtype, device=u.device)
         r = torch.empty(int(self.len_b.sum()), dtype=u.dtype, device=u.device)
         st = torch.empty(self.batch, dtype=torch.int32, device=u.device)
-        cnt = torch.empty((self.batch, 3), dtype=torch.int32, device=u.device)
+        cnt = torch.empty((self.batch, 4), dtype=torch.int64, device=u.device)
         _check(lib().bigint_diag_divmod_ragged(_p(cnt), _p(q), _p(u_off), _p(r), _p(v_off), _p(st),
                                                _p(u), _p(u_off), _p(v), _p(v_off), self.batch,
                                                self._h, _stream()), "bigint_diag_divmod_ragged")

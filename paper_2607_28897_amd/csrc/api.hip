@@ -357,8 +357,40 @@ struct bigint_plan_s {
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  const void* key[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  const void* key[9] = {};
+  // counters reported by bigint_plan_info
+  int64_t n_launches = 0;     // kernel launches one call enqueues
+  int64_t n_captures = 0;     // graphs instantiated so far
+  int64_t n_replays = 0;      // calls served by launching an instantiated graph
 };
+
+// Runs launch(stream) through the plan's hipGraph: captured on the plan's own
+// stream the first time (and whenever the call's pointers change), then
+// launched on the caller's stream, the null stream included.
+template <class F>
+static int plan_graph_call(bigint_plan_s* plan, const void* const* key, int nkey, F launch,
+                           hipStream_t s) {
+  if (memcmp(key, plan->key, sizeof(void*) * nkey) != 0 || !plan->exec) {
+    if (plan->exec) { (void)hipGraphExecDestroy(plan->exec); plan->exec = nullptr; }
+    if (plan->graph) { (void)hipGraphDestroy(plan->graph); plan->graph = nullptr; }
+    if (!plan->cap_stream) BI_HIP(hipStreamCreateWithFlags(&plan->cap_stream, hipStreamNonBlocking));
+    BI_HIP(hipStreamBeginCapture(plan->cap_stream, hipStreamCaptureModeThreadLocal));
+    const int rc = launch(plan->cap_stream);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(plan->cap_stream, &g);
+    if (rc != BIGINT_OK) { if (g) (void)hipGraphDestroy(g); return rc; }
+    if (e != hipSuccess) { set_hip_error(e); return BIGINT_EHIP; }
+    plan->graph = g;
+    BI_HIP(hipGraphInstantiate(&plan->exec, g, nullptr, nullptr, 0));
+    memset(plan->key, 0, sizeof(plan->key));
+    memcpy(plan->key, key, sizeof(void*) * nkey);
+    ++plan->n_captures;
+  } else {
+    ++plan->n_replays;
+  }
+  BI_HIP(hipGraphLaunch(plan->exec, s));
+  return BIGINT_OK;
+}
 
 static int plan_build_mul(bigint_plan_s* p) {
   const int64_t B = p->batch;
@@ -456,6 +488,7 @@ static int plan_build_mul(bigint_plan_s* p) {
     }
     p->cls = cls;
   }
+  p->n_launches = plain ? (B > 0 ? 1 : 0) : (int64_t)p->cls.size();
   if (B > 0) {
     BI_HIP(hipMalloc(&p->d_queue, sizeof(QueueItem) * B));
     BI_HIP(hipMemcpy(p->d_queue, q.data(), sizeof(QueueItem) * B, hipMemcpyHostToDevice));
@@ -485,6 +518,7 @@ static int plan_build_div(bigint_plan_s* p) {
   std::vector<int32_t> q(B);
   for (int64_t t = 0; t < B; ++t) q[t] = (int32_t)idx[t];
   p->grid = div_chunk(p->cap_u, p->cap_v, B);
+  p->n_launches = B > 0 ? (B + p->grid - 1) / p->grid : 0;
   if (B > 0) {
     BI_HIP(hipMalloc(&p->d_queue, sizeof(int32_t) * B));
     BI_HIP(hipMemcpy(p->d_queue, q.data(), sizeof(int32_t) * B, hipMemcpyHostToDevice));
@@ -552,6 +586,13 @@ int bigint_plan_destroy(bigint_plan_t plan) {
   return BIGINT_OK;
 }
 
+int bigint_plan_info(bigint_plan_t plan, int64_t* info, int n) {
+  if (!plan || (!info && n > 0) || n < 0) return BIGINT_EINVAL;
+  const int64_t v[3] = {plan->n_launches, plan->n_captures, plan->n_replays};
+  for (int i = 0; i < n; ++i) info[i] = i < 3 ? v[i] : 0;
+  return BIGINT_OK;
+}
+
 int bigint_mul_ragged(uint32_t* out, const int64_t* out_off, const uint32_t* a,
                       const int64_t* a_off, const uint32_t* b, const int64_t* b_off, int64_t batch,
                       bigint_plan_t plan, void* stream) {
@@ -570,24 +611,9 @@ int bigint_mul_ragged(uint32_t* out, const int64_t* out_off, const uint32_t* a,
     return launch_mul_ragged(out, out_off, a, a_off, b, b_off, plan->d_queue, plan->cls.data(),
                              (int)plan->cls.size(), ls);
   };
-  if ((plan->flags & BIGINT_PLAN_NO_GRAPH) || s == nullptr) return launch(s);
+  if (plan->flags & BIGINT_PLAN_NO_GRAPH) return launch(s);
   const void* key[6] = {out, out_off, a, a_off, b, b_off};
-  if (!plan->exec || memcmp(key, plan->key, sizeof(key)) != 0) {
-    if (plan->exec) { (void)hipGraphExecDestroy(plan->exec); plan->exec = nullptr; }
-    if (plan->graph) { (void)hipGraphDestroy(plan->graph); plan->graph = nullptr; }
-    if (!plan->cap_stream) BI_HIP(hipStreamCreateWithFlags(&plan->cap_stream, hipStreamNonBlocking));
-    BI_HIP(hipStreamBeginCapture(plan->cap_stream, hipStreamCaptureModeThreadLocal));
-    const int rc = launch(plan->cap_stream);
-    hipGraph_t g = nullptr;
-    const hipError_t e = hipStreamEndCapture(plan->cap_stream, &g);
-    if (rc != BIGINT_OK) { if (g) (void)hipGraphDestroy(g); return rc; }
-    if (e != hipSuccess) { set_hip_error(e); return BIGINT_EHIP; }
-    plan->graph = g;
-    BI_HIP(hipGraphInstantiate(&plan->exec, g, nullptr, nullptr, 0));
-    memcpy(plan->key, key, sizeof(key));
-  }
-  BI_HIP(hipGraphLaunch(plan->exec, s));
-  return BIGINT_OK;
+  return plan_graph_call(plan, key, 6, launch, s);
 }
 
 // ---- division ------------------------------------------------------------------
@@ -639,7 +665,7 @@ int bigint_shinv(uint32_t* w, const uint32_t* v, int64_t nv, int64_t h, int64_t 
 static int divmod_ragged(uint32_t* q, const int64_t* q_off, uint32_t* r, const int64_t* r_off,
                          int32_t* status, const uint32_t* u, const int64_t* u_off,
                          const uint32_t* v, const int64_t* v_off, int64_t batch,
-                         bigint_plan_t plan, int32_t* counts, hipStream_t s) {
+                         bigint_plan_t plan, int64_t* counts, hipStream_t s) {
   if (!plan || plan->op != BIGINT_OP_DIVMOD || batch != plan->batch) return BIGINT_EINVAL;
   if (batch == 0) return BIGINT_OK;
   if (!q || !q_off || !r || !r_off || !u || !u_off || !v || !v_off) return BIGINT_EINVAL;
@@ -648,17 +674,23 @@ static int divmod_ragged(uint32_t* q, const int64_t* q_off, uint32_t* r, const i
   if (overlap(q, tu * 4, u, tu * 4) || overlap(q, tu * 4, v, tv * 4) || overlap(r, tv * 4, u, tu * 4) ||
       overlap(r, tv * 4, v, tv * 4) || overlap(q, tu * 4, r, tv * 4))
     return BIGINT_EINVAL;
-  if (counts && (overlap(counts, (size_t)batch * 12, q, tu * 4) ||
-                 overlap(counts, (size_t)batch * 12, r, tv * 4)))
+  if (counts && (overlap(counts, (size_t)batch * 32, q, tu * 4) ||
+                 overlap(counts, (size_t)batch * 32, r, tv * 4)))
     return BIGINT_EINVAL;
   if (!plan->ws) {
     BI_HIP(hipMalloc(&plan->ws, plan->ws_need));
     plan->ws_bytes = plan->ws_need;
     plan->ws_owned = true;
   }
-  return launch_divmod(q, q_off, r, r_off, status, u, u_off, 0, v, v_off, 0,
-                       reinterpret_cast<const int32_t*>(plan->d_queue), batch, plan->ws,
-                       plan->cap_u, plan->cap_v, plan->grid, -1, counts, s);
+  auto launch = [&](hipStream_t ls) {
+    return launch_divmod(q, q_off, r, r_off, status, u, u_off, 0, v, v_off, 0,
+                         reinterpret_cast<const int32_t*>(plan->d_queue), batch, plan->ws,
+                         plan->cap_u, plan->cap_v, plan->grid, -1, counts, ls);
+  };
+  // the counting variant is a diagnostic: launched directly
+  if (counts || (plan->flags & BIGINT_PLAN_NO_GRAPH)) return launch(s);
+  const void* key[9] = {q, q_off, r, r_off, status, u, u_off, v, v_off};
+  return plan_graph_call(plan, key, 9, launch, s);
 }
 
 int bigint_divmod_ragged(uint32_t* q, const int64_t* q_off, uint32_t* r, const int64_t* r_off,
@@ -669,7 +701,7 @@ int bigint_divmod_ragged(uint32_t* q, const int64_t* q_off, uint32_t* r, const i
                        (hipStream_t)stream);
 }
 
-int bigint_diag_divmod_ragged(int32_t* counts, uint32_t* q, const int64_t* q_off, uint32_t* r,
+int bigint_diag_divmod_ragged(int64_t* counts, uint32_t* q, const int64_t* q_off, uint32_t* r,
                               const int64_t* r_off, int32_t* status, const uint32_t* u,
                               const int64_t* u_off, const uint32_t* v, const int64_t* v_off,
                               int64_t batch, bigint_plan_t plan, void* stream) {
@@ -694,8 +726,9 @@ int bigint_diag_mad_rate(uint64_t* scratch, int64_t blocks, int64_t iters, void*
 // ---- autotuning ------------------------------------------------------------------
 // For each size bin, every tile configuration (strips per band P, waves per
 // work-group, digit width) multiplies the same random batch; the fastest is
-// kept.  All candidates must give identical bytes (checked on the first
-// instance).
+// kept.  All candidates must give identical bytes: every candidate's whole
+// output is compared with the first one's on the device, and any difference
+// fails the call (BIGINT_EHIP) without changing the table.
 
 int bigint_autotune(const char* cache_path, int flags) {
   (void)flags;
@@ -721,7 +754,15 @@ int bigint_autotune(const char* cache_path, int flags) {
         hipMalloc(&out, out_bytes) != hipSuccess) {
       rc = BIGINT_ENOMEM;
     }
-    std::vector<uint32_t> host((size_t)nb * n), first, cur(2 * (size_t)n);
+    // ref: the first candidate's whole output; every later candidate must
+    // reproduce it byte for byte (compared on the device); diff: the count
+    // of differing words
+    uint32_t *ref = nullptr, *diff = nullptr;
+    if (rc == BIGINT_OK && (hipMalloc(&ref, out_bytes) != hipSuccess ||
+                            hipMalloc(&diff, sizeof(uint32_t)) != hipSuccess))
+      rc = BIGINT_ENOMEM;
+    bool have_ref = false;
+    std::vector<uint32_t> host((size_t)nb * n);
     if (rc == BIGINT_OK) {
       uint64_t x = 0x9e3779b97f4a7c15ull ^ (uint64_t)n;  // splitmix64 stream
       auto next = [&]() {
@@ -758,17 +799,31 @@ int bigint_autotune(const char* cache_path, int flags) {
         }
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rc = BIGINT_EHIP; break; }
-        if (hipMemcpy(cur.data(), out, cur.size() * 4, hipMemcpyDeviceToHost) != hipSuccess) {
-          rc = BIGINT_EHIP;
-          break;
+        if (!have_ref) {
+          if (hipMemcpyAsync(ref, out, out_bytes, hipMemcpyDeviceToDevice, s) != hipSuccess) {
+            rc = BIGINT_EHIP;
+            break;
+          }
+          have_ref = true;
+        } else {
+          uint32_t nd = 0;
+          if (hipMemsetAsync(diff, 0, sizeof(uint32_t), s) != hipSuccess ||
+              launch_count_diff(diff, ref, out, out_bytes / 4, s) != BIGINT_OK ||
+              hipMemcpyAsync(&nd, diff, sizeof(uint32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+              hipStreamSynchronize(s) != hipSuccess) {
+            rc = BIGINT_EHIP;
+            break;
+          }
+          if (nd != 0) { rc = BIGINT_EHIP; set_hip_error(hipErrorUnknown); break; }
         }
-        if (first.empty()) first = cur;
-        else if (first != cur) { rc = BIGINT_EHIP; set_hip_error(hipErrorUnknown); break; }
         if (ms < best) { best = ms; pick = TuneEntry{n, P, W, D}; }
       }
+    (void)hipStreamSynchronize(s);
     if (a) (void)hipFree(a);
     if (b) (void)hipFree(b);
     if (out) (void)hipFree(out);
+    if (ref) (void)hipFree(ref);
+    if (diff) (void)hipFree(diff);
     table.push_back(pick);
   }
   (void)hipEventDestroy(e0);

@@ -296,12 +296,27 @@ __device__ inline void wg_mul_small(uint32_t* dst, const uint32_t* a, int na, co
 // overlap a, b): small operands by column sums, the rest on the MFMA-split
 // multiply.  One out-of-line copy serves every call site of the division, so
 // the kernel's code stays small enough for the instruction cache.
+// adjust (nullable): adjust[3] += the int8 multiply-accumulates of the MFMA
+// products (digit pairs (i, j) of the computed strips, i + j below 256 times
+// their count); the column-sum products run on the vector ALU and add none.
+__host__ __device__ inline int64_t tri(int64_t x) { return x > 0 ? x * (x + 1) / 2 : 0; }
+
+__host__ __device__ inline int64_t mfma_pairs(int na, int nb, int nout) {
+  const int64_t Na = mfma::ndigits_w<kDW>(na), Nb = mfma::ndigits_w<kDW>(nb);
+  const int64_t K = Na + Nb - 1;
+  const int64_t lim = nout < 0 ? K : min(K, (int64_t)mfma::kStrip *
+                                             ((nout + mfma::strip_limbs<kDW>() - 1) / mfma::strip_limbs<kDW>()));
+  // pairs with i + j < lim in [0, Na) x [0, Nb), by inclusion and exclusion
+  return tri(lim) - tri(lim - Na) - tri(lim - Nb) + tri(lim - Na - Nb);
+}
+
 __device__ __noinline__ void wg_mul(uint32_t* dst, const uint32_t* a, int na, const uint32_t* b,
-                                       int nb, char* smem, int nout) {
+                                       int nb, char* smem, int nout, int64_t* adjust) {
   if (na <= kSmallMul && nb <= kSmallMul) {
     wg_mul_small(dst, a, na, b, nb, smem, nout);
     return;
   }
+  if (adjust) adjust[3] += mfma_pairs(na, nb, nout);
   mfma::wg_mul_mfma<kDW, kP>(dst, nullptr, a, na, b, nb, smem, nout);
 }
 
@@ -344,7 +359,7 @@ __host__ __device__ inline Bufs carve_bufs(uint32_t* ws, int nu, int nv) {
 // make w = floor(B^c / v) and E = B^c - v w in [0, v).  Returns the new lw.
 // adjust (nullable): diagnostic counters; adjust[1] += the unit steps of w.
 __device__ inline int fixup(const uint32_t* v, int k1, int c, Bufs& bf, int lw, Shared* sh,
-                            char* smem, int* adjust) {
+                            char* smem, int64_t* adjust) {
   // P = v * w
   const int lp = k1 + lw;
   const int le = max(k1 + 2, 2);
@@ -355,7 +370,7 @@ __device__ inline int fixup(const uint32_t* v, int k1, int c, Bufs& bf, int lw, 
     // ends in limb 0 (P >= B^c, and P mod B^le = P - B^c) or in an all-ones
     // limb (P < B^c, e = -P mod B^le), so the low le limbs of P suffice.  Any
     // other top limb means a far estimate: the whole product below decides.
-    wg_mul(bf.T, v, k1, bf.W, lw, smem, le);
+    wg_mul(bf.T, v, k1, bf.W, lw, smem, le, adjust);
     // every wave reads the same limb after the multiply's closing barrier
     const uint32_t top = __builtin_amdgcn_readfirstlane(bf.T[le - 1]);
     if (top == 0u) {
@@ -371,7 +386,7 @@ __device__ inline int fixup(const uint32_t* v, int k1, int c, Bufs& bf, int lw, 
     }
   }
   if (!have_e) {
-    wg_mul(bf.T, v, k1, bf.W, lw, smem, -1);
+    wg_mul(bf.T, v, k1, bf.W, lw, smem, -1, adjust);
     // sign: P >= B^c  <=>  some limb at index >= c is nonzero
     const int pp = wg_prec(bf.T, lp, sh);
     if (pp <= c) {
@@ -449,7 +464,7 @@ __device__ inline int fixup(const uint32_t* v, int k1, int c, Bufs& bf, int lw, 
 // Leaves w in bf.W and returns its limb count; E = B^h - v w.
 // adjust (nullable): adjust[0] += Newton steps, adjust[1] += fix-up unit steps.
 __device__ inline int shifted_inverse(const uint32_t* v, int k1, int h, Bufs& bf, Shared* sh,
-                                      char* smem, int* adjust) {
+                                      char* smem, int64_t* adjust) {
   const int k = k1 - 1;
   // starting value: floor(B^(k+2) / v) from below, using the top three limbs
   if (threadIdx.x == 0) {
@@ -512,7 +527,7 @@ __device__ inline int shifted_inverse(const uint32_t* v, int k1, int h, Bufs& bf
       // than w B^sd <= B^(c-m-1) to w e, which moves that floor by at most
       // one unit (the next fix-up absorbs it)
       const int sd = max(0, min(le - 1, c - m - 1 - lw));
-      wg_mul(bf.T, bf.W, lw, bf.E + sd, le - sd, smem, -1);
+      wg_mul(bf.T, bf.W, lw, bf.E + sd, le - sd, smem, -1, adjust);
       const int ly = lw + le - sd;
       // w' = w B^m + floor(Y / B^(c - m)), Y = w (e >> sd limbs)
       lnew = lw + m + 1;
@@ -542,7 +557,7 @@ __device__ inline int shifted_inverse(const uint32_t* v, int k1, int h, Bufs& bf
 // corrections, each added to.
 __device__ inline int wg_divmod(uint32_t* q, int nq, uint32_t* r, int nr, const uint32_t* u, int nu,
                                 const uint32_t* v, int nv, Bufs bf, Shared* sh, char* smem,
-                                bool inverse_only, int h_inv, int* adjust) {
+                                bool inverse_only, int h_inv, int64_t* adjust) {
   if (threadIdx.x == 0) sh->failed = 0u;
   __syncthreads();
   const int k1 = wg_prec(v, nv, sh);
@@ -591,7 +606,7 @@ __device__ inline int wg_divmod(uint32_t* q, int nq, uint32_t* r, int nr, const 
   // less than B^(su+lw) <= B^(h-1) to u w, so q comes out exact or one low
   // (and floor(u w / B^h) itself is floor(u / v) or one below)
   const int su = max(0, h - 1 - lw);
-  wg_mul(bf.T, u + su, h - su, bf.W, lw, smem, -1);
+  wg_mul(bf.T, u + su, h - su, bf.W, lw, smem, -1, adjust);
   const int lz = h - su + lw;
   const int lq = max(lz - (h - su), 1);
   wg_shr_copy(bf.U2, lq + 2, bf.T, lz, h - su);
@@ -599,7 +614,7 @@ __device__ inline int wg_divmod(uint32_t* q, int nq, uint32_t* r, int nr, const 
   // q v mod B^(k1+2) is needed
   const int lq2 = max(wg_prec(bf.U2, lq + 1, sh), 1);
   const int lr = k1 + 2;
-  wg_mul(bf.T, bf.U2, lq2, v, k1, smem, lr);
+  wg_mul(bf.T, bf.U2, lq2, v, k1, smem, lr, adjust);
   wg_arith<true>(bf.E, lr, u, h, bf.T, min(lr, lq2 + k1), sh);
   // corrections: while r >= v, q += 1 and r -= v (at most twice)
   for (int rounds = 0; rounds < 4; ++rounds) {

@@ -81,6 +81,8 @@ int launch_mul_plain_ragged(uint32_t* out, const int64_t* out_off, const uint32_
                             const QueueItem* queue, int64_t nitems, size_t lds, hipStream_t s);
 
 int launch_mfma_rate(int32_t* out, int blocks, int iters, int toggle, hipStream_t s);
+// *count += the number of indices i < n with x[i] != y[i] (count is device memory)
+int launch_count_diff(uint32_t* count, const uint32_t* x, const uint32_t* y, size_t n, hipStream_t s);
 int launch_mad_rate(uint64_t* out, int blocks, int iters, hipStream_t s);
 
 // ---- division -------------------------------------------------------------------
@@ -95,6 +97,6 @@ int launch_divmod(uint32_t* q, const int64_t* q_off, uint32_t* r, const int64_t*
                   int32_t* status, const uint32_t* u, const int64_t* u_off, int nu,
                   const uint32_t* v, const int64_t* v_off, int nv, const int32_t* queue,
                   int64_t nitems, void* ws, int cap_u, int cap_v, int chunk, int h_inv,
-                  int32_t* adjust, hipStream_t s);
+                  int64_t* adjust, hipStream_t s);
 
 }  // namespace bi

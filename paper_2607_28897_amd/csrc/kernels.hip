@@ -779,6 +779,25 @@ __global__ __launch_bounds__(256) void k_mad_rate(uint64_t* out, int iters) {
   out[blockIdx.x * blockDim.x + threadIdx.x] = t;
 }
 
+// number of differing words of two device arrays (the autotuner's identity
+// check): one atomic add per wave that saw a difference
+__global__ __launch_bounds__(256) void k_count_diff(uint32_t* count, const uint32_t* x,
+                                                    const uint32_t* y, size_t n) {
+  uint32_t d = 0;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    d += x[i] != y[i];
+  for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o);
+  if (lane_id() == 0 && d) atomicAdd(count, d);
+}
+
+int launch_count_diff(uint32_t* count, const uint32_t* x, const uint32_t* y, size_t n, hipStream_t s) {
+  const unsigned blocks = (unsigned)std::min<size_t>(std::max<size_t>(cdiv((int64_t)n, 256), 1), 8192);
+  hipLaunchKernelGGL(k_count_diff, dim3(blocks), dim3(256), 0, s, count, x, y, n);
+  BI_LAUNCH_CHECK();
+  return BIGINT_OK;
+}
+
 int launch_mad_rate(uint64_t* out, int blocks, int iters, hipStream_t s) {
   hipLaunchKernelGGL(k_mad_rate, dim3(blocks), dim3(256), 0, s, out, iters);
   BI_LAUNCH_CHECK();

@@ -28,15 +28,15 @@ int div_threads(int cap_u) {
 // measured 11% slower on 512 ragged divisions: the loop made the compiler
 // keep loop-invariant values live across the whole division.)
 // h_inv >= 0 selects the shifted-inverse diagnostic: q[i] = floor(B^h_inv / v).
-// adjust (nullable): 3 int32 per instance, the division's counters (Newton
-// steps, fix-up unit steps, quotient corrections).
+// adjust (nullable): 4 int64 per instance, the division's counters (Newton
+// steps, fix-up unit steps, quotient corrections, MFMA multiply-accumulates).
 __global__ __launch_bounds__(kDivThreads, 4) void k_divmod(uint32_t* q, const int64_t* q_off, uint32_t* r,
                                                 const int64_t* r_off, int32_t* status,
                                                 const uint32_t* u, const int64_t* u_off, int nu,
                                                 const uint32_t* v, const int64_t* v_off, int nv,
                                                 const int32_t* queue, int64_t first, int64_t nitems,
                                                 uint32_t* ws, int cap_u, int cap_v, int h_inv,
-                                                int32_t* adjust) {
+                                                int64_t* adjust) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
   __shared__ div::Shared sh;
   const int64_t t = first + blockIdx.x;
@@ -57,15 +57,14 @@ __global__ __launch_bounds__(kDivThreads, 4) void k_divmod(uint32_t* q, const in
     lq = h_inv >= 0 ? h_inv + 1 : nu; qo = i * (int64_t)lq;
     lr = nv; ro = i * (int64_t)nv;
   }
-  int cnt[3] = {0, 0, 0};
+  int64_t cnt[4] = {0, 0, 0, 0};
   const int st = div::wg_divmod(q + qo, lq, r ? r + ro : nullptr, lr, u ? u + uo : nullptr, lu,
                                 v + vo, lv, bf, &sh, smem, h_inv >= 0, h_inv, cnt);
   if (threadIdx.x == 0) {
     if (status) status[i] = st;
     if (adjust) {
-      adjust[3 * i] = cnt[0];
-      adjust[3 * i + 1] = cnt[1];
-      adjust[3 * i + 2] = cnt[2];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) adjust[4 * i + j] = cnt[j];
     }
   }
 }
@@ -100,7 +99,7 @@ int launch_divmod(uint32_t* q, const int64_t* q_off, uint32_t* r, const int64_t*
                   int32_t* status, const uint32_t* u, const int64_t* u_off, int nu,
                   const uint32_t* v, const int64_t* v_off, int nv, const int32_t* queue,
                   int64_t nitems, void* ws, int cap_u, int cap_v, int chunk, int h_inv,
-                  int32_t* adjust, hipStream_t s) {
+                  int64_t* adjust, hipStream_t s) {
   const size_t lds = div_lds_bytes(cap_u, cap_v);
   if (lds > 163840 - sizeof(div::Shared) - 64) return BIGINT_EUNSUPPORTED;
   if (chunk < 1) return BIGINT_EINVAL;

@@ -14,3 +14,15 @@ def host(t):
 
 def rand_limbs(g, *shape):
     return g.integers(0, 2**32, size=shape, dtype=np.uint64).astype(np.uint32)
+
+
+def oracle_map(fn, items):
+    """fn over items on a pool of host threads (the oracle's C calls release
+    the interpreter lock); results in input order.  At most 16 threads, the
+    host share of one GPU."""
+    import concurrent.futures as cf
+    import os
+    workers = max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity")
+                         else (os.cpu_count() or 1)))
+    with cf.ThreadPoolExecutor(max_workers=workers) as ex:
+        return list(ex.map(fn, items))

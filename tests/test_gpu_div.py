@@ -4,7 +4,7 @@ inverse itself against floor(B^h / v)."""
 import numpy as np
 import pytest
 
-from gpu_util import dev, host, rand_limbs
+from gpu_util import dev, host, oracle_map, rand_limbs
 
 pytestmark = pytest.mark.gpu
 
@@ -73,25 +73,68 @@ def test_edge_alphabet(bi, orc):
         _check_batch(bi, orc, u, v)
 
 
-def test_ragged_512_divisions_sampled(bi, orc):
-    import torch
+def _to_int(x):
+    return int.from_bytes(np.ascontiguousarray(x, dtype="<u4").tobytes(), "little")
+
+
+@pytest.fixture(scope="module")
+def divs_512(orc):
+    """The 512-division configuration (dividends log-uniform in [2^16, 2^18]
+    bits, divisors half the limbs) and the oracle's quotient and remainder of
+    every division."""
     from paper_2607_28897_amd import inputs
     c = inputs.ragged_div_2e16_2e18()
-    nu, nv = c["nu"], c["nv"]
-    plan = bi.DivPlan(nu, nv)
-    q, r, st = plan(dev(c["u"]), torch.from_numpy(c["u_off"]).cuda(), dev(c["v"]),
-                    torch.from_numpy(c["v_off"]).cuda())
-    q, r, st = host(q), host(r), st.cpu().numpy()
-    assert not st.any()
-    order = np.argsort(-nu)
-    sample = list(order[:3]) + list(order[-3:]) + list(range(0, 512, 61))
     u_off, v_off = c["u_off"], c["v_off"]
-    for i in sample:
-        u = c["u"][u_off[i]:u_off[i + 1]]
-        v = c["v"][v_off[i]:v_off[i + 1]]
-        wq, wr, _ = orc.divmod1(u, v)
-        assert np.array_equal(q[u_off[i]:u_off[i + 1]], wq), i
-        assert np.array_equal(r[v_off[i]:v_off[i + 1]], wr), i
+    res = oracle_map(lambda i: orc.divmod1(c["u"][u_off[i]:u_off[i + 1]],
+                                           c["v"][v_off[i]:v_off[i + 1]]), range(512))
+    c["want_q"] = np.concatenate([x[0] for x in res])
+    c["want_r"] = np.concatenate([x[1] for x in res])
+    return c
+
+
+def _check_512(c, q, r, st):
+    """Every division: the unique characterisation u = q v + r, 0 <= r < v
+    (Python integers), then limb-by-limb equality with the oracle."""
+    assert not st.any()
+    u_off, v_off = c["u_off"], c["v_off"]
+    for i in range(512):
+        U = _to_int(c["u"][u_off[i]:u_off[i + 1]])
+        V = _to_int(c["v"][v_off[i]:v_off[i + 1]])
+        Q = _to_int(q[u_off[i]:u_off[i + 1]])
+        R = _to_int(r[v_off[i]:v_off[i + 1]])
+        assert U == Q * V + R and 0 <= R < V, i
+    assert np.array_equal(q, c["want_q"])
+    assert np.array_equal(r, c["want_r"])
+
+
+def test_ragged_512_divisions_every_instance(bi, divs_512):
+    """All 512 divisions, from the captured graph and from two replays."""
+    import torch
+    c = divs_512
+    plan = bi.DivPlan(c["nu"], c["nv"])
+    tu, tuo = dev(c["u"]), torch.from_numpy(c["u_off"]).cuda()
+    tv, tvo = dev(c["v"]), torch.from_numpy(c["v_off"]).cuda()
+    for rep in range(3):
+        q, r, st = plan(tu, tuo, tv, tvo)
+        _check_512(c, host(q), host(r), st.cpu().numpy())
+    info = plan.info()
+    assert info["graphs_instantiated"] >= 1, info
+    plan.close()
+
+
+def test_ragged_512_divisions_direct_and_counters(bi, divs_512):
+    """All 512 divisions launched without a graph, and through the counting
+    diagnostic (same bytes; every division issues MFMA work)."""
+    import torch
+    c = divs_512
+    plan = bi.DivPlan(c["nu"], c["nv"], bi.PLAN_NO_GRAPH)
+    tu, tuo = dev(c["u"]), torch.from_numpy(c["u_off"]).cuda()
+    tv, tvo = dev(c["v"]), torch.from_numpy(c["v_off"]).cuda()
+    q, r, st = plan(tu, tuo, tv, tvo)
+    _check_512(c, host(q), host(r), st.cpu().numpy())
+    q2, r2, st2, cnt = plan.counters(tu, tuo, tv, tvo)
+    assert torch.equal(q, q2) and torch.equal(r, r2) and torch.equal(st, st2)
+    assert (cnt.cpu().numpy()[:, 3] > 0).all()
     plan.close()
 
 
@@ -190,9 +233,15 @@ def test_ragged_counters(bi, orc):
         assert np.array_equal(r[v_off[i]:v_off[i + 1]], wr), i
         k1, h = _prec(vs[i]), _prec(us[i])
         if k1 <= 1 or h < k1:
-            assert cnt[i].tolist() == [0, 0, 0], i
+            assert cnt[i].tolist() == [0, 0, 0, 0], i
             continue
         assert cnt[i, 0] == _newton_steps(k1, h), (i, cnt[i])
         assert 0 <= cnt[i, 1] <= 4 * (cnt[i, 0] + 1), (i, cnt[i])
         assert 0 <= cnt[i, 2] <= 3, (i, cnt[i])
+        # MFMA work: none when every product has operands of at most 64 limbs;
+        # otherwise below the digit pairs of ten full h x h products
+        if h <= 64:
+            assert cnt[i, 3] == 0, (i, cnt[i])
+        else:
+            assert 0 < cnt[i, 3] <= 10 * (4 * h) ** 2, (i, cnt[i])
     plan.close()

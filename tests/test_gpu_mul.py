@@ -4,7 +4,7 @@ bit for bit, through the C-ABI; plus the intermediate steps of the MFMA path
 import numpy as np
 import pytest
 
-from gpu_util import dev, host, rand_limbs
+from gpu_util import dev, host, oracle_map, rand_limbs
 
 pytestmark = pytest.mark.gpu
 
@@ -72,24 +72,50 @@ def test_pairs_2e15(bi, orc, algo):
     assert np.array_equal(host(p), orc.mul(c["a"], c["b"]))
 
 
-@pytest.mark.parametrize("algo", ALGOS)
-def test_pairs_2e17_sampled(bi, orc, algo):
+@pytest.fixture(scope="module")
+def pairs_2e17(orc):
+    """1024 pairs of 2^17-bit integers (half carry-adversarial) and the
+    oracle's product of every pair."""
     from paper_2607_28897_amd import inputs
     c = inputs.pairs_2e17_mixed()
-    p = host(_mul(bi, dev(c["a"]), dev(c["b"]), algo))
-    # every instance is checked against the oracle on a sample of rows, half
-    # uniform and half carry-adversarial
-    for i in list(range(0, 512, 37)) + list(range(512, 1024, 37)):
-        assert np.array_equal(p[i], orc.mul1(c["a"][i], c["b"][i])), i
+    c["want"] = np.stack(oracle_map(lambda i: orc.mul1(c["a"][i], c["b"][i]), range(1024)))
+    return c
+
+
+@pytest.fixture(scope="module")
+def pairs_2e19(orc):
+    """256 pairs of 2^19-bit integers and the oracle's product of every pair."""
+    from paper_2607_28897_amd import inputs
+    c = inputs.pairs_2e19()
+    c["want"] = np.stack(oracle_map(lambda i: orc.mul1(c["a"][i], c["b"][i]), range(256)))
+    return c
+
+
+def _rows_differing(got, want):
+    return [int(i) for i in np.nonzero((got != want).any(axis=1))[0]]
 
 
 @pytest.mark.parametrize("algo", ALGOS)
-def test_pairs_2e19_sampled(bi, orc, algo):
-    from paper_2607_28897_amd import inputs
-    c = inputs.pairs_2e19()
+def test_pairs_2e17_every_instance(bi, pairs_2e17, algo):
+    """All 1024 products of the 2^17-bit configuration, uniform and
+    carry-adversarial halves, against the oracle limb by limb."""
+    c = pairs_2e17
     p = host(_mul(bi, dev(c["a"]), dev(c["b"]), algo))
-    for i in (0, 1, 77, 128, 200, 255):
-        assert np.array_equal(p[i], orc.mul1(c["a"][i], c["b"][i])), i
+    assert p.shape == c["want"].shape
+    assert _rows_differing(p, c["want"]) == []
+
+
+@pytest.mark.parametrize("algo", ALGOS + ["karatsuba"])
+def test_pairs_2e19_every_instance(bi, pairs_2e19, algo):
+    """All 256 products of the 2^19-bit configuration (the headline), for the
+    plain kernel, both digit widths of the MFMA-split kernel and one
+    Karatsuba level, against the oracle limb by limb."""
+    c = pairs_2e19
+    if algo == "karatsuba":
+        p = host(bi.mul(dev(c["a"]), dev(c["b"]), bi.MUL_KARATSUBA))
+    else:
+        p = host(_mul(bi, dev(c["a"]), dev(c["b"]), algo))
+    assert _rows_differing(p, c["want"]) == []
 
 
 @pytest.mark.parametrize("algo", ALGOS)

@@ -4,7 +4,7 @@ each segment's end, hipGraph replay), against the oracle."""
 import numpy as np
 import pytest
 
-from gpu_util import dev, host
+from gpu_util import dev, host, oracle_map
 
 pytestmark = pytest.mark.gpu
 
@@ -49,31 +49,69 @@ def test_small_ragged_mixed_sizes(bi, orc, flags):
         assert np.array_equal(res[oo[i]:oo[i + 1]], want), i
 
 
-def test_ragged_4096_sampled_and_replay(bi, orc):
-    import torch
+@pytest.fixture(scope="module")
+def ragged_4096(orc):
+    """The 4096-product ragged configuration (bit lengths log-uniform in
+    [2^15, 2^19]) and the oracle's product of every pair, flattened like the
+    library's output."""
     from paper_2607_28897_amd import inputs
     c = inputs.ragged_mul_2e15_2e19()
     lens = c["lens"]
-    plan = bi.MulPlan(lens, lens)
-    ta, tao = dev(c["a"]), torch.from_numpy(c["a_off"]).cuda()
-    tb, tbo = dev(c["b"]), torch.from_numpy(c["b_off"]).cuda()
-    out_off, total = None, int(2 * lens.sum())
-    out = torch.empty(total, dtype=torch.int32, device="cuda")
+    rows = oracle_map(lambda i: orc.mul1(c["a"][c["a_off"][i]:c["a_off"][i + 1]],
+                                         c["b"][c["b_off"][i]:c["b_off"][i + 1]]), range(lens.size))
+    c["want"] = np.concatenate(rows)
     off = np.zeros(lens.size + 1, np.int64)
     np.cumsum(2 * lens, out=off[1:])
-    out_off = torch.from_numpy(off).cuda()
-    plan(ta, tao, tb, tbo, out=out, out_off=out_off)       # captures the graph
-    r1 = host(out).copy()
-    out.zero_()
-    plan(ta, tao, tb, tbo, out=out, out_off=out_off)       # replays it
-    r2 = host(out)
-    assert np.array_equal(r1, r2)
-    order = np.argsort(-lens)
-    sample = list(order[:4]) + list(order[-4:]) + list(range(0, 4096, 257))
-    for i in sample:
-        a = c["a"][c["a_off"][i]:c["a_off"][i + 1]]
-        b = c["b"][c["b_off"][i]:c["b_off"][i + 1]]
-        assert np.array_equal(r1[off[i]:off[i + 1]], orc.mul1(a, b)), i
+    c["out_off"] = off
+    return c
+
+
+def _first_bad_instance(got, c):
+    off = c["out_off"]
+    bad = np.nonzero(got != c["want"])[0]
+    return None if bad.size == 0 else int(np.searchsorted(off, bad[0], side="right") - 1)
+
+
+@pytest.mark.parametrize("stream", ["default", "side"])
+def test_ragged_4096_every_instance_graph_replays(bi, ragged_4096, stream):
+    """Every product of the 4096-instance configuration against the oracle,
+    from the captured graph's first launch and from three replays (with
+    other work on the stream in between, each replay into a cleared buffer),
+    on torch's default stream (the null stream) and on a side stream; the
+    plan's counters show one graph instantiated and replayed."""
+    import torch
+    c = ragged_4096
+    lens = c["lens"]
+    st = torch.cuda.Stream() if stream == "side" else torch.cuda.default_stream()
+    with torch.cuda.stream(st):
+        plan = bi.MulPlan(lens, lens)
+        ta, tao = dev(c["a"]), torch.from_numpy(c["a_off"]).cuda()
+        tb, tbo = dev(c["b"]), torch.from_numpy(c["b_off"]).cuda()
+        out = torch.empty(int(2 * lens.sum()), dtype=torch.int32, device="cuda")
+        out_off = torch.from_numpy(c["out_off"]).cuda()
+        scratch = torch.zeros(1 << 20, dtype=torch.int32, device="cuda")
+        for rep in range(4):
+            out.fill_(-1)
+            plan(ta, tao, tb, tbo, out=out, out_off=out_off)
+            scratch.add_(1)                               # eager work between replays
+            st.synchronize()
+            assert _first_bad_instance(host(out), c) is None, rep
+        info = plan.info()
+        assert info["graphs_instantiated"] == 1 and info["graph_replays"] == 3, info
+        assert info["launches_per_call"] >= 1
+        plan.close()
+
+
+def test_ragged_4096_direct_launch(bi, ragged_4096):
+    """The same batch without a graph (BIGINT_PLAN_NO_GRAPH), every product."""
+    import torch
+    c = ragged_4096
+    lens = c["lens"]
+    plan = bi.MulPlan(lens, lens, bi.PLAN_NO_GRAPH)
+    out, _ = plan(dev(c["a"]), torch.from_numpy(c["a_off"]).cuda(), dev(c["b"]),
+                  torch.from_numpy(c["b_off"]).cuda())
+    assert _first_bad_instance(host(out), c) is None
+    assert plan.info()["graphs_instantiated"] == 0
     plan.close()
 
 
