@@ -179,6 +179,21 @@ int bigint_divmod(uint32_t* q, uint32_t* r, int32_t* status, const uint32_t* u,
                   int64_t nu, const uint32_t* v, int64_t nv, int64_t batch,
                   void* stream);
 
+/* bigint_divmod_noalloc: bigint_divmod (same arguments, same results, same
+ * size limits) for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation.
+ * It calls no allocation routine.  Its workspace is a fixed array of
+ * 128 MiB in device memory that each GPU the library runs on holds until the
+ * process ends; a batch whose divisions need more workspace slots than that
+ * array holds at once runs in several consecutive launches on `stream`.
+ * Every call on one GPU shares that GPU's array: calls that overlap in time
+ * on one GPU (different streams or threads) race and must not be issued.
+ * The first call on a device looks up the array's address there
+ * (hipGetSymbolAddress); a failure is BIGINT_EHIP. */
+int bigint_divmod_noalloc(uint32_t* q, uint32_t* r, int32_t* status,
+                          const uint32_t* u, int64_t nu, const uint32_t* v,
+                          int64_t nv, int64_t batch, void* stream);
+
 /* ---- plans for ragged batches ------------------------------------------------------
  * A plan fixes the instance sizes of a ragged batch (host arrays len_a, len_b
  * of `batch` limb counts; for DIVMOD len_a are the dividend and len_b the

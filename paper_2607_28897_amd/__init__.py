@@ -72,6 +72,7 @@ def lib() -> ctypes.CDLL:
             "bigint_sub": ([_vp, _vp, _vp, _vp, _i64, _i64, _vp], _int),
             "bigint_mul": ([_vp, _vp, _i64, _vp, _i64, _i64, _int, _vp], _int),
             "bigint_divmod": ([_vp, _vp, _vp, _vp, _i64, _vp, _i64, _i64, _vp], _int),
+            "bigint_divmod_noalloc": ([_vp, _vp, _vp, _vp, _i64, _vp, _i64, _i64, _vp], _int),
             "bigint_plan_create": ([ctypes.POINTER(_vp), _int, _vp, _vp, _i64, _int], _int),
             "bigint_plan_workspace_size": ([_vp, ctypes.POINTER(ctypes.c_size_t)], _int),
             "bigint_plan_set_workspace": ([_vp, _vp, ctypes.c_size_t], _int),

@@ -652,6 +652,33 @@ int bigint_divmod(uint32_t* q, uint32_t* r, int32_t* status, const uint32_t* u, 
   return divmod_launch_alloc(q, r, status, u, nu, v, nv, batch, -1, (hipStream_t)stream);
 }
 
+int bigint_divmod_noalloc(uint32_t* q, uint32_t* r, int32_t* status, const uint32_t* u, int64_t nu,
+                          const uint32_t* v, int64_t nv, int64_t batch, void* stream) {
+  if (!q || !r || !u || !v || nu <= 0 || nv <= 0 || batch < 0) return BIGINT_EINVAL;
+  if (nu > 8192 || nv > 8192 || batch > 0x7fffffff) return BIGINT_EUNSUPPORTED;
+  const size_t qb = (size_t)nu * batch * 4, rb = (size_t)nv * batch * 4;
+  const size_t ub = (size_t)nu * batch * 4, vb = (size_t)nv * batch * 4, sb = (size_t)batch * 4;
+  if (overlap(q, qb, u, ub) || overlap(q, qb, v, vb) || overlap(r, rb, u, ub) ||
+      overlap(r, rb, v, vb) || overlap(q, qb, r, rb))
+    return BIGINT_EINVAL;
+  if (status && (overlap(status, sb, q, qb) || overlap(status, sb, r, rb) ||
+                 overlap(status, sb, u, ub) || overlap(status, sb, v, vb)))
+    return BIGINT_EINVAL;
+  if (batch == 0) return BIGINT_OK;
+  void* ws = nullptr;
+  size_t cap = 0;
+  const int rc = div_scratch(&ws, &cap);
+  if (rc != BIGINT_OK) return rc;
+  // work-groups per launch: as bigint_divmod, but no more workspace slots
+  // than the scratch array holds (the launches run one after another)
+  const size_t slot = div_ws_bytes((int)nu, (int)nv, 1);
+  const int64_t grid = std::min<int64_t>(div_chunk((int)nu, (int)nv, batch), (int64_t)(cap / slot));
+  if (grid < 1) return BIGINT_EUNSUPPORTED;
+  return launch_divmod(q, nullptr, r, nullptr, status, u, nullptr, (int)nu, v, nullptr, (int)nv,
+                       nullptr, batch, ws, (int)nu, (int)nv, (int)grid, -1, nullptr,
+                       (hipStream_t)stream);
+}
+
 int bigint_shinv(uint32_t* w, const uint32_t* v, int64_t nv, int64_t h, int64_t batch,
                  void* stream) {
   if (!w || !v || nv <= 0 || batch < 0 || h < nv) return BIGINT_EINVAL;

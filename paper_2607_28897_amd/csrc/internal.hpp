@@ -93,6 +93,9 @@ size_t div_ws_bytes(int cap_u, int cap_v, int slots);
 size_t div_lds_bytes(int cap_u, int cap_v);
 int div_groups_per_cu(int cap_u, int cap_v);
 int div_chunk(int cap_u, int cap_v, int64_t batch);
+// The allocation-free division's device workspace on the current device:
+// its address (from hipGetSymbolAddress, once per device) and size.
+int div_scratch(void** ptr, size_t* bytes);
 int launch_divmod(uint32_t* q, const int64_t* q_off, uint32_t* r, const int64_t* r_off,
                   int32_t* status, const uint32_t* u, const int64_t* u_off, int nu,
                   const uint32_t* v, const int64_t* v_off, int nv, const int32_t* queue,

@@ -1,6 +1,7 @@
 // kernels_div.hip -- division kernels: one work-group per division, the
 // divisions taken in queue order (largest first).
 #include <algorithm>
+#include <mutex>
 
 #include "internal.hpp"
 #include "dev_divmod.hpp"
@@ -93,6 +94,37 @@ int div_groups_per_cu(int cap_u, int cap_v) {
 int div_chunk(int cap_u, int cap_v, int64_t batch) {
   const int64_t resident = (int64_t)num_cus() * div_groups_per_cu(cap_u, cap_v);
   return (int)std::max<int64_t>(1, std::min<int64_t>(batch, 8 * resident));
+}
+
+// ---- workspace of the allocation-free division (bigint_divmod_noalloc) ----------
+// A file-scope device array, one copy per GPU, held until the process ends.
+// Every call on a GPU shares that GPU's copy (calls that overlap on one GPU
+// race); the division needs none of it cleared.  In host code the array's
+// name is only a stand-in: its device address comes from
+// hipGetSymbolAddress, looked up once per device and kept.
+constexpr size_t kDivScratchBytes = (size_t)128 << 20;
+__device__ __align__(256) uint8_t scratch[kDivScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+int div_scratch(void** ptr, size_t* bytes) {
+  int dev = 0;
+  BI_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return BIGINT_EUNSUPPORTED;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    BI_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return BIGINT_EHIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *ptr = g_scratch_ptr[dev];
+  *bytes = kDivScratchBytes;
+  return BIGINT_OK;
 }
 
 int launch_divmod(uint32_t* q, const int64_t* q_off, uint32_t* r, const int64_t* r_off,
