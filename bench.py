@@ -383,7 +383,7 @@ def divmod_leg(torch, bi, inputs, args):
             "same_size_products_ms": round(mms, 4), "div_over_mul": round(ms / mms, 3),
             "roofline": mfma_roofline(2.0 * macs, ms, f"2 int8 ops per digit product the division's MFMA "
                                                     f"products compute, {2.0 * macs:.4g} per call"),
-            "newton_steps_histogram": hist(0), "fixup_corrections_histogram": hist(1),
+            "newton_steps_histogram": hist(0), "negative_branch_steps_histogram": hist(1),
             "quotient_corrections_histogram": hist(2)}
 
 
@@ -536,7 +536,7 @@ def divmod_mode(torch, bi, inputs, args):
                       "same_size_products_ms": round(mms, 4), "div_over_mul": round(ms / mms, 3),
                       "all_status_ok": bool((st == 0).all().item()),
                       "newton_steps_histogram": hist(0),
-                      "fixup_corrections_histogram": hist(1),
+                      "negative_branch_steps_histogram": hist(1),
                       "quotient_corrections_histogram": hist(2), "uniform_rows": rows}))
     plan.close()
     mplan.close()

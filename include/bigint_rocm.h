@@ -166,10 +166,12 @@ int bigint_poly(uint32_t* out, const uint32_t* a, const uint32_t* b, int64_t n,
 
 /* ---- division (Section 5.3) ------------------------------------------------------
  * q[i] = floor(u[i] / v[i]), r[i] = u[i] - q[i]*v[i], 0 <= r[i] < v[i].
- * The quotient comes from the whole shifted inverse w = floor(B^h / v)
- * (B = 2^32, h = precision of u) computed by Newton steps whose
- * multiplications run on the MFMA-split multiply (Section 5.3, `step`), then
- * q = floor(u*w / B^h) with one final correction.
+ * The quotient comes from the whole shifted inverse w ~ B^h / v (B = 2^32,
+ * h = precision of u), grown by the paper's signed Newton `step` (Section
+ * 5.3, both branches, one guard limb, no exact fix-up on the way) whose
+ * multiplications run on the MFMA-split multiply; then q~ = floor(u*w / B^h)
+ * and the signed remainder u - q~ v brought into [0, v) by a few unit
+ * corrections.
  * u: batch*nu limbs, v: batch*nv limbs, q: batch*nu limbs, r: batch*nv limbs,
  * status: batch int32 or NULL.  A zero divisor gives status BIGINT_DIVZERO,
  * q = 0 and r = u mod 2^(32 nv); the call itself still returns BIGINT_OK.
@@ -272,10 +274,11 @@ int bigint_shinv(uint32_t* w, const uint32_t* v, int64_t nv, int64_t h,
 /* bigint_diag_divmod_ragged: bigint_divmod_ragged (same arguments, same
  * results) that also writes, per division, four counters of the procedure
  * of Section 5.3 to counts[4*i .. 4*i+3] (device int64, 4*batch, must not
- * overlap q or r): [0] the Newton steps (`step`) taken, [1] the unit
- * corrections the exact fix-ups applied to the inverse, [2] the corrections
- * of the final quotient (a bounded loop; hitting its bound marks the
- * division BIGINT_DIV_FAILED), [3] the int8 multiply-accumulates of the
+ * overlap q or r): [0] the Newton steps (`step`) taken, [1] those taken on
+ * the negative branch (e = B^c - V w <= 0: w B^m minus a ceiling), [2] the
+ * unit corrections of the quotient (adding or subtracting v from the signed
+ * remainder; bounded loops, and hitting a bound marks the division
+ * BIGINT_DIV_FAILED), [3] the int8 multiply-accumulates of the
  * division's MFMA products: for each product, the digit pairs (i, j) whose
  * coefficient i + j lies in the strips it computes (products of operands of
  * at most 64 limbs run on the vector ALU and add none).  Divisions that need

@@ -1,20 +1,25 @@
 // dev_divmod.hpp -- division through the whole shifted inverse (Section 5.3).
 //
-// For a divisor v with k+1 significant limbs (B = 2^32) and a dividend u with
-// h significant limbs, the quotient is read off w = floor(B^h / v):
-// q = floor(u w / B^h) is floor(u/v) or one less, fixed by one comparison of
-// r = u - q v with v.  w itself is grown by Newton steps in the integral
-// domain, in the form of the paper's `step` (Section 5.3, Fig. "step"):
-//     w' = w B^m + floor(w (B^cur - v w) / B^(cur-m))
-// which turns w = floor(B^cur / v) into an approximation of
-// floor(B^(cur+m) / v) from below; with m <= cur - k - 1 its error is a few
-// units.  Each step is preceded by an exact fix-up at scale cur (the signed
-// difference e = B^cur - v w -- the paper's powDiff -- is brought into
-// [0, v) by adding or subtracting v), so e >= 0 and only the positive
-// branch of `step` occurs.  The starting value comes from the top three limbs
-// of v.  All multiplications are full products on the MFMA-split multiply;
-// linear operations (precision, shifts, additions, comparisons) run on the
-// whole work-group.  Division by a one-limb divisor is a short division.
+// For a divisor v with k1 significant limbs (B = 2^32) and a dividend u with
+// h significant limbs, the quotient is read off w ~ B^h / v:
+// q~ = floor(u w / B^h) is within a few units of floor(u / v), and the signed
+// remainder u - q~ v, reduced into [0, v) by adding or subtracting v, fixes
+// it.  w is grown by Newton steps in the integral domain, the paper's `step`
+// (Section 5.3, Fig. bdiv-F-code) with both of its branches: with
+// e = B^c - V w (the signed powDiff, V the divisor's top limbs),
+//     w' = w B^m + floor(w e / B^(c-m))      if e > 0
+//     w' = w B^m - ceil(w |e| / B^(c-m))     if e <= 0
+// (the ceiling: the truncated quotient plus one unless the dropped limbs are
+// all zero -- nullUpToInd and baddOne).  If w is within eta units of B^c / V,
+// w' is within eta^2 B^(m-c+t) + 1 units of B^(c+m) / V; one guard limb
+// (m <= c - t - 1) keeps eta below 2 at every scale with no exact fix-up, so
+// the whole procedure takes no correction step before the quotient's.  The
+// starting value is the exact floor(B^(t0+2) / V0) of the top t0 = min(k1, 4)
+// limbs of v, within one unit of B^(k1+2) / v.  Multiplications run on the
+// MFMA-split multiply at their operands' actual lengths (low products where
+// only limbs below a bound are needed); linear operations (precision,
+// shifts, additions, comparisons) run on the whole work-group.  Division by
+// a one-limb divisor is a short division.
 #pragma once
 
 #include "common.hpp"
@@ -26,7 +31,7 @@ namespace div {
 
 constexpr int kP = 4;   // strips per band of the multiplications
 constexpr int kDW = 8;  // digit width of the multiplications
-constexpr int kMaxAdjust = 64;  // cap on fix-up rounds per scale
+constexpr int kMaxAdjust = 64;  // cap on the exact fix-up's rounds (the inverse diagnostic)
 constexpr int kGuard = 2;       // divisor limbs kept beyond the precision of a Newton step
 
 // LDS words used by the division itself (besides the multiply's area)
@@ -34,7 +39,7 @@ struct Shared {
   uint32_t red[4];      // reductions
   uint32_t scan[32];    // carry-scan scratch
   uint32_t w0[4];       // initial estimate (one thread)
-  uint32_t failed;      // a fix-up hit its cap (never expected)
+  uint32_t failed;      // a bounded loop hit its bound, or an estimate left its error bound (never expected)
 };
 
 // ---- work-group linear operations on global limb arrays ------------------------
@@ -192,8 +197,8 @@ __device__ __forceinline__ int wg_cmp(const uint32_t* x, int nx, const uint32_t*
 // 9% slower.)
 template <bool SUB, class FX, class FY>
 __device__ __forceinline__ uint32_t div_addsub(uint32_t* out, int n, FX X, FY Y, Shared* sh,
-                                               uint32_t* top = nullptr) {
-  return wg_addsub<16, SUB>(out, n, X, Y, 0u, sh->scan, top);
+                                               uint32_t* top = nullptr, uint32_t cin = 0u) {
+  return wg_addsub<16, SUB>(out, n, X, Y, cin, sh->scan, top);
 }
 
 // dst[0..n) = x + y (or x - y), operands zero-extended; returns carry/borrow
@@ -320,15 +325,26 @@ __device__ __noinline__ void wg_mul(uint32_t* dst, const uint32_t* a, int na, co
   mfma::wg_mul_mfma<kDW, kP>(dst, nullptr, a, na, b, nb, smem, nout);
 }
 
-// ---- one-lane helpers for the starting value ------------------------------------
+// ---- one-lane helper for the starting value ------------------------------------
 
-// floor(N / D) for a 128-bit N and a divisor D < 2^97 given as (hi, lo), by
-// restoring long division bit by bit (no division instruction needed).
-__device__ inline unsigned __int128 udiv128(unsigned __int128 N, unsigned __int128 D) {
-  unsigned __int128 q = 0, r = 0;
-  for (int i = 127; i >= 0; --i) {
-    r = (r << 1) | ((N >> i) & 1);
-    if (r >= D) { r -= D; q |= (unsigned __int128)1 << i; }
+// floor(B^(t0+2) / V) for the top t0 = min(k1, 4) limbs V of v (B = 2^32):
+// restoring long division of a single one bit by V, one quotient bit per
+// round, with the 128-bit remainder's carry-out kept in a flag.  The
+// quotient is at most B^3 (97 bits).
+__device__ inline unsigned __int128 seed_inverse(const uint32_t* v, int k1) {
+  typedef unsigned __int128 u128;
+  const int t0 = min(k1, 4);
+  u128 V = 0;
+  for (int i = 0; i < t0; ++i) V = (V << 32) | v[k1 - 1 - i];
+  const int nb = 32 * (t0 + 2);
+  u128 r = 0, q = 0;
+  for (int i = nb; i >= 0; --i) {
+    const bool over = (r >> 127) != 0;
+    r = (r << 1) | (u128)(i == nb ? 1u : 0u);
+    if (over || r >= V) {
+      r -= V;
+      if (i < 128) q |= (u128)1 << i;
+    }
   }
   return q;
 }
@@ -460,91 +476,89 @@ __device__ inline int fixup(const uint32_t* v, int k1, int c, Bufs& bf, int lw, 
   return lw;
 }
 
-// w = floor(B^h / v) for a divisor with k1 >= 2 significant limbs and h >= k1.
-// Leaves w in bf.W and returns its limb count; E = B^h - v w.
-// adjust (nullable): adjust[0] += Newton steps, adjust[1] += fix-up unit steps.
+// w ~ B^h / v (within two units) for a divisor with k1 >= 2 significant
+// limbs and h >= k1, by the signed Newton steps of the header comment.
+// Leaves w in bf.W and returns its limb count.
+// adjust (nullable): adjust[0] += Newton steps, adjust[1] += steps taken on
+// the negative branch (e <= 0).
 __device__ inline int shifted_inverse(const uint32_t* v, int k1, int h, Bufs& bf, Shared* sh,
                                       char* smem, int64_t* adjust) {
-  const int k = k1 - 1;
-  // starting value: floor(B^(k+2) / v) from below, using the top three limbs
   if (threadIdx.x == 0) {
-    typedef unsigned __int128 u128;
-    u128 w0;
-    if (k1 == 2) {
-      // exact: floor(B^3 / (v1 B + v0))
-      const u128 V = ((u128)v[1] << 32) | v[0];
-      w0 = udiv128((u128)1 << 96, V);
-    } else {
-      const u128 V3 = ((u128)v[k] << 64) | ((u128)v[k - 1] << 32) | v[k - 2];
-      w0 = udiv128(~(u128)0, V3 + 1);
-    }
-    sh->w0[0] = (uint32_t)w0;
-    sh->w0[1] = (uint32_t)(w0 >> 32);
-    sh->w0[2] = (uint32_t)(w0 >> 64);
-    sh->w0[3] = (uint32_t)(w0 >> 96);
+    const unsigned __int128 w0 = seed_inverse(v, k1);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) sh->w0[i] = (uint32_t)(w0 >> (32 * i));
   }
   __syncthreads();
-  int cur = k + 2;
-  int lw;
-  if (h < cur) {
-    // h == k1: w = floor(B^h / v) < B; start from w0 / B
-    cur = h;
-    for (int i = threadIdx.x; i < 4; i += blockDim.x) bf.W[i] = (i < 3) ? sh->w0[i + 1] : 0u;
-    __syncthreads();
-    lw = 3;
-  } else {
-    for (int i = threadIdx.x; i < 4; i += blockDim.x) bf.W[i] = sh->w0[i];
-    __syncthreads();
-    lw = 4;
-  }
-  lw = wg_prec(bf.W, lw, sh);
-  if (lw == 0) {  // estimate 0: start from 1 (the fix-up walks up)
-    if (threadIdx.x == 0) bf.W[0] = 1u;
-    __syncthreads();
-    lw = 1;
-  }
-  // Newton steps.  w ~ floor(B^cur / v) carries p = cur - k1 + 1 limbs, and a
-  // step to precision p' only needs the divisor to about p' limbs: with V =
-  // the top t = min(k1, p' + kGuard) limbs of v (v = V B^s + low, s = k1 - t),
-  // floor(B^(cur-s) / V) differs from floor(B^cur / v) by at most a unit or
-  // two, so each step runs on V at the scale cur - s: an exact fix-up there
-  // (which also yields e = B^(cur-s) - V w in [0, V)), then the step.  The
-  // last fix-up, at scale h, uses all of v.
-  for (;;) {
-    const int m = min(h - cur, cur - k1);
-    const int t = cur == h ? k1 : min(k1, cur + m - k1 + 1 + kGuard);
+  // w0 ~ B^(k1+2) / v; a quotient of at most two limbs (h < k1 + 2) takes
+  // w0 / B^(k1+2-h) instead, within one unit of B^h / v as well
+  int cur = k1 + 2;
+  const int d0 = cur > h ? cur - h : 0;
+  for (int i = threadIdx.x; i < 4; i += blockDim.x) bf.W[i] = i + d0 < 4 ? sh->w0[i + d0] : 0u;
+  __syncthreads();
+  cur -= d0;
+  int lw = max(wg_prec(bf.W, 4, sh), 1);
+  // Newton steps: w ~ B^cur / v carries p = cur - k1 limbs of precision, and
+  // a step to p' = p + m only needs the divisor to p' + kGuard limbs: with V
+  // the top t of them (v = V B^s + low), w also approximates B^(cur-s) / V
+  // to within B^(1 - kGuard) units of the same value, so each step runs on V
+  // at the scale c = cur - s.  m = cur - k1 - 1 keeps one guard limb.
+  while (cur < h) {
+    const int m = min(h - cur, cur - k1 - 1);
+    const int t = min(k1, cur + m - k1 + 1 + kGuard);
     const int sdrop = k1 - t;
     const uint32_t* V = v + sdrop;
     const int c = cur - sdrop;
-    lw = fixup(V, t, c, bf, lw, sh, smem, adjust);
-    if (cur == h) break;
-    if (adjust) adjust[0] += 1;
-    // Y = w * e (e < V has at most t limbs; a zero e costs one product of zeros)
-    const int le = t;
-    int lnew;
-    {
-      // only floor(w e / B^(c-m)) is needed: the low sd limbs of e add less
-      // than w B^sd <= B^(c-m-1) to w e, which moves that floor by at most
-      // one unit (the next fix-up absorbs it)
-      const int sd = max(0, min(le - 1, c - m - 1 - lw));
-      wg_mul(bf.T, bf.W, lw, bf.E + sd, le - sd, smem, -1, adjust);
-      const int ly = lw + le - sd;
-      // w' = w B^m + floor(Y / B^(c - m)), Y = w (e >> sd limbs)
-      lnew = lw + m + 1;
-      auto X = [&](int j) -> uint32_t { return (j >= m && j - m < lw) ? bf.W[j - m] : 0u; };
-      auto Y = [&](int j) -> uint32_t {
-        const int s2 = j + c - m - sd;
-        return s2 < ly ? bf.T[s2] : 0u;
-      };
-      if (threadIdx.x == 0) sh->red[3] = 0;
-      div_addsub<false>(bf.U2, lnew, X, Y, sh, &sh->red[3]);
+    // powDiff: e = B^c - V w with |e| < 3 V < B^(t+1); since c >= t + 2,
+    // (V w) mod B^(t+2) ends in limb 0 when V w >= B^c (then |e| = that
+    // residue) and in an all-ones limb when V w < B^c (then e = its negation)
+    const int le = t + 2;
+    wg_mul(bf.E, V, t, bf.W, lw, smem, le, adjust);
+    // every wave reads the same limb after the multiply's closing barrier
+    const uint32_t top = __builtin_amdgcn_readfirstlane(bf.E[le - 1]);
+    const bool neg = top == 0u;
+    if (!neg) {
+      if (top != 0xffffffffu) {   // outside the error bound: never expected
+        if (threadIdx.x == 0) sh->failed = 1u;
+        __syncthreads();
+        break;
+      }
+      auto X = [&](int) -> uint32_t { return 0u; };
+      auto Y = [&](int j) -> uint32_t { return bf.E[j]; };
+      div_addsub<true>(bf.E, le, X, Y, sh);   // e = 0 - (V w mod B^le), in place
     }
+    if (adjust) {
+      adjust[0] += 1;
+      adjust[1] += neg ? 1 : 0;
+    }
+    // step: Y = w |e|, of which floor(Y / B^(c-m)) is needed; the low sd
+    // limbs of |e| add less than w B^sd <= B^(c-m-1) to Y, so dropping them
+    // moves that quotient by at most one unit (inside the error bound)
+    const int sd = max(0, min(le - 1, c - m - 1 - lw));
+    wg_mul(bf.T, bf.W, lw, bf.E + sd, le - sd, smem, -1, adjust);
+    const int ly = lw + le - sd;
+    const int sy = c - m - sd;           // Y / B^sy
+    // negative branch: the ceiling takes one more unit unless the dropped
+    // limbs Y[0 .. sy) are all zero (nullUpToInd)
+    uint32_t cin = 0u;
+    if (neg) {
+      int nz = 0;
+      for (int j = threadIdx.x; j < min(sy, ly); j += blockDim.x) nz |= bf.T[j] != 0u;
+      cin = __syncthreads_or(nz) ? 1u : 0u;
+    }
+    const int lnew = lw + m + 1;
+    auto X = [&](int j) -> uint32_t { return (j >= m && j - m < lw) ? bf.W[j - m] : 0u; };
+    auto Y = [&](int j) -> uint32_t { return j + sy < ly ? bf.T[j + sy] : 0u; };
+    // (the reset happens before every thread's atomicMax: the addition's
+    // carry scan synchronises the work-group first)
+    if (threadIdx.x == 0) sh->red[3] = 0;
+    if (neg) div_addsub<true>(bf.U2, lnew, X, Y, sh, &sh->red[3], cin);
+    else div_addsub<false>(bf.U2, lnew, X, Y, sh, &sh->red[3]);
     {  // the new w is in U2: swap the two buffers instead of copying
       uint32_t* tmp = bf.W;
       bf.W = bf.U2;
       bf.U2 = tmp;
     }
-    lw = max((int)sh->red[3], 1);   // w's length, reduced by the addition itself
+    lw = max((int)sh->red[3], 1);   // w's length, from the addition itself
     __syncthreads();
     cur += m;
   }
@@ -599,33 +613,45 @@ __device__ inline int wg_divmod(uint32_t* q, int nq, uint32_t* r, int nr, const 
   }
   int lw = shifted_inverse(v, k1, h, bf, sh, smem, adjust);
   if (inverse_only) {
+    // the diagnostic wants floor(B^h / v) exactly: one exact fix-up at scale h
+    lw = fixup(v, k1, h, bf, lw, sh, smem, nullptr);
     wg_shr_copy(q, nq, bf.W, lw, 0);
     return sh->failed ? BIGINT_DIV_FAILED : BIGINT_DIV_OK;
   }
-  // q = floor(u w / B^h), from the top limbs of u only: the low su limbs add
-  // less than B^(su+lw) <= B^(h-1) to u w, so q comes out exact or one low
-  // (and floor(u w / B^h) itself is floor(u / v) or one below)
+  // q~ = floor(u w / B^h), from the top limbs of u only: the low su limbs add
+  // less than B^(su+lw) <= B^(h-1) to u w, so they move q~ by at most one unit
   const int su = max(0, h - 1 - lw);
   wg_mul(bf.T, u + su, h - su, bf.W, lw, smem, -1, adjust);
-  const int lz = h - su + lw;
-  const int lq = max(lz - (h - su), 1);
-  wg_shr_copy(bf.U2, lq + 2, bf.T, lz, h - su);
-  // r = u - q v, which lies in [0, 3v) and so fits k1 + 2 limbs: only
-  // q v mod B^(k1+2) is needed
-  const int lq2 = max(wg_prec(bf.U2, lq + 1, sh), 1);
+  const uint32_t* qt = bf.T + (h - su);              // q~: lw limbs
+  const int lq = max(wg_prec(qt, lw, sh), 1);
+  // r~ = u - q~ v; |r~| < 4 v < B^(k1+1), so r~ mod B^(k1+2) holds it with
+  // its sign in the top limb
   const int lr = k1 + 2;
-  wg_mul(bf.T, bf.U2, lq2, v, k1, smem, lr, adjust);
-  wg_arith<true>(bf.E, lr, u, h, bf.T, min(lr, lq2 + k1), sh);
-  // corrections: while r >= v, q += 1 and r -= v (at most twice)
-  for (int rounds = 0; rounds < 4; ++rounds) {
-    if (wg_cmp(bf.E, lr, v, k1, lr, sh) < 0) break;
-    wg_arith<true>(bf.E, lr, bf.E, lr, v, k1, sh);
-    wg_arith1<false>(bf.U2, lq2 + 1, bf.U2, lq2 + 1, 1u, sh);
-    if (adjust) adjust[2] += 1;
-    if (rounds == 3 && threadIdx.x == 0) sh->failed = 1u;
+  wg_mul(bf.U2, qt, lq, v, k1, smem, lr, adjust);
+  wg_arith<true>(bf.E, lr, u, h, bf.U2, min(lr, lq + k1), sh);
+  // corrections: while r~ < 0, r~ += v (q~ - 1); while r~ >= v, r~ -= v (q~ + 1)
+  // (each loop is bounded; leaving one at its bound marks the division failed,
+  // which the error analysis rules out: the model and tests see at most 2)
+  int dq = 0;
+  bool done_neg = false, done_pos = false;
+  for (int rounds = 0; rounds < 8; ++rounds) {
+    const uint32_t top = __builtin_amdgcn_readfirstlane(bf.E[lr - 1]);
+    if (top == 0u) { done_neg = true; break; }
+    wg_arith<false>(bf.E, lr, bf.E, lr, v, k1, sh);
+    --dq;
   }
-  wg_shr_copy(q, nq, bf.U2, lq2 + 1, 0);
-  wg_shr_copy(r, nr, bf.E, lr, 0);
+  for (int rounds = 0; rounds < 8 && done_neg; ++rounds) {
+    if (wg_cmp(bf.E, lr, v, k1, lr, sh) < 0) { done_pos = true; break; }
+    wg_arith<true>(bf.E, lr, bf.E, lr, v, k1, sh);
+    ++dq;
+  }
+  if (!done_pos && threadIdx.x == 0) sh->failed = 1u;
+  if (adjust) adjust[2] += dq < 0 ? -dq : dq;
+  // q = q~ + dq over all nq limbs, r = r~ over nr limbs
+  if (dq >= 0) wg_arith1<false>(q, nq, qt, lq, (uint32_t)dq, sh);
+  else wg_arith1<true>(q, nq, qt, lq, (uint32_t)(-dq), sh);
+  wg_shr_copy(r, nr, bf.E, k1, 0);
+  __syncthreads();
   return sh->failed ? BIGINT_DIV_FAILED : BIGINT_DIV_OK;
 }
 

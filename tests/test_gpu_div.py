@@ -183,12 +183,13 @@ def test_divisor_structures(bi, orc, nu, nv):
 
 
 def _newton_steps(k1, h):
-    """Steps of the shifted-inverse schedule (start at scale k1 + 1, grow by
-    m = min(h - cur, cur - k1) limbs per step until the scale reaches h)."""
-    cur = min(k1 + 1, h)
+    """Steps of the shifted-inverse schedule (start at scale k1 + 2, grow by
+    m = min(h - cur, cur - k1 - 1) limbs per step -- one guard limb -- until
+    the scale reaches h)."""
+    cur = min(k1 + 2, h)
     steps = 0
     while cur < h:
-        cur += min(h - cur, cur - k1)
+        cur += min(h - cur, cur - k1 - 1)
         steps += 1
     return steps
 
@@ -236,8 +237,8 @@ def test_ragged_counters(bi, orc):
             assert cnt[i].tolist() == [0, 0, 0, 0], i
             continue
         assert cnt[i, 0] == _newton_steps(k1, h), (i, cnt[i])
-        assert 0 <= cnt[i, 1] <= 4 * (cnt[i, 0] + 1), (i, cnt[i])
-        assert 0 <= cnt[i, 2] <= 3, (i, cnt[i])
+        assert 0 <= cnt[i, 1] <= cnt[i, 0], (i, cnt[i])      # negative-branch steps
+        assert 0 <= cnt[i, 2] <= 3, (i, cnt[i])               # quotient corrections
         # MFMA work: none when every product has operands of at most 64 limbs;
         # otherwise below the digit pairs of ten full h x h products
         if h <= 64:
@@ -245,3 +246,45 @@ def test_ragged_counters(bi, orc):
         else:
             assert 0 < cnt[i, 3] <= 10 * (4 * h) ** 2, (i, cnt[i])
     plan.close()
+
+
+def test_negative_branch_steps(bi, orc):
+    """Divisors whose shifted inverse overshoots, so the Newton steps take
+    the paper's negative branch (w B^m minus a ceiling, with nonzero dropped
+    limbs): B^(n-1) + small and B^(n-1) + B^(n/2) + 1; and powers of the base
+    (e = 0 exactly at every step).  Exact results, and the counters show the
+    branch was taken."""
+    import torch
+    g = np.random.default_rng(123)
+    us, vs, kinds = [], [], []
+    for nv in (5, 17, 100, 600, 1000):
+        for kind in ("pow_plus", "pow_mid", "pow"):
+            v = np.zeros(nv, np.uint32)
+            v[-1] = 1
+            if kind == "pow_plus":
+                v[0] = int(g.integers(1, 1000))
+            elif kind == "pow_mid":
+                v[nv // 2] = 1
+                v[0] = 1
+            for urow in (rand_limbs(g, 1, 2 * nv)[0], np.full(2 * nv, 0xFFFFFFFF, np.uint32)):
+                us.append(urow)
+                vs.append(v)
+                kinds.append((kind, nv))
+    nu = np.array([len(x) for x in us], np.int64)
+    nv_ = np.array([len(x) for x in vs], np.int64)
+    u_off = np.concatenate([[0], np.cumsum(nu)]).astype(np.int64)
+    v_off = np.concatenate([[0], np.cumsum(nv_)]).astype(np.int64)
+    plan = bi.DivPlan(nu, nv_)
+    q, r, st, cnt = plan.counters(dev(np.concatenate(us)), torch.from_numpy(u_off).cuda(),
+                                  dev(np.concatenate(vs)), torch.from_numpy(v_off).cuda())
+    q, r, st, cnt = host(q), host(r), st.cpu().numpy(), cnt.cpu().numpy()
+    for i in range(len(us)):
+        wq, wr, ws = orc.divmod1(us[i], vs[i])
+        assert st[i] == ws == 0, i
+        assert np.array_equal(q[u_off[i]:u_off[i + 1]], wq), (i, kinds[i])
+        assert np.array_equal(r[v_off[i]:v_off[i + 1]], wr), (i, kinds[i])
+        # (the 5-limb B^4 + B^2 + 1 starts below its inverse and stays there)
+        if kinds[i] != ("pow_mid", 5):
+            assert cnt[i, 0] >= 2 and cnt[i, 1] >= 1, (i, kinds[i], cnt[i])
+    plan.close()
+
