@@ -78,6 +78,11 @@ extern "C" {
  * beyond that returns BIGINT_EUNSUPPORTED. */
 #define BIGINT_MFMA_MAX_LIMBS 18432
 
+/* Largest dividend or divisor (in u32 limbs) the division takes: 2^19 bits.
+ * Its products (up to about that many limbs per operand) run on the
+ * MFMA-split multiply, whose operands must fit one work-group's LDS. */
+#define BIGINT_DIV_MAX_LIMBS 16384
+
 typedef struct bigint_plan_s* bigint_plan_t;
 
 /* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
@@ -175,7 +180,7 @@ int bigint_poly(uint32_t* out, const uint32_t* a, const uint32_t* b, int64_t n,
  * u: batch*nu limbs, v: batch*nv limbs, q: batch*nu limbs, r: batch*nv limbs,
  * status: batch int32 or NULL.  A zero divisor gives status BIGINT_DIVZERO,
  * q = 0 and r = u mod 2^(32 nv); the call itself still returns BIGINT_OK.
- * nu, nv in [1, 8192] (else BIGINT_EUNSUPPORTED).  The call allocates its
+ * nu, nv in [1, BIGINT_DIV_MAX_LIMBS] (else BIGINT_EUNSUPPORTED).  The call allocates its
  * workspace with hipMallocAsync on `stream`. */
 int bigint_divmod(uint32_t* q, uint32_t* r, int32_t* status, const uint32_t* u,
                   int64_t nu, const uint32_t* v, int64_t nv, int64_t batch,
@@ -263,7 +268,8 @@ int bigint_autotune_load(const char* cache_path);
  *   computed by the int8 MFMA tiles (int32 output, before recombination).
  * bigint_shinv: w[i*(h+1) ..] = floor(B^h / v[i]) with B = 2^32, the whole
  *   shifted inverse of the division; v: batch*nv limbs, needs h >= nv and
- *   a nonzero top limb of v (else that instance's w is 0); h <= 8192. */
+ *   a nonzero top limb of v (else that instance's w is 0);
+ *   h <= BIGINT_DIV_MAX_LIMBS. */
 int bigint_digits7(uint8_t* out, const uint32_t* a, int64_t n, int64_t D,
                    int64_t batch, void* stream);
 int bigint_conv7(int32_t* c, const uint32_t* a, int64_t na, const uint32_t* b,

@@ -34,6 +34,7 @@ MUL_AUTO, MUL_PLAIN, MUL_MFMA, MUL_KARATSUBA = 0, 1, 2, 3
 OP_MUL, OP_DIVMOD = 1, 2
 PLAN_DEFAULT, PLAN_PLAIN, PLAN_NO_GRAPH = 0, 1, 2
 MFMA_MAX_LIMBS = 18432
+DIV_MAX_LIMBS = 16384
 
 
 class BigIntError(RuntimeError):

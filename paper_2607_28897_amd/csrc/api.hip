@@ -501,7 +501,7 @@ static int plan_build_div(bigint_plan_s* p) {
   const int64_t B = p->batch;
   int64_t cu = 1, cv = 1;
   for (int64_t i = 0; i < B; ++i) {
-    if (p->la[i] > 8192 || p->lb[i] > 8192) return BIGINT_EUNSUPPORTED;
+    if (p->la[i] > BIGINT_DIV_MAX_LIMBS || p->lb[i] > BIGINT_DIV_MAX_LIMBS) return BIGINT_EUNSUPPORTED;
     cu = std::max(cu, p->la[i]);
     cv = std::max(cv, p->lb[i]);
   }
@@ -639,7 +639,8 @@ static int divmod_launch_alloc(uint32_t* q, uint32_t* r, int32_t* status, const 
 int bigint_divmod(uint32_t* q, uint32_t* r, int32_t* status, const uint32_t* u, int64_t nu,
                   const uint32_t* v, int64_t nv, int64_t batch, void* stream) {
   if (!q || !r || !u || !v || nu <= 0 || nv <= 0 || batch < 0) return BIGINT_EINVAL;
-  if (nu > 8192 || nv > 8192 || batch > 0x7fffffff) return BIGINT_EUNSUPPORTED;
+  if (nu > BIGINT_DIV_MAX_LIMBS || nv > BIGINT_DIV_MAX_LIMBS || batch > 0x7fffffff)
+    return BIGINT_EUNSUPPORTED;
   const size_t qb = (size_t)nu * batch * 4, rb = (size_t)nv * batch * 4;
   const size_t ub = (size_t)nu * batch * 4, vb = (size_t)nv * batch * 4, sb = (size_t)batch * 4;
   if (overlap(q, qb, u, ub) || overlap(q, qb, v, vb) || overlap(r, rb, u, ub) ||
@@ -655,7 +656,8 @@ int bigint_divmod(uint32_t* q, uint32_t* r, int32_t* status, const uint32_t* u, 
 int bigint_divmod_noalloc(uint32_t* q, uint32_t* r, int32_t* status, const uint32_t* u, int64_t nu,
                           const uint32_t* v, int64_t nv, int64_t batch, void* stream) {
   if (!q || !r || !u || !v || nu <= 0 || nv <= 0 || batch < 0) return BIGINT_EINVAL;
-  if (nu > 8192 || nv > 8192 || batch > 0x7fffffff) return BIGINT_EUNSUPPORTED;
+  if (nu > BIGINT_DIV_MAX_LIMBS || nv > BIGINT_DIV_MAX_LIMBS || batch > 0x7fffffff)
+    return BIGINT_EUNSUPPORTED;
   const size_t qb = (size_t)nu * batch * 4, rb = (size_t)nv * batch * 4;
   const size_t ub = (size_t)nu * batch * 4, vb = (size_t)nv * batch * 4, sb = (size_t)batch * 4;
   if (overlap(q, qb, u, ub) || overlap(q, qb, v, vb) || overlap(r, rb, u, ub) ||
@@ -682,7 +684,7 @@ int bigint_divmod_noalloc(uint32_t* q, uint32_t* r, int32_t* status, const uint3
 int bigint_shinv(uint32_t* w, const uint32_t* v, int64_t nv, int64_t h, int64_t batch,
                  void* stream) {
   if (!w || !v || nv <= 0 || batch < 0 || h < nv) return BIGINT_EINVAL;
-  if (h > 8192 || batch > 0x7fffffff) return BIGINT_EUNSUPPORTED;
+  if (h > BIGINT_DIV_MAX_LIMBS || batch > 0x7fffffff) return BIGINT_EUNSUPPORTED;
   if (overlap(w, (size_t)(h + 1) * batch * 4, v, (size_t)nv * batch * 4)) return BIGINT_EINVAL;
   if (batch == 0) return BIGINT_OK;
   return divmod_launch_alloc(w, nullptr, nullptr, nullptr, nv, v, nv, batch, (int)h,

@@ -106,6 +106,33 @@ __device__ __forceinline__ int wg_prec(const uint32_t* x, int n, Shared* sh) {
   return r;
 }
 
+// the significant limbs of x[0..nx) and of y[0..ny) in one pass (the loads
+// of both arrays in flight together, one reduction)
+__device__ __forceinline__ void wg_prec2(const uint32_t* x, int nx, const uint32_t* y, int ny,
+                                         Shared* sh, int* px, int* py) {
+  if (max(nx, ny) <= 64 * kWaveRounds) {
+    *px = wg_prec(x, nx, sh);
+    *py = wg_prec(y, ny, sh);
+    return;
+  }
+  if (threadIdx.x == 0) { sh->red[0] = 0; sh->red[1] = 0; }
+  __syncthreads();
+  int mx = 0, my = 0;
+  const int n = max(nx, ny);
+#pragma unroll 8
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const uint32_t a = nx > 0 ? x[min(i, nx - 1)] : 0u, b = ny > 0 ? y[min(i, ny - 1)] : 0u;
+    mx = (i < nx && a != 0u) ? i + 1 : mx;
+    my = (i < ny && b != 0u) ? i + 1 : my;
+  }
+  if (mx) atomicMax(&sh->red[0], (uint32_t)mx);
+  if (my) atomicMax(&sh->red[1], (uint32_t)my);
+  __syncthreads();
+  *px = (int)sh->red[0];
+  *py = (int)sh->red[1];
+  __syncthreads();
+}
+
 // sign of x - y over n limbs (both zero-extended to n), and whether x is 0,
 // in one pass
 struct Cmp { int sign; bool xzero; };
@@ -297,56 +324,118 @@ __device__ inline void wg_mul_small(uint32_t* dst, const uint32_t* a, int na, co
   __syncthreads();
 }
 
-// dst[0 .. nout) = a * b mod B^nout (nout < 0: all na+nb limbs; dst must not
-// overlap a, b): small operands by column sums, the rest on the MFMA-split
-// multiply.  One out-of-line copy serves every call site of the division, so
-// the kernel's code stays small enough for the instruction cache.
 // adjust (nullable): adjust[3] += the int8 multiply-accumulates of the MFMA
-// products (digit pairs (i, j) of the computed strips, i + j below 256 times
-// their count); the column-sum products run on the vector ALU and add none.
+// products (digit pairs (i, j) of the computed strips: i + j from 256 times
+// the first computed strip up to 256 times their end); the column-sum
+// products run on the vector ALU and add none.
 __host__ __device__ inline int64_t tri(int64_t x) { return x > 0 ? x * (x + 1) / 2 : 0; }
 
-__host__ __device__ inline int64_t mfma_pairs(int na, int nb, int nout) {
+// digit pairs (i, j) in [0, Na) x [0, Nb) with i + j < lim, by inclusion and exclusion
+__host__ __device__ inline int64_t pairs_below(int64_t Na, int64_t Nb, int64_t lim) {
+  return tri(lim) - tri(lim - Na) - tri(lim - Nb) + tri(lim - Na - Nb);
+}
+
+__host__ __device__ inline int64_t mfma_pairs(int na, int nb, int nout, int nlo) {
   const int64_t Na = mfma::ndigits_w<kDW>(na), Nb = mfma::ndigits_w<kDW>(nb);
   const int64_t K = Na + Nb - 1;
   const int64_t lim = nout < 0 ? K : min(K, (int64_t)mfma::kStrip *
                                              ((nout + mfma::strip_limbs<kDW>() - 1) / mfma::strip_limbs<kDW>()));
-  // pairs with i + j < lim in [0, Na) x [0, Nb), by inclusion and exclusion
-  return tri(lim) - tri(lim - Na) - tri(lim - Nb) + tri(lim - Na - Nb);
+  const int64_t lo = min(lim, (int64_t)mfma::kStrip * kP * mfma::high_band<kDW>(nlo, kP));
+  return pairs_below(Na, Nb, lim) - pairs_below(Na, Nb, lo);
 }
 
-__device__ __noinline__ void wg_mul(uint32_t* dst, const uint32_t* a, int na, const uint32_t* b,
-                                       int nb, char* smem, int nout, int64_t* adjust) {
+// dst[0 .. nout) = a * b mod B^nout (nout < 0: all na+nb limbs; dst must not
+// overlap a, b): small operands by column sums, the rest on the MFMA-split
+// multiply.  nlo > 0: only the limbs from nlo up are needed, and the MFMA
+// multiply may skip the strips below (dst[nlo ..) is then floor(a b / B^nlo)
+// or one less).  Returns true when every limb of dst is exact.  One
+// out-of-line copy serves every call site of the division, so the kernel's
+// code stays small enough for the instruction cache.
+__device__ __noinline__ bool wg_mul(uint32_t* dst, const uint32_t* a, int na, const uint32_t* b,
+                                    int nb, char* smem, int nout, int64_t* adjust, int nlo = 0) {
   if (na <= kSmallMul && nb <= kSmallMul) {
     wg_mul_small(dst, a, na, b, nb, smem, nout);
-    return;
+    return true;
   }
-  if (adjust) adjust[3] += mfma_pairs(na, nb, nout);
-  mfma::wg_mul_mfma<kDW, kP>(dst, nullptr, a, na, b, nb, smem, nout);
+  if (adjust) adjust[3] += mfma_pairs(na, nb, nout, nlo);
+  mfma::wg_mul_mfma<kDW, kP>(dst, nullptr, a, na, b, nb, smem, nout, nlo);
+  return mfma::high_band<kDW>(nlo, kP) == 0;
 }
 
 // ---- one-lane helper for the starting value ------------------------------------
 
-// floor(B^(t0+2) / V) for the top t0 = min(k1, 4) limbs V of v (B = 2^32):
-// restoring long division of a single one bit by V, one quotient bit per
-// round, with the 128-bit remainder's carry-out kept in a flag.  The
-// quotient is at most B^3 (97 bits).
-__device__ inline unsigned __int128 seed_inverse(const uint32_t* v, int k1) {
-  typedef unsigned __int128 u128;
-  const int t0 = min(k1, 4);
-  u128 V = 0;
-  for (int i = 0; i < t0; ++i) V = (V << 32) | v[k1 - 1 - i];
-  const int nb = 32 * (t0 + 2);
-  u128 r = 0, q = 0;
-  for (int i = nb; i >= 0; --i) {
-    const bool over = (r >> 127) != 0;
-    r = (r << 1) | (u128)(i == nb ? 1u : 0u);
-    if (over || r >= V) {
-      r -= V;
-      if (i < 128) q |= (u128)1 << i;
-    }
+// floor(B^(N+2) / V) for an N-limb V with a nonzero top limb (B = 2^32), by
+// long division in base B (Knuth, TAOCP vol. 2, 4.3.1, Algorithm D):
+// normalise V so its top bit is set, then four quotient limbs, each
+// estimated from the top two remainder limbs and the divisor's top limb,
+// corrected by the divisor's second limb and a final add-back.  N is a
+// compile-time constant, so every limb array lives in registers.
+template <int N>
+__device__ inline unsigned __int128 seed_div(const uint32_t* v, int k1) {
+  constexpr int M = 3;   // the dividend B^(N+2) has N + 3 limbs
+  uint32_t vn[N], un[N + M + 1];
+  const int sft = __clz(v[k1 - 1]);
+#pragma unroll
+  for (int i = N - 1; i >= 0; --i) {
+    const uint32_t hi = v[k1 - N + i];
+    const uint32_t lo = i > 0 ? v[k1 - N + i - 1] : 0u;
+    vn[i] = sft ? (hi << sft) | (lo >> (32 - sft)) : hi;
   }
-  return q;
+#pragma unroll
+  for (int i = 0; i < N + M + 1; ++i) un[i] = 0u;
+  un[N + 2] = 1u << sft;
+  uint32_t q[M + 1];
+#pragma unroll
+  for (int j = M; j >= 0; --j) {
+    const uint64_t num = ((uint64_t)un[j + N] << 32) | un[j + N - 1];
+    uint64_t qhat = num / vn[N - 1];
+    uint64_t rhat = num - qhat * vn[N - 1];
+    for (int k = 0; k < 2; ++k) {
+      if (qhat >= (1ull << 32) || qhat * vn[N - 2] > ((rhat << 32) | un[j + N - 2])) {
+        --qhat;
+        rhat += vn[N - 1];
+        if (rhat < (1ull << 32)) continue;
+      }
+      break;
+    }
+    // un[j .. j+N] -= qhat * vn
+    int64_t borrow = 0;
+    uint64_t carry = 0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      const uint64_t p = qhat * vn[i] + carry;
+      carry = p >> 32;
+      const int64_t t = (int64_t)un[i + j] - (int64_t)(uint32_t)p + borrow;
+      un[i + j] = (uint32_t)t;
+      borrow = t >> 32;
+    }
+    const int64_t t = (int64_t)un[j + N] - (int64_t)carry + borrow;
+    un[j + N] = (uint32_t)t;
+    if (t < 0) {   // qhat was one too large: add V back
+      --qhat;
+      uint64_t c = 0;
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        const uint64_t x = (uint64_t)un[i + j] + vn[i] + c;
+        un[i + j] = (uint32_t)x;
+        c = x >> 32;
+      }
+      un[j + N] += (uint32_t)c;
+    }
+    q[j] = (uint32_t)qhat;
+  }
+  unsigned __int128 w = 0;
+#pragma unroll
+  for (int j = M; j >= 0; --j) w = (w << 32) | q[j];
+  return w;
+}
+
+// floor(B^(t0+2) / V) for the top t0 = min(k1, 4) limbs V of v (k1 >= 2):
+// at most B^3 (97 bits)
+__device__ inline unsigned __int128 seed_inverse(const uint32_t* v, int k1) {
+  if (k1 >= 4) return seed_div<4>(v, k1);
+  if (k1 == 3) return seed_div<3>(v, k1);
+  return seed_div<2>(v, k1);
 }
 
 // ---- the division of one instance ----------------------------------------------
@@ -534,16 +623,23 @@ __device__ inline int shifted_inverse(const uint32_t* v, int k1, int h, Bufs& bf
     // limbs of |e| add less than w B^sd <= B^(c-m-1) to Y, so dropping them
     // moves that quotient by at most one unit (inside the error bound)
     const int sd = max(0, min(le - 1, c - m - 1 - lw));
-    wg_mul(bf.T, bf.W, lw, bf.E + sd, le - sd, smem, -1, adjust);
-    const int ly = lw + le - sd;
     const int sy = c - m - sd;           // Y / B^sy
+    // only the limbs from sy up are needed: a high product, which may come
+    // out one unit low (inside the error bound as well)
+    const bool exact = wg_mul(bf.T, bf.W, lw, bf.E + sd, le - sd, smem, -1, adjust, sy);
+    const int ly = lw + le - sd;
     // negative branch: the ceiling takes one more unit unless the dropped
-    // limbs Y[0 .. sy) are all zero (nullUpToInd)
+    // limbs Y[0 .. sy) are all zero (nullUpToInd); when the high product left
+    // them out it always takes it (one unit more at most)
     uint32_t cin = 0u;
     if (neg) {
-      int nz = 0;
-      for (int j = threadIdx.x; j < min(sy, ly); j += blockDim.x) nz |= bf.T[j] != 0u;
-      cin = __syncthreads_or(nz) ? 1u : 0u;
+      if (exact) {
+        int nz = 0;
+        for (int j = threadIdx.x; j < min(sy, ly); j += blockDim.x) nz |= bf.T[j] != 0u;
+        cin = __syncthreads_or(nz) ? 1u : 0u;
+      } else {
+        cin = 1u;
+      }
     }
     const int lnew = lw + m + 1;
     auto X = [&](int j) -> uint32_t { return (j >= m && j - m < lw) ? bf.W[j - m] : 0u; };
@@ -574,7 +670,13 @@ __device__ inline int wg_divmod(uint32_t* q, int nq, uint32_t* r, int nr, const 
                                 bool inverse_only, int h_inv, int64_t* adjust) {
   if (threadIdx.x == 0) sh->failed = 0u;
   __syncthreads();
-  const int k1 = wg_prec(v, nv, sh);
+  int k1, hu;
+  if (inverse_only) {
+    k1 = wg_prec(v, nv, sh);
+    hu = h_inv;
+  } else {
+    wg_prec2(v, nv, u, nu, sh, &k1, &hu);
+  }
   if (k1 == 0) {
     if (!inverse_only) {
       wg_fill(q, nq, 0u);
@@ -584,7 +686,7 @@ __device__ inline int wg_divmod(uint32_t* q, int nq, uint32_t* r, int nr, const 
     }
     return BIGINT_DIVZERO;
   }
-  const int h = inverse_only ? h_inv : wg_prec(u, nu, sh);
+  const int h = hu;
   if (!inverse_only && h < k1) {  // u < v
     wg_fill(q, nq, 0u);
     wg_shr_copy(r, nr, u, nu, 0);
@@ -619,19 +721,20 @@ __device__ inline int wg_divmod(uint32_t* q, int nq, uint32_t* r, int nr, const 
     return sh->failed ? BIGINT_DIV_FAILED : BIGINT_DIV_OK;
   }
   // q~ = floor(u w / B^h), from the top limbs of u only: the low su limbs add
-  // less than B^(su+lw) <= B^(h-1) to u w, so they move q~ by at most one unit
+  // less than B^(su+lw) <= B^(h-1) to u w, so they move q~ by at most one
+  // unit; a high product (limbs from h - su up) takes at most one more
   const int su = max(0, h - 1 - lw);
-  wg_mul(bf.T, u + su, h - su, bf.W, lw, smem, -1, adjust);
+  wg_mul(bf.T, u + su, h - su, bf.W, lw, smem, -1, adjust, h - su);
   const uint32_t* qt = bf.T + (h - su);              // q~: lw limbs
   const int lq = max(wg_prec(qt, lw, sh), 1);
-  // r~ = u - q~ v; |r~| < 4 v < B^(k1+1), so r~ mod B^(k1+2) holds it with
+  // r~ = u - q~ v; |r~| < 8 v < B^(k1+1), so r~ mod B^(k1+2) holds it with
   // its sign in the top limb
   const int lr = k1 + 2;
   wg_mul(bf.U2, qt, lq, v, k1, smem, lr, adjust);
   wg_arith<true>(bf.E, lr, u, h, bf.U2, min(lr, lq + k1), sh);
   // corrections: while r~ < 0, r~ += v (q~ - 1); while r~ >= v, r~ -= v (q~ + 1)
   // (each loop is bounded; leaving one at its bound marks the division failed,
-  // which the error analysis rules out: the model and tests see at most 2)
+  // which the error analysis rules out: at most 4 corrections are possible)
   int dq = 0;
   bool done_neg = false, done_pos = false;
   for (int rounds = 0; rounds < 8; ++rounds) {

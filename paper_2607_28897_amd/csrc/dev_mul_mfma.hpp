@@ -640,18 +640,35 @@ __device__ __forceinline__ void run_band(int band, const Lds& s, const Geo& g, u
     }
 }
 
+// First band of a product whose limbs below nlo are not needed: the strips
+// of the bands before it lie entirely below limb nlo - 2.  (The part of the
+// product they hold is below 2^34 B^(first strip's limb) <= B^nlo, so leaving
+// it out lowers floor(a b / B^nlo) by at most one.)
+template <int DW>
+__host__ __device__ inline int high_band(int nlo, int P) {
+  return nlo > 2 ? ((nlo - 2) / strip_limbs<DW>()) / P : 0;
+}
+
 // out[0 .. nout) = a * b mod B^nout for one instance (whole work-group),
-// digits of DW bits; nout < 0 means the whole na+nb limbs.  With coef !=
-// nullptr (7-bit digits only, whole product) the raw coefficients c_k
-// (k < Na+Nb-1) are written instead.
+// digits of DW bits; nout < 0 means the whole na+nb limbs.  nlo > 0 asks
+// only for the limbs from nlo up: the bands below high_band(nlo) are not
+// computed, out[nlo ..) then holds floor(a b / B^nlo) mod B^(nout-nlo) or
+// one less, and the limbs below nlo are left as they were or wrong.  With
+// coef != nullptr (7-bit digits only, whole product) the raw coefficients
+// c_k (k < Na+Nb-1) are written instead.
 template <int DW, int P>
 __device__ __forceinline__ void wg_mul_mfma(uint32_t* out, int32_t* coef, const uint32_t* __restrict__ a, int na,
-                            const uint32_t* __restrict__ b, int nb, char* smem, int nout = -1) {
+                            const uint32_t* __restrict__ b, int nb, char* smem, int nout = -1,
+                            int nlo = 0) {
   static_assert(DW == 7 || DW == 8, "digit width");
   constexpr int kStripLimbs = strip_limbs<DW>();
   const Geo g = make_geo<DW>(na, nb, coef ? -1 : nout);
   const Lds s = carve(smem, g, P);
-  const int NB = (g.W + P - 1) / P;
+  const int NBall = (g.W + P - 1) / P;
+  // bands [band_lo, NBall) are computed; strips from w_first up
+  const int band_lo = coef ? 0 : min(high_band<DW>(nlo, P), NBall);
+  const int w_first = band_lo * P;
+  const int NB = NBall - band_lo;
 
   stage<DW>(s, g, a, b);
   if constexpr (DW == 8) {
@@ -662,7 +679,7 @@ __device__ __forceinline__ void wg_mul_mfma(uint32_t* out, int32_t* coef, const 
   }
   // band order: most expensive first (rank sort by cost; the costs sit in
   // the wave scratch area, which holds 256 ints per wave >= NB)
-  for (int t = threadIdx.x; t < NB; t += blockDim.x) s.scr[t] = band_cost(g, t, P);
+  for (int t = threadIdx.x; t < NB; t += blockDim.x) s.scr[t] = band_cost(g, band_lo + t, P);
   if (threadIdx.x == 0) s.misc[0] = 0;
   __syncthreads();
   for (int t = threadIdx.x; t < NB; t += blockDim.x) {
@@ -681,7 +698,7 @@ __device__ __forceinline__ void wg_mul_mfma(uint32_t* out, int32_t* coef, const 
     if (lane_id() == 0) t = atomicAdd(&s.misc[0], 1u);
     t = __builtin_amdgcn_readfirstlane(t);
     if ((int)t >= NB) break;
-    const int band = __builtin_amdgcn_readfirstlane((int)s.order[t]);
+    const int band = band_lo + __builtin_amdgcn_readfirstlane((int)s.order[t]);
     run_band<DW, P>(band, s, g, out, coef);
   }
   __syncthreads();
@@ -694,13 +711,13 @@ __device__ __forceinline__ void wg_mul_mfma(uint32_t* out, int32_t* coef, const 
     // 0..1 plus C_{w'-1} are all ones and so is its tail.
     const uint64_t kC = (1ull << 63) - 1;
     uint32_t carry = 0u;
-    for (int base = 0; base < g.W; base += blockDim.x) {
+    for (int base = w_first; base < g.W; base += blockDim.x) {
       const int w = base + threadIdx.x;
       const bool valid = w < g.W;
       const int j0 = kStripLimbs * (valid ? w : 0);
       const uint32_t l0 = (valid && j0 < g.nout) ? out[j0] : 0u;
       const uint32_t l1 = (valid && j0 + 1 < g.nout) ? out[j0 + 1] : 0u;
-      const uint64_t d = (valid && w > 0) ? (s.carry[w - 1] & kC) : 0ull;
+      const uint64_t d = (valid && w > w_first) ? (s.carry[w - 1] & kC) : 0ull;
       const bool ones = valid && (s.carry[w] >> 63);
       const uint64_t x0 = ((uint64_t)l1 << 32) | l0;
       const uint64_t x = x0 + d;

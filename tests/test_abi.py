@@ -61,7 +61,7 @@ def test_host_side_argument_checks(bi):
     assert L.bigint_mul(ctypes.c_void_p(0x100000), p, 20000, q, 20000, 1,
                         bi.MUL_MFMA, None) == EUNS
     assert L.bigint_divmod(None, q, None, p, 4, p, 4, 1, None) == EINVAL
-    assert L.bigint_divmod(ctypes.c_void_p(0x100000), ctypes.c_void_p(0x200000), None, p, 9000,
+    assert L.bigint_divmod(ctypes.c_void_p(0x100000), ctypes.c_void_p(0x200000), None, p, 16385,
                            q, 4, 1, None) == EUNS
     assert L.bigint_shinv(ctypes.c_void_p(0x100000), p, 5, 4, 1, None) == EINVAL   # h < nv
     assert L.bigint_set_mfma_config(5, 0, 0) == EINVAL

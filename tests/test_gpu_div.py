@@ -288,3 +288,59 @@ def test_negative_branch_steps(bi, orc):
             assert cnt[i, 0] >= 2 and cnt[i, 1] >= 1, (i, kinds[i], cnt[i])
     plan.close()
 
+
+
+@pytest.mark.parametrize("nu,nv", [(16384, 8192), (16384, 2), (16384, 16000), (16384, 5000),
+                                   (16383, 9)])
+def test_dividends_2e19(bi, orc, nu, nv):
+    """2^19-bit dividends (the top of the 2^15..2^19-bit range): random,
+    all-ones and divisor-multiple dividends, checked by u = q v + r,
+    0 <= r < v and against the oracle."""
+    g = np.random.default_rng(nu + nv)
+    u = rand_limbs(g, 3, nu)
+    v = rand_limbs(g, 3, nv)
+    v[:, -1] |= 1
+    u[1] = 0xFFFFFFFF
+    q, r, st = bi.divmod(dev(u), dev(v))
+    q, r, st = host(q), host(r), st.cpu().numpy()
+    for i in range(3):
+        U, V, Q, R = _to_int(u[i]), _to_int(v[i]), _to_int(q[i]), _to_int(r[i])
+        assert st[i] == 0 and U == Q * V + R and 0 <= R < V, i
+        wq, wr, _ = orc.divmod1(u[i], v[i])
+        assert np.array_equal(q[i], wq) and np.array_equal(r[i], wr), i
+
+
+def test_ragged_with_2e19_dividends(bi, orc):
+    """A ragged plan whose largest dividends have 16384 limbs (one
+    work-group per CU for the whole launch), mixed with small divisions."""
+    import torch
+    g = np.random.default_rng(5)
+    nu = np.array([16384, 3, 16384, 700, 9000, 40], np.int64)
+    nv = np.array([8192, 2, 3, 350, 8999, 39], np.int64)
+    us = [rand_limbs(g, 1, n)[0] for n in nu]
+    vs = [rand_limbs(g, 1, n)[0] for n in nv]
+    for v in vs:
+        v[-1] |= 1
+    u_off = np.concatenate([[0], np.cumsum(nu)]).astype(np.int64)
+    v_off = np.concatenate([[0], np.cumsum(nv)]).astype(np.int64)
+    plan = bi.DivPlan(nu, nv)
+    q, r, st = plan(dev(np.concatenate(us)), torch.from_numpy(u_off).cuda(),
+                    dev(np.concatenate(vs)), torch.from_numpy(v_off).cuda())
+    q, r, st = host(q), host(r), st.cpu().numpy()
+    for i in range(nu.size):
+        wq, wr, _ = orc.divmod1(us[i], vs[i])
+        assert st[i] == 0, i
+        assert np.array_equal(q[u_off[i]:u_off[i + 1]], wq), i
+        assert np.array_equal(r[v_off[i]:v_off[i + 1]], wr), i
+    plan.close()
+
+
+def test_shifted_inverse_2e19(bi, orc):
+    g = np.random.default_rng(19)
+    for nv, h in ((8192, 16384), (3, 16384)):
+        v = rand_limbs(g, 2, nv)
+        v[:, -1] |= 1
+        w = host(bi.shinv(dev(v), h))
+        for i in range(2):
+            want, _ = orc.shinv1(v[i], h)
+            assert np.array_equal(w[i], want), (nv, h, i)

@@ -59,6 +59,6 @@ def test_noalloc_argument_checks(bi):
     L = bi.lib()
     assert L.bigint_divmod_noalloc(None, None, None, None, 1, None, 1, 1, None) == bi.EINVAL
     x = ctypes.c_void_p(16)
-    assert L.bigint_divmod_noalloc(x, ctypes.c_void_p(1 << 20), None, ctypes.c_void_p(2 << 20), 8193,
+    assert L.bigint_divmod_noalloc(x, ctypes.c_void_p(1 << 20), None, ctypes.c_void_p(2 << 20), 16385,
                                    ctypes.c_void_p(3 << 20), 5, 1, None) == bi.EUNSUPPORTED
     assert L.bigint_divmod_noalloc(x, x, None, x, 5, x, 5, -1, None) == bi.EINVAL
