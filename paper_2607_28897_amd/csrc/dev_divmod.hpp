@@ -39,6 +39,7 @@ struct Shared {
   uint32_t red[4];      // reductions
   uint32_t scan[32];    // carry-scan scratch
   uint32_t w0[4];       // initial estimate (one thread)
+  int early_cur, early_lw;  // scale and length of w after the one-wave steps
   uint32_t failed;      // a bounded loop hit its bound, or an estimate left its error bound (never expected)
 };
 
@@ -114,6 +115,18 @@ __device__ __forceinline__ void wg_prec2(const uint32_t* x, int nx, const uint32
     *px = wg_prec(x, nx, sh);
     *py = wg_prec(y, ny, sh);
     return;
+  }
+  // the usual case first: a nonzero limb among the top 64 of each settles
+  // its precision with one load per lane (every wave the same ballots)
+  {
+    const int i = lane_id();
+    const uint32_t a = nx > i ? x[nx - 1 - i] : 0u, b = ny > i ? y[ny - 1 - i] : 0u;
+    const uint64_t ma = __ballot(a != 0u), mb = __ballot(b != 0u);
+    if (ma != 0ull && mb != 0ull) {
+      *px = nx - (__ffsll((long long)ma) - 1);
+      *py = ny - (__ffsll((long long)mb) - 1);
+      return;
+    }
   }
   if (threadIdx.x == 0) { sh->red[0] = 0; sh->red[1] = 0; }
   __syncthreads();
@@ -250,6 +263,46 @@ constexpr int kSmallMul = 64;  // operands up to this many limbs: column-sum pro
 // LDS bytes of the column-sum product (both operands staged)
 constexpr size_t kSmallMulLds = (size_t)2 * kSmallMul * 4;
 
+// Lane l holds the sums of product columns k = l and l + 64 as
+// C_k = s_k + 2^64 c_k.  Writes limbs [0, n) (n <= 128) of sum_k C_k B^k to
+// dst: limb k receives lo32(s_k) + hi32(s_(k-1)) + c_(k-2) (< 3 * 2^32), whose
+// overflow (at most 2) goes one limb up through two wave-level carry scans
+// (limbs 0..63, then 64..127).
+__device__ __forceinline__ void wave_cols_to_limbs(const uint64_t (&s)[2], const uint32_t (&c)[2],
+                                                   uint32_t* dst, int n) {
+  const int l = lane_id();
+  // neighbours: column k-1 and k-2 (lane l-1 / l-2 of the same half, or of
+  // the lower half across the lane-0 boundary)
+  const int l1 = (l + 63) & 63, l2 = (l + 62) & 63;
+  const uint32_t sh0 = __shfl((uint32_t)(s[0] >> 32), l1), sh1 = __shfl((uint32_t)(s[1] >> 32), l1);
+  const uint32_t c0 = __shfl(c[0], l2), c1 = __shfl(c[1], l2);
+  uint32_t tl[2], th[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int k = l + 64 * h;
+    const uint32_t hi1 = k >= 1 ? (l >= 1 ? (h ? sh1 : sh0) : sh0) : 0u;
+    const uint32_t cc2 = k >= 2 ? (l >= 2 ? (h ? c1 : c0) : c0) : 0u;
+    const uint64_t t = (uint64_t)(uint32_t)s[h] + hi1 + cc2;
+    tl[h] = (uint32_t)t;
+    th[h] = (uint32_t)(t >> 32);
+  }
+  // limb k = tl_k + th_(k-1), carries rippling up
+  const uint32_t t0 = __shfl(th[0], l1), t1 = __shfl(th[1], l1);
+  uint32_t carry = 0u;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int k = l + 64 * h;
+    const uint32_t y = k >= 1 ? (l >= 1 ? (h ? t1 : t0) : t0) : 0u;
+    const uint32_t x = tl[h];
+    const uint32_t r = x + y;
+    const bool g = r < x, p = r == 0xffffffffu;
+    const WaveCarry w = wave_carry_masks(g, p);
+    const uint32_t ci = wave_carry_in(w, carry);
+    carry = wave_carry_out(w, carry);
+    if (k < n) dst[k] = r + ci;
+  }
+}
+
 // dst[0 .. n) = a * b mod B^n with n = na + nb (nout < 0) or min(nout, na + nb),
 // for 1 <= na, nb <= kSmallMul, on wave 0 alone (the other waves wait at the
 // closing barrier).  The MFMA multiply's fixed steps (digit staging, prefix
@@ -290,36 +343,7 @@ __device__ inline void wg_mul_small(uint32_t* dst, const uint32_t* a, int na, co
       s[h] = sum;
       c[h] = cnt;
     }
-    // neighbours: column k-1 and k-2 (lane l-1 / l-2 of the same half, or of
-    // the lower half across the lane-0 boundary)
-    const int l1 = (l + 63) & 63, l2 = (l + 62) & 63;
-    const uint32_t sh0 = __shfl((uint32_t)(s[0] >> 32), l1), sh1 = __shfl((uint32_t)(s[1] >> 32), l1);
-    const uint32_t c0 = __shfl(c[0], l2), c1 = __shfl(c[1], l2);
-    uint32_t tl[2], th[2];
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int k = l + 64 * h;
-      const uint32_t hi1 = k >= 1 ? (l >= 1 ? (h ? sh1 : sh0) : sh0) : 0u;
-      const uint32_t cc2 = k >= 2 ? (l >= 2 ? (h ? c1 : c0) : c0) : 0u;
-      const uint64_t t = (uint64_t)(uint32_t)s[h] + hi1 + cc2;
-      tl[h] = (uint32_t)t;
-      th[h] = (uint32_t)(t >> 32);
-    }
-    // limb k = tl_k + th_(k-1), carries rippling up
-    const uint32_t t0 = __shfl(th[0], l1), t1 = __shfl(th[1], l1);
-    uint32_t carry = 0u;
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int k = l + 64 * h;
-      const uint32_t y = k >= 1 ? (l >= 1 ? (h ? t1 : t0) : t0) : 0u;
-      const uint32_t x = tl[h];
-      const uint32_t r = x + y;
-      const bool g = r < x, p = r == 0xffffffffu;
-      const WaveCarry w = wave_carry_masks(g, p);
-      const uint32_t ci = wave_carry_in(w, carry);
-      carry = wave_carry_out(w, carry);
-      if (k < n) dst[k] = r + ci;
-    }
+    wave_cols_to_limbs(s, c, dst, n);
   }
   __syncthreads();
 }
@@ -360,6 +384,157 @@ __device__ __noinline__ bool wg_mul(uint32_t* dst, const uint32_t* a, int na, co
   if (adjust) adjust[3] += mfma_pairs(na, nb, nout, nlo);
   mfma::wg_mul_mfma<kDW, kP>(dst, nullptr, a, na, b, nb, smem, nout, nlo);
   return mfma::high_band<kDW>(nlo, kP) == 0;
+}
+
+// ---- the first Newton steps on one wave ---------------------------------------------
+// While every operand of a step fits in 128 limbs (two per lane), wave 0
+// runs the step alone out of LDS: column-sum products, ballot carry scans,
+// no work-group barrier and no global round trip, while the other waves
+// wait at one barrier.  (On the whole work-group each such step took
+// 10-12 us, nearly all of it the fixed latency of a dozen passes and
+// barriers.)
+constexpr int kWaveLimbs = 128;
+constexpr int kEarlyArr = kWaveLimbs + 8;                  // limbs per LDS array
+constexpr size_t kEarlyLds = (size_t)5 * kEarlyArr * 4;   // w, new w, e, w e, V
+
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// dst[0 .. n) = a * b mod B^n for n <= 128, operands and result in LDS (dst
+// must not overlap them); lane l forms columns l and l + 64
+__device__ inline void wave_mul_lds(uint32_t* dst, const uint32_t* sa, int na, const uint32_t* sb,
+                                    int nb, int n) {
+  const int l = lane_id();
+  uint64_t s[2];
+  uint32_t c[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int k = l + 64 * h;
+    uint64_t sum = 0;
+    uint32_t cnt = 0;
+    const int lo = max(0, k - nb + 1), hi = min(k, na - 1);
+    for (int i = lo; i <= hi; ++i) {
+      const uint64_t t = (uint64_t)sa[i] * sb[k - i] + sum;
+      cnt += t < sum;
+      sum = t;
+    }
+    s[h] = sum;
+    c[h] = cnt;
+  }
+  wave_cols_to_limbs(s, c, dst, n);
+  wave_lds_sync();
+}
+
+// dst[j] = X(j) + Y(j) (+ cin) or X(j) - Y(j) (- cin) for j < n <= 128 on
+// one wave (every X, Y read before dst is written); returns the number of
+// significant limbs of the result
+template <bool SUB, class FX, class FY>
+__device__ inline int wave_addsub128(uint32_t* dst, int n, FX X, FY Y, uint32_t cin) {
+  const int l = lane_id();
+  uint32_t xs[2], ys[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int j = l + 64 * h;
+    xs[h] = j < n ? X(j) : 0u;
+    ys[h] = j < n ? Y(j) : 0u;
+  }
+  wave_lds_sync();
+  uint32_t carry = cin;
+  int top = 0;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int j = l + 64 * h;
+    const bool in = j < n;
+    const uint32_t x = xs[h], y = ys[h];
+    const uint32_t r = SUB ? x - y : x + y;
+    const bool g = in && (SUB ? x < y : r < x);
+    const bool p = in && (SUB ? x == y : r == 0xffffffffu);
+    const WaveCarry w = wave_carry_masks(g, p);
+    const uint32_t ci = wave_carry_in(w, carry);
+    carry = wave_carry_out(w, carry);
+    const uint32_t res = SUB ? r - ci : r + ci;
+    if (in) dst[j] = res;
+    const uint64_t nz = __ballot(in && res != 0u);
+    if (nz) top = 64 * h + 64 - __clzll(nz);
+  }
+  wave_lds_sync();
+  return top;
+}
+
+// The Newton steps of shifted_inverse (same formulas, same products, all
+// exact) from scale cur while each fits one wave; wave 0 only.  w: lw limbs
+// in global memory on entry and on return; smem: kEarlyLds bytes of LDS.
+// Updates cur and lw; failed is set if an estimate leaves its error bound.
+__device__ inline void wave_newton_early(const uint32_t* v, int k1, int h, uint32_t* W, char* smem,
+                                         int64_t* adjust, int& cur, int& lw, bool& failed) {
+  uint32_t* sW = reinterpret_cast<uint32_t*>(smem);
+  uint32_t* sU = sW + kEarlyArr;
+  uint32_t* sE = sU + kEarlyArr;
+  uint32_t* sT = sE + kEarlyArr;
+  uint32_t* sV = sT + kEarlyArr;
+  const int l = lane_id();
+#pragma unroll
+  for (int h2 = 0; h2 < 2; ++h2) {
+    const int j = l + 64 * h2;
+    sW[j] = j < lw ? W[j] : 0u;
+  }
+  wave_lds_sync();
+  while (cur < h) {
+    const int m = min(h - cur, cur - k1 - 1);
+    const int t = min(k1, cur + m - k1 + 1 + kGuard);
+    const int sdrop = k1 - t;
+    const int c = cur - sdrop;
+    const int le = t + 2;
+    const int sd = max(0, min(le - 1, c - m - 1 - lw));
+    const int ly = lw + le - sd;
+    const int lnew = lw + m + 1;
+    if (le > kWaveLimbs || ly > kWaveLimbs || lnew > kWaveLimbs) break;
+#pragma unroll
+    for (int h2 = 0; h2 < 2; ++h2) {
+      const int j = l + 64 * h2;
+      if (j < t) sV[j] = v[sdrop + j];
+    }
+    wave_lds_sync();
+    // powDiff from the low product, as on the work-group
+    wave_mul_lds(sE, sV, t, sW, lw, le);
+    const uint32_t top = __builtin_amdgcn_readfirstlane(sE[le - 1]);
+    const bool neg = top == 0u;
+    if (!neg) {
+      if (top != 0xffffffffu) { failed = true; break; }
+      wave_addsub128<true>(sE, le, [](int) -> uint32_t { return 0u; },
+                           [&](int j) -> uint32_t { return sE[j]; }, 0u);
+    }
+    if (adjust) {
+      adjust[0] += 1;
+      adjust[1] += neg ? 1 : 0;
+    }
+    // step (the whole product w |e|: the ceiling's dropped-limb test is exact)
+    wave_mul_lds(sT, sW, lw, sE + sd, le - sd, ly);
+    const int sy = c - m - sd;
+    uint32_t cin = 0u;
+    if (neg) {
+      const int nlow = min(sy, ly);
+      const bool nz = (l < nlow && sT[l] != 0u) || (l + 64 < nlow && sT[l + 64] != 0u);
+      cin = __ballot(nz) != 0ull ? 1u : 0u;
+    }
+    auto X = [&](int j) -> uint32_t { return (j >= m && j - m < lw) ? sW[j - m] : 0u; };
+    auto Y = [&](int j) -> uint32_t { return j + sy < ly ? sT[j + sy] : 0u; };
+    const int top2 = neg ? wave_addsub128<true>(sU, lnew, X, Y, cin)
+                         : wave_addsub128<false>(sU, lnew, X, Y, 0u);
+    uint32_t* tmp = sW;
+    sW = sU;
+    sU = tmp;
+    lw = max(top2, 1);
+    cur += m;
+  }
+#pragma unroll
+  for (int h2 = 0; h2 < 2; ++h2) {
+    const int j = l + 64 * h2;
+    if (j < lw) W[j] = sW[j];
+  }
 }
 
 // ---- one-lane helper for the starting value ------------------------------------
@@ -586,6 +761,23 @@ __device__ inline int shifted_inverse(const uint32_t* v, int k1, int h, Bufs& bf
   __syncthreads();
   cur -= d0;
   int lw = max(wg_prec(bf.W, 4, sh), 1);
+  // the first steps on wave 0 alone (see wave_newton_early)
+  if (cur < h) {
+    if (wave_id() == 0) {
+      int c2 = cur, l2 = lw;
+      bool f = false;
+      wave_newton_early(v, k1, h, bf.W, smem, adjust, c2, l2, f);
+      if (lane_id() == 0) {
+        sh->early_cur = c2;
+        sh->early_lw = l2;
+        if (f) sh->failed = 1u;
+      }
+    }
+    __syncthreads();
+    cur = sh->early_cur;
+    lw = sh->early_lw;
+    if (sh->failed) return lw;
+  }
   // Newton steps: w ~ B^cur / v carries p = cur - k1 limbs of precision, and
   // a step to p' = p + m only needs the divisor to p' + kGuard limbs: with V
   // the top t of them (v = V B^s + low), w also approximates B^(cur-s) / V
@@ -750,11 +942,11 @@ __device__ inline int wg_divmod(uint32_t* q, int nq, uint32_t* r, int nr, const 
   }
   if (!done_pos && threadIdx.x == 0) sh->failed = 1u;
   if (adjust) adjust[2] += dq < 0 ? -dq : dq;
-  // q = q~ + dq over all nq limbs, r = r~ over nr limbs
+  // q = q~ + dq over all nq limbs and r = r~ over nr limbs, in one pass
+  // (r's copy rides along with the addition's first round)
+  for (int i = threadIdx.x; i < nr; i += blockDim.x) r[i] = i < k1 ? bf.E[i] : 0u;
   if (dq >= 0) wg_arith1<false>(q, nq, qt, lq, (uint32_t)dq, sh);
   else wg_arith1<true>(q, nq, qt, lq, (uint32_t)(-dq), sh);
-  wg_shr_copy(r, nr, bf.E, k1, 0);
-  __syncthreads();
   return sh->failed ? BIGINT_DIV_FAILED : BIGINT_DIV_OK;
 }
 

@@ -78,9 +78,9 @@ size_t div_lds_bytes(int cap_u, int cap_v) {
   // the largest product of a division has two factors of at most cap_u + 8 limbs
   const int m = cap_u + 8;
   (void)cap_v;
-  // (and at least what the small-operand product needs)
+  // (and at least what the small-operand product and the one-wave steps need)
   return std::max<size_t>(mfma::lds_bytes<div::kDW>(m, m, div_threads(cap_u) / 64, div::kP),
-                          div::kSmallMulLds);
+                          std::max(div::kSmallMulLds, div::kEarlyLds));
 }
 
 // Work-groups that fit one CU: the kernel is built for 4 waves per SIMD (16
