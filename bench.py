@@ -404,7 +404,8 @@ def peak_mode(torch, bi):
     """Achievable int8 MFMA rate with no memory traffic (v_mfma_i32_16x16x64_i8,
     8 independent accumulators per wave, 64 per loop round), for 4..32 waves
     per CU, with constant operands and with operands whose bits change every
-    round (as random digits do); then the rate of the plain kernel's
+    round (as random digits do), and the same with v_mfma_i32_32x32x32_i8
+    (4 accumulators, 32 per round, the same work); then the rate of the plain kernel's
     v_mad_u64_u32 (8 independent chains per lane), in 10^12 operations/s."""
     import ctypes
     L = bi.lib()
@@ -412,7 +413,7 @@ def peak_mode(torch, bi):
     s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
     ncu = torch.cuda.get_device_properties(0).multi_processor_count
     res = {}
-    for toggle in (0, 1):
+    for toggle in (0, 1, 3):
         for per_cu in (1, 2, 4, 8):
             blocks, iters = ncu * per_cu, 1000
             L.bigint_diag_mfma_rate(ctypes.c_void_p(out.data_ptr()), blocks, 20, toggle, s)
@@ -426,7 +427,8 @@ def peak_mode(torch, bi):
                 raise bi.BigIntError(rc, "bigint_diag_mfma_rate")
             ms = e0.elapsed_time(e1)
             macs = blocks * 4 * iters * 64 * 16384
-            key = ("toggling" if toggle else "constant") + f"_{4 * per_cu}_waves_per_cu_TOPs"
+            key = ("toggling" if toggle & 1 else "constant") + ("_32x32x32" if toggle & 2 else "") + \
+                f"_{4 * per_cu}_waves_per_cu_TOPs"
             res[key] = round(2 * macs / ms / 1e9, 1)
     # the plain kernel's inner operation: 32x32-bit products added to 64 bits
     out64 = torch.empty(8192 * 256, dtype=torch.int64, device="cuda")

@@ -252,7 +252,9 @@ int bigint_divmod_ragged(uint32_t* q, const int64_t* q_off, uint32_t* r,
 
 /* ---- autotuning ----------------------------------------------------------------
  * Times every candidate tile configuration of the MFMA-split multiply on the
- * current device for each size bin (2^12..2^19 bits), keeps the fastest and
+ * current device for each size bin (2^12..2^19 bits): strips per band,
+ * waves per work-group, digit width and MFMA tile (16x16x64 or 32x32x32,
+ * the "chunk width"); keeps the fastest and
  * writes the table as JSON to `cache_path` (host path; NULL = do not write).
  * Later plans use the table.  bigint_autotune_load reads such a file (a
  * NULL path restores the built-in table).  All candidates produce identical
@@ -299,8 +301,11 @@ int bigint_diag_divmod_ragged(int64_t* counts, uint32_t* q, const int64_t* q_off
 /* Register-only int8 MFMA rate probe: `blocks` work-groups of 4 waves, each
  * wave issuing 64 v_mfma_i32_16x16x64_i8 per iteration (8 independent
  * accumulators, 16384 multiply-accumulates each) for `iters` iterations, no
- * memory traffic.  toggle != 0 flips the operand bit patterns between rounds
- * of 8 (random data draws more power than constant data).
+ * memory traffic.  toggle bit 0 flips the operand bit patterns between
+ * rounds of 8 (random data draws more power than constant data); toggle
+ * bit 1 runs v_mfma_i32_32x32x32_i8 instead (4 accumulators per wave, 32
+ * MFMAs of 32,768 multiply-accumulates per iteration: the same work per
+ * iteration).
  * scratch: blocks*256 int32 (results kept so the work is not removed).
  * Time it with events on `stream` to get the achievable MFMA rate. */
 int bigint_diag_mfma_rate(int32_t* scratch, int64_t blocks, int64_t iters, int toggle,
@@ -315,7 +320,8 @@ int bigint_diag_mfma_rate(int32_t* scratch, int64_t blocks, int64_t iters, int t
 int bigint_diag_mad_rate(uint64_t* scratch, int64_t blocks, int64_t iters, void* stream);
 
 /* Tile parameters of the MFMA multiply used by the next calls on this thread
- * (strips per wave band: 4, 8 or 16; waves per work-group: 4 or 8, or 1 for
+ * (strips per wave band: 4, 8 or 16, or 32 with 32x32 tiles; waves per
+ * work-group: 4 or 8, or 1 for
  * one wave per instance with four instances per work-group -- the paper's
  * ipb instances per block -- which bigint_mul and bigint_mullo use with
  * 8-bit digits when na + nb <= 4096 limbs and otherwise treat as 4; digit
@@ -323,6 +329,20 @@ int bigint_diag_mad_rate(uint64_t* scratch, int64_t blocks, int64_t iters, void*
  * table only.  Exists so tests can check that every configuration gives the
  * same bytes; other values return BIGINT_EINVAL. */
 int bigint_set_mfma_config(int strips_per_band, int waves, int digit_bits);
+
+/* MFMA tile of the next calls on this thread: 16 (v_mfma_i32_16x16x64_i8,
+ * the default) or 32 (v_mfma_i32_32x32x32_i8: a 32x32 result tile of 1024
+ * digit coefficients, four strips, with twice the multiply-accumulates per
+ * instruction for the same operand bytes); 0 keeps the tuned choice.  The
+ * 32x32 tile serves bigint_mul and bigint_mullo with 8-bit digits and 8 or
+ * 16 strips per band on a work-group per instance, where its LDS fits (its
+ * zero padding is wider: 18,432-limb operands on 8 waves do not); every other
+ * configuration (and the ragged, Karatsuba, Poly and division kernels) runs
+ * 16x16 tiles.  Both tiles give the same bytes.  Other values return
+ * BIGINT_EINVAL.  bigint_mfma_tile returns the tile bigint_mul would use for
+ * an na x nb product on this thread (16 or 32), or a negative status. */
+int bigint_set_mfma_tile(int tile);
+int bigint_mfma_tile(int64_t na, int64_t nb);
 
 /* The tile configuration bigint_mul would use on this thread for an na x nb
  * product (tuned table, then this thread's overrides), written to the three

@@ -20,7 +20,8 @@ import os
 
 __all__ = [
     "lib", "add", "sub", "mul", "divmod", "digits7", "conv7", "shinv",
-    "MulPlan", "DivPlan", "autotune", "autotune_load", "set_mfma_config", "mfma_config", "BigIntError",
+    "MulPlan", "DivPlan", "autotune", "autotune_load", "set_mfma_config", "mfma_config",
+    "set_mfma_tile", "mfma_tile", "BigIntError",
     "mullo", "add6", "poly",
     "MUL_AUTO", "MUL_PLAIN", "MUL_MFMA", "MUL_KARATSUBA",
 ]
@@ -88,6 +89,8 @@ def lib() -> ctypes.CDLL:
             "bigint_shinv": ([_vp, _vp, _i64, _i64, _i64, _vp], _int),
             "bigint_set_mfma_config": ([_int, _int, _int], _int),
             "bigint_mfma_config": ([_i64, _i64, _pint, _pint, _pint], _int),
+            "bigint_set_mfma_tile": ([_int], _int),
+            "bigint_mfma_tile": ([_i64, _i64], _int),
             "bigint_mullo": ([_vp, _vp, _vp, _i64, _i64, _vp], _int),
             "bigint_add6": ([_vp, _vp, _vp, _vp, _i64, _i64, _vp], _int),
             "bigint_poly": ([_vp, _vp, _vp, _i64, _i64, _vp], _int),
@@ -288,6 +291,19 @@ def poly(a, b):
     out = torch.empty_like(a)
     _check(lib().bigint_poly(_p(out), _p(a), _p(b), n, ba, _stream()), "bigint_poly")
     return _back(out, wd)
+
+
+def set_mfma_tile(tile: int = 0):
+    """MFMA tile of the next calls on this thread: 16, 32, or 0 (tuned)."""
+    _check(lib().bigint_set_mfma_tile(tile), "bigint_set_mfma_tile")
+
+
+def mfma_tile(na: int, nb: int) -> int:
+    """The MFMA tile (16 or 32) bigint_mul uses for an na x nb product."""
+    t = lib().bigint_mfma_tile(na, nb)
+    if t < 0:
+        raise BigIntError(t, "bigint_mfma_tile")
+    return t
 
 
 def mfma_config(na: int, nb: int):

@@ -15,7 +15,7 @@ namespace bi {
 static thread_local int t_last_hip = 0;
 void set_hip_error(hipError_t e) { t_last_hip = (int)e; }
 
-static thread_local int t_cfg_P = 0, t_cfg_waves = 0, t_cfg_dw = 0;
+static thread_local int t_cfg_P = 0, t_cfg_waves = 0, t_cfg_dw = 0, t_cfg_tile = 0;
 
 // Tile choice per size bin.  The built-in table is what bigint_autotune
 // picked on an MI355X; a table loaded with bigint_autotune_load (or produced
@@ -23,6 +23,7 @@ static thread_local int t_cfg_P = 0, t_cfg_waves = 0, t_cfg_dw = 0;
 struct TuneEntry {
   int max_limbs;  // bin upper bound (operand limbs)
   int P, waves, dw;
+  int tile = 16;  // MFMA tile (16 or 32)
 };
 static std::mutex g_tune_mu;
 // (waves 1: one wave per instance, four instances per work-group)
@@ -41,11 +42,22 @@ MfmaCfg default_mfma_cfg(int na, int nb) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     for (const auto& e : g_tune)
       if (n <= e.max_limbs) {
-        c = MfmaCfg{e.P, e.waves, e.dw};
+        c = MfmaCfg{e.P, e.waves, e.dw, e.tile};
         break;
       }
   }
   if (c.dw == 7 && mfma_lds(na, nb, c) > 163840) c.dw = 8;
+  return c;
+}
+
+// 32x32 tiles need 8-bit digits, whole tiles per band (8 or 16 strips), a
+// work-group of their own and room in LDS for their wider zero padding
+// (near 18,432 limbs with 8 waves it does not fit): otherwise 16x16 tiles
+static MfmaCfg valid_tile(MfmaCfg c, int na, int nb) {
+  if (c.tile == 32 && (c.dw != 8 || (c.P != 8 && c.P != 16 && c.P != 32) || c.waves == 1 ||
+                       mfma_lds(na, nb, c) > 163840))
+    c.tile = 16;
+  if (c.tile == 16 && c.P == 32) c.P = 16;   // 16x16 bands hold at most 16 strips
   return c;
 }
 
@@ -54,6 +66,7 @@ MfmaCfg default_mfma_cfg(int na, int nb) {
 static MfmaCfg ragged_mfma_cfg(int na, int nb) {
   MfmaCfg c = default_mfma_cfg(na, nb);
   if (c.waves == 1) c.waves = 4;
+  c.tile = 16;   // the ragged kernels run 16x16 tiles
   return c;
 }
 
@@ -62,7 +75,8 @@ MfmaCfg current_mfma_cfg(int na, int nb) {
   if (t_cfg_P) c.P = t_cfg_P;
   if (t_cfg_waves) c.waves = t_cfg_waves;
   if (t_cfg_dw) c.dw = t_cfg_dw;
-  return c;
+  if (t_cfg_tile) c.tile = t_cfg_tile;
+  return valid_tile(c, na, nb);
 }
 
 // One wave per instance pays only once the batch keeps every CU busy with
@@ -101,7 +115,7 @@ static MfmaCfg uniform_mfma_cfg(int na, int nb, int64_t batch, bool low) {
     if ((one || low) && t_cfg_P == 0) w.P = 4;
     if (mfma_lds(na, nb, w) <= 163840) c = w;
   }
-  return c;
+  return valid_tile(c, na, nb);
 }
 
 // CU count of the device current at the first call (one initialisation,
@@ -148,7 +162,7 @@ int bigint_last_hip_error(void) { return t_last_hip; }
 
 int bigint_set_mfma_config(int strips_per_band, int waves, int digit_bits) {
   if (strips_per_band != 0 && strips_per_band != 4 && strips_per_band != 8 &&
-      strips_per_band != 16)
+      strips_per_band != 16 && strips_per_band != 32)
     return BIGINT_EINVAL;
   if (waves != 0 && waves != 1 && waves != 4 && waves != 8) return BIGINT_EINVAL;
   if (digit_bits != 0 && digit_bits != 7 && digit_bits != 8) return BIGINT_EINVAL;
@@ -156,6 +170,18 @@ int bigint_set_mfma_config(int strips_per_band, int waves, int digit_bits) {
   t_cfg_waves = waves;
   t_cfg_dw = digit_bits;
   return BIGINT_OK;
+}
+
+int bigint_set_mfma_tile(int tile) {
+  if (tile != 0 && tile != 16 && tile != 32) return BIGINT_EINVAL;
+  t_cfg_tile = tile;
+  return BIGINT_OK;
+}
+
+int bigint_mfma_tile(int64_t na, int64_t nb) {
+  if (na <= 0 || nb <= 0) return BIGINT_EINVAL;
+  if (na > BIGINT_MFMA_MAX_LIMBS || nb > BIGINT_MFMA_MAX_LIMBS) return BIGINT_EUNSUPPORTED;
+  return current_mfma_cfg((int)na, (int)nb).tile;
 }
 
 int bigint_mfma_config(int64_t na, int64_t nb, int* strips_per_band, int* waves, int* digit_bits) {
@@ -216,6 +242,7 @@ int bigint_mul(uint32_t* out, const uint32_t* a, int64_t na, const uint32_t* b, 
     const int h = (int)((na + 1) / 2);
     MfmaCfg hc = current_mfma_cfg(h, h);
     if (hc.waves == 1) hc.waves = 4;   // the half products run one per work-group
+    hc.tile = 16;                      // on 16x16 tiles
     if (!mfma_fits(h, h, hc)) return BIGINT_EUNSUPPORTED;
     if (batch == 0) return BIGINT_OK;
     hipStream_t s = (hipStream_t)stream;
@@ -279,6 +306,7 @@ int bigint_poly(uint32_t* out, const uint32_t* a, const uint32_t* b, int64_t n, 
   if (overlap(out, bytes, a, bytes) || overlap(out, bytes, b, bytes)) return BIGINT_EINVAL;
   MfmaCfg cfg = default_mfma_cfg((int)n, (int)n);
   cfg.dw = 8;
+  cfg.tile = 16;   // Poly's kernels run 16x16 tiles
   if (cfg.waves == 1 && mfma_wave_fits(n, n) && wave_batch(n, n, batch, kWavePoly)) {
     // small operands in large batches: one wave per instance, like the products
     if (batch == 0) return BIGINT_OK;
@@ -324,6 +352,7 @@ int bigint_conv7(int32_t* c, const uint32_t* a, int64_t na, const uint32_t* b, i
   if (!c || !a || !b || na <= 0 || nb <= 0 || batch < 0) return BIGINT_EINVAL;
   MfmaCfg cfg = current_mfma_cfg((int)na, (int)nb);
   cfg.dw = 7;  // the raw coefficients are those of the 7-bit digits
+  cfg.tile = 16;
   if (!mfma_fits(na, nb, cfg) || batch > 0x7fffffff) return BIGINT_EUNSUPPORTED;
   const int64_t K = (32 * na + 6) / 7 + (32 * nb + 6) / 7 - 1;
   const size_t cb = (size_t)K * batch * 4;
@@ -762,9 +791,10 @@ int bigint_diag_mad_rate(uint64_t* scratch, int64_t blocks, int64_t iters, void*
 int bigint_autotune(const char* cache_path, int flags) {
   (void)flags;
   static const int kBins[] = {128, 256, 512, 1024, 2048, 4096, 8192, 16384};
-  static const int kP[] = {4, 8, 16};
+  static const int kP[] = {4, 8, 16, 32};
   static const int kW[] = {1, 4, 8};
   static const int kD[] = {7, 8};
+  static const int kT[] = {16, 32};
   std::vector<TuneEntry> table;
   hipStream_t s = nullptr;
   BI_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
@@ -808,11 +838,16 @@ int bigint_autotune(const char* cache_path, int flags) {
     }
     float best = 1e30f;
     TuneEntry pick{n, 16, 8, 7};
+    for (int T : kT)
     for (int D : kD)
     for (int P : kP)
       for (int W : kW) {
         if (rc != BIGINT_OK) break;
-        const MfmaCfg cfg{P, W, D};
+        const MfmaCfg cfg{P, W, D, T};
+        // 16x16 bands: 4..16 strips; 32x32 bands: 8..32 strips, 8-bit digits,
+        // a work-group per instance
+        if (T == 16 && P == 32) continue;
+        if (T == 32 && (D != 8 || P == 4 || W == 1)) continue;
         if (mfma_lds(n, n, cfg) > 163840) continue;
         // one wave per instance: 8-bit digits, 4 or 8 strips per band, small sizes
         if (W == 1 && (D != 8 || P == 16 || !mfma_wave_fits(n, n))) continue;
@@ -845,7 +880,7 @@ int bigint_autotune(const char* cache_path, int flags) {
           }
           if (nd != 0) { rc = BIGINT_EHIP; set_hip_error(hipErrorUnknown); break; }
         }
-        if (ms < best) { best = ms; pick = TuneEntry{n, P, W, D}; }
+        if (ms < best) { best = ms; pick = TuneEntry{n, P, W, D, T}; }
       }
     (void)hipStreamSynchronize(s);
     if (a) (void)hipFree(a);
@@ -876,8 +911,9 @@ int bigint_autotune(const char* cache_path, int flags) {
     const bool have = hipGetDeviceProperties(&prop, dev) == hipSuccess;
     fprintf(f, "{\"arch\": \"%s\", \"op\": \"mul_mfma\", \"bins\": [", have ? prop.gcnArchName : "?");
     for (size_t i = 0; i < table.size(); ++i)
-      fprintf(f, "%s{\"max_limbs\": %d, \"strips_per_band\": %d, \"waves\": %d, \"digit_bits\": %d}",
-              i ? ", " : "", table[i].max_limbs, table[i].P, table[i].waves, table[i].dw);
+      fprintf(f, "%s{\"max_limbs\": %d, \"strips_per_band\": %d, \"waves\": %d, \"digit_bits\": %d, "
+                 "\"tile\": %d}",
+              i ? ", " : "", table[i].max_limbs, table[i].P, table[i].waves, table[i].dw, table[i].tile);
     fprintf(f, "]}\n");
     fclose(f);
   }
@@ -916,8 +952,16 @@ int bigint_autotune_load(const char* cache_path) {
     if (!field("\"strips_per_band\"", &e.P) || !field("\"waves\"", &e.waves) ||
         !field("\"digit_bits\"", &e.dw))
       return BIGINT_EINVAL;
-    if ((e.P != 4 && e.P != 8 && e.P != 16) || (e.waves != 1 && e.waves != 4 && e.waves != 8) ||
-        (e.dw != 7 && e.dw != 8) || e.max_limbs <= 0)
+    // "tile" (optional, 16 when absent) belongs to this entry if it comes
+    // before the next entry's "max_limbs"
+    {
+      const size_t nt = txt.find("\"tile\"", pos), nm = txt.find("\"max_limbs\"", pos);
+      if (nt != std::string::npos && (nm == std::string::npos || nt < nm) && !field("\"tile\"", &e.tile))
+        return BIGINT_EINVAL;
+    }
+    if ((e.P != 4 && e.P != 8 && e.P != 16 && e.P != 32) ||
+        (e.waves != 1 && e.waves != 4 && e.waves != 8) || (e.dw != 7 && e.dw != 8) ||
+        (e.tile != 16 && e.tile != 32) || (e.P == 32 && e.tile != 32) || e.max_limbs <= 0)
       return BIGINT_EINVAL;
     table.push_back(e);
   }

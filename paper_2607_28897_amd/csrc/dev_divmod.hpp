@@ -263,40 +263,47 @@ constexpr int kSmallMul = 64;  // operands up to this many limbs: column-sum pro
 // LDS bytes of the column-sum product (both operands staged)
 constexpr size_t kSmallMulLds = (size_t)2 * kSmallMul * 4;
 
-// Lane l holds the sums of product columns k = l and l + 64 as
-// C_k = s_k + 2^64 c_k.  Writes limbs [0, n) (n <= 128) of sum_k C_k B^k to
+// Lane l holds the sums of product columns k = l + 64 g (g < H) as
+// C_k = s_k + 2^64 c_k.  Writes limbs [0, n) (n <= 64 H) of sum_k C_k B^k to
 // dst: limb k receives lo32(s_k) + hi32(s_(k-1)) + c_(k-2) (< 3 * 2^32), whose
-// overflow (at most 2) goes one limb up through two wave-level carry scans
-// (limbs 0..63, then 64..127).
-__device__ __forceinline__ void wave_cols_to_limbs(const uint64_t (&s)[2], const uint32_t (&c)[2],
+// overflow (at most 2) goes one limb up through wave-level carry scans over
+// limbs 0..63, 64..127, ...
+template <int H>
+__device__ __forceinline__ void wave_cols_to_limbs(const uint64_t (&s)[H], const uint32_t (&c)[H],
                                                    uint32_t* dst, int n) {
   const int l = lane_id();
-  // neighbours: column k-1 and k-2 (lane l-1 / l-2 of the same half, or of
-  // the lower half across the lane-0 boundary)
+  // neighbours: column k-1 and k-2 (lane l-1 / l-2 of the same group, or of
+  // the group below across the lane-0 boundary)
   const int l1 = (l + 63) & 63, l2 = (l + 62) & 63;
-  const uint32_t sh0 = __shfl((uint32_t)(s[0] >> 32), l1), sh1 = __shfl((uint32_t)(s[1] >> 32), l1);
-  const uint32_t c0 = __shfl(c[0], l2), c1 = __shfl(c[1], l2);
-  uint32_t tl[2], th[2];
+  uint32_t sh[H], cc[H];
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int k = l + 64 * h;
-    const uint32_t hi1 = k >= 1 ? (l >= 1 ? (h ? sh1 : sh0) : sh0) : 0u;
-    const uint32_t cc2 = k >= 2 ? (l >= 2 ? (h ? c1 : c0) : c0) : 0u;
-    const uint64_t t = (uint64_t)(uint32_t)s[h] + hi1 + cc2;
-    tl[h] = (uint32_t)t;
-    th[h] = (uint32_t)(t >> 32);
+  for (int g = 0; g < H; ++g) {
+    sh[g] = __shfl((uint32_t)(s[g] >> 32), l1);
+    cc[g] = __shfl(c[g], l2);
+  }
+  uint32_t tl[H], th[H];
+#pragma unroll
+  for (int g = 0; g < H; ++g) {
+    const int k = l + 64 * g;
+    const uint32_t hi1 = k >= 1 ? (l >= 1 ? sh[g] : sh[g > 0 ? g - 1 : 0]) : 0u;
+    const uint32_t cc2 = k >= 2 ? (l >= 2 ? cc[g] : cc[g > 0 ? g - 1 : 0]) : 0u;
+    const uint64_t t = (uint64_t)(uint32_t)s[g] + hi1 + cc2;
+    tl[g] = (uint32_t)t;
+    th[g] = (uint32_t)(t >> 32);
   }
   // limb k = tl_k + th_(k-1), carries rippling up
-  const uint32_t t0 = __shfl(th[0], l1), t1 = __shfl(th[1], l1);
+  uint32_t tt[H];
+#pragma unroll
+  for (int g = 0; g < H; ++g) tt[g] = __shfl(th[g], l1);
   uint32_t carry = 0u;
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int k = l + 64 * h;
-    const uint32_t y = k >= 1 ? (l >= 1 ? (h ? t1 : t0) : t0) : 0u;
-    const uint32_t x = tl[h];
+  for (int g = 0; g < H; ++g) {
+    const int k = l + 64 * g;
+    const uint32_t y = k >= 1 ? (l >= 1 ? tt[g] : tt[g > 0 ? g - 1 : 0]) : 0u;
+    const uint32_t x = tl[g];
     const uint32_t r = x + y;
-    const bool g = r < x, p = r == 0xffffffffu;
-    const WaveCarry w = wave_carry_masks(g, p);
+    const bool gen = r < x, p = r == 0xffffffffu;
+    const WaveCarry w = wave_carry_masks(gen, p);
     const uint32_t ci = wave_carry_in(w, carry);
     carry = wave_carry_out(w, carry);
     if (k < n) dst[k] = r + ci;
@@ -343,7 +350,7 @@ __device__ inline void wg_mul_small(uint32_t* dst, const uint32_t* a, int na, co
       s[h] = sum;
       c[h] = cnt;
     }
-    wave_cols_to_limbs(s, c, dst, n);
+    wave_cols_to_limbs<2>(s, c, dst, n);
   }
   __syncthreads();
 }
@@ -392,8 +399,11 @@ __device__ __noinline__ bool wg_mul(uint32_t* dst, const uint32_t* a, int na, co
 // no work-group barrier and no global round trip, while the other waves
 // wait at one barrier.  (On the whole work-group each such step took
 // 10-12 us, nearly all of it the fixed latency of a dozen passes and
-// barriers.)
-constexpr int kWaveLimbs = 128;
+// barriers.  Four limbs per lane, which takes one more step onto the wave,
+// measured 1% slower: one wave's serial column sums then cost as much as
+// the work-group's step.)
+constexpr int kWaveGroups = 2;                             // limbs per lane
+constexpr int kWaveLimbs = 64 * kWaveGroups;
 constexpr int kEarlyArr = kWaveLimbs + 8;                  // limbs per LDS array
 constexpr size_t kEarlyLds = (size_t)5 * kEarlyArr * 4;   // w, new w, e, w e, V
 
@@ -403,62 +413,62 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// dst[0 .. n) = a * b mod B^n for n <= 128, operands and result in LDS (dst
-// must not overlap them); lane l forms columns l and l + 64
+// dst[0 .. n) = a * b mod B^n for n <= kWaveLimbs, operands and result in
+// LDS (dst must not overlap them); lane l forms columns l + 64 g
 __device__ inline void wave_mul_lds(uint32_t* dst, const uint32_t* sa, int na, const uint32_t* sb,
                                     int nb, int n) {
   const int l = lane_id();
-  uint64_t s[2];
-  uint32_t c[2];
+  uint64_t s[kWaveGroups];
+  uint32_t c[kWaveGroups];
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int k = l + 64 * h;
+  for (int g = 0; g < kWaveGroups; ++g) {
+    const int k = l + 64 * g;
     uint64_t sum = 0;
     uint32_t cnt = 0;
-    const int lo = max(0, k - nb + 1), hi = min(k, na - 1);
+    const int lo = max(0, k - nb + 1), hi = min(min(k, na - 1), k < n ? k : -1);
     for (int i = lo; i <= hi; ++i) {
       const uint64_t t = (uint64_t)sa[i] * sb[k - i] + sum;
       cnt += t < sum;
       sum = t;
     }
-    s[h] = sum;
-    c[h] = cnt;
+    s[g] = sum;
+    c[g] = cnt;
   }
-  wave_cols_to_limbs(s, c, dst, n);
+  wave_cols_to_limbs<kWaveGroups>(s, c, dst, n);
   wave_lds_sync();
 }
 
-// dst[j] = X(j) + Y(j) (+ cin) or X(j) - Y(j) (- cin) for j < n <= 128 on
-// one wave (every X, Y read before dst is written); returns the number of
-// significant limbs of the result
+// dst[j] = X(j) + Y(j) (+ cin) or X(j) - Y(j) (- cin) for j < n <= kWaveLimbs
+// on one wave (every X, Y read before dst is written); returns the number
+// of significant limbs of the result
 template <bool SUB, class FX, class FY>
-__device__ inline int wave_addsub128(uint32_t* dst, int n, FX X, FY Y, uint32_t cin) {
+__device__ inline int wave_addsub_w(uint32_t* dst, int n, FX X, FY Y, uint32_t cin) {
   const int l = lane_id();
-  uint32_t xs[2], ys[2];
+  uint32_t xs[kWaveGroups], ys[kWaveGroups];
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int j = l + 64 * h;
-    xs[h] = j < n ? X(j) : 0u;
-    ys[h] = j < n ? Y(j) : 0u;
+  for (int g = 0; g < kWaveGroups; ++g) {
+    const int j = l + 64 * g;
+    xs[g] = j < n ? X(j) : 0u;
+    ys[g] = j < n ? Y(j) : 0u;
   }
   wave_lds_sync();
   uint32_t carry = cin;
   int top = 0;
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int j = l + 64 * h;
+  for (int g = 0; g < kWaveGroups; ++g) {
+    const int j = l + 64 * g;
     const bool in = j < n;
-    const uint32_t x = xs[h], y = ys[h];
+    const uint32_t x = xs[g], y = ys[g];
     const uint32_t r = SUB ? x - y : x + y;
-    const bool g = in && (SUB ? x < y : r < x);
+    const bool gen = in && (SUB ? x < y : r < x);
     const bool p = in && (SUB ? x == y : r == 0xffffffffu);
-    const WaveCarry w = wave_carry_masks(g, p);
+    const WaveCarry w = wave_carry_masks(gen, p);
     const uint32_t ci = wave_carry_in(w, carry);
     carry = wave_carry_out(w, carry);
     const uint32_t res = SUB ? r - ci : r + ci;
     if (in) dst[j] = res;
     const uint64_t nz = __ballot(in && res != 0u);
-    if (nz) top = 64 * h + 64 - __clzll(nz);
+    if (nz) top = 64 * g + 64 - __clzll(nz);
   }
   wave_lds_sync();
   return top;
@@ -477,8 +487,8 @@ __device__ inline void wave_newton_early(const uint32_t* v, int k1, int h, uint3
   uint32_t* sV = sT + kEarlyArr;
   const int l = lane_id();
 #pragma unroll
-  for (int h2 = 0; h2 < 2; ++h2) {
-    const int j = l + 64 * h2;
+  for (int g = 0; g < kWaveGroups; ++g) {
+    const int j = l + 64 * g;
     sW[j] = j < lw ? W[j] : 0u;
   }
   wave_lds_sync();
@@ -493,8 +503,8 @@ __device__ inline void wave_newton_early(const uint32_t* v, int k1, int h, uint3
     const int lnew = lw + m + 1;
     if (le > kWaveLimbs || ly > kWaveLimbs || lnew > kWaveLimbs) break;
 #pragma unroll
-    for (int h2 = 0; h2 < 2; ++h2) {
-      const int j = l + 64 * h2;
+    for (int g = 0; g < kWaveGroups; ++g) {
+      const int j = l + 64 * g;
       if (j < t) sV[j] = v[sdrop + j];
     }
     wave_lds_sync();
@@ -504,7 +514,7 @@ __device__ inline void wave_newton_early(const uint32_t* v, int k1, int h, uint3
     const bool neg = top == 0u;
     if (!neg) {
       if (top != 0xffffffffu) { failed = true; break; }
-      wave_addsub128<true>(sE, le, [](int) -> uint32_t { return 0u; },
+      wave_addsub_w<true>(sE, le, [](int) -> uint32_t { return 0u; },
                            [&](int j) -> uint32_t { return sE[j]; }, 0u);
     }
     if (adjust) {
@@ -517,13 +527,15 @@ __device__ inline void wave_newton_early(const uint32_t* v, int k1, int h, uint3
     uint32_t cin = 0u;
     if (neg) {
       const int nlow = min(sy, ly);
-      const bool nz = (l < nlow && sT[l] != 0u) || (l + 64 < nlow && sT[l + 64] != 0u);
+      bool nz = false;
+#pragma unroll
+      for (int g = 0; g < kWaveGroups; ++g) nz |= l + 64 * g < nlow && sT[l + 64 * g] != 0u;
       cin = __ballot(nz) != 0ull ? 1u : 0u;
     }
     auto X = [&](int j) -> uint32_t { return (j >= m && j - m < lw) ? sW[j - m] : 0u; };
     auto Y = [&](int j) -> uint32_t { return j + sy < ly ? sT[j + sy] : 0u; };
-    const int top2 = neg ? wave_addsub128<true>(sU, lnew, X, Y, cin)
-                         : wave_addsub128<false>(sU, lnew, X, Y, 0u);
+    const int top2 = neg ? wave_addsub_w<true>(sU, lnew, X, Y, cin)
+                         : wave_addsub_w<false>(sU, lnew, X, Y, 0u);
     uint32_t* tmp = sW;
     sW = sU;
     sU = tmp;
@@ -531,8 +543,8 @@ __device__ inline void wave_newton_early(const uint32_t* v, int k1, int h, uint3
     cur += m;
   }
 #pragma unroll
-  for (int h2 = 0; h2 < 2; ++h2) {
-    const int j = l + 64 * h2;
+  for (int g = 0; g < kWaveGroups; ++g) {
+    const int j = l + 64 * g;
     if (j < lw) W[j] = sW[j];
   }
 }

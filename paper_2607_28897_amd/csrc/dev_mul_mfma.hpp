@@ -63,6 +63,7 @@ namespace bi {
 namespace mfma {
 
 constexpr int kPadA = 320;  // zero bytes on both sides of reversed alpha (>= 303)
+constexpr int kPadA32 = 1040;  // the same for 32x32 tiles (an A tile spans 1023 digits)
 constexpr int kPadB = 64;   // zero bytes before beta (a tile reads from Y >= -64)
 constexpr int kPadBt = 96;  // zero bytes after beta (reads reach Y + 80)
 constexpr int kStrip = 256; // coefficients per strip
@@ -89,15 +90,17 @@ struct Geo {
 
 // nout < na + nb asks for the product mod B^nout only: the strips past limb
 // nout are not computed (carries only move up, so the low limbs are exact).
-template <int DW>
+// TS: the MFMA tile (16: 16x16x64, 32: 32x32x32), which sets the padding.
+template <int DW, int TS = 16>
 __host__ __device__ inline Geo make_geo(int na, int nb, int nout = -1) {
+  constexpr int kPA = TS == 32 ? kPadA32 : kPadA;
   Geo g;
   g.na = na; g.nb = nb;
   g.Na = ndigits_w<DW>(na); g.Nb = ndigits_w<DW>(nb);
   g.NBa = (g.Na + kStrip - 1) / kStrip;
   g.NBb = (g.Nb + kStrip - 1) / kStrip;
-  g.QA = ((g.Na - 1 + kPadA) + 15) & ~15;
-  g.SA = ((g.QA + kPadA + 1) + 15) & ~15;
+  g.QA = ((g.Na - 1 + kPA) + 15) & ~15;
+  g.SA = ((g.QA + kPA + 1) + 15) & ~15;
   g.SB = ((kPadB + g.Nb + kPadBt) + 15) & ~15;
   const int K = g.Na + g.Nb - 1;
   g.W = (K + kStrip - 1) / kStrip;
@@ -111,9 +114,9 @@ __host__ __device__ inline int bs_bytes(const Geo& g) { return (4 * (g.NBa + g.N
 
 // LDS layout: [Abuf SA][Bbuf SB][per-wave scratch 1 KiB each][strip carries
 // 8W][band order 2*NB][misc 128][block prefix sums (8-bit digits)]
-template <int DW>
+template <int DW, int TS = 16>
 __host__ __device__ inline size_t lds_bytes(int na, int nb, int nwaves, int P) {
-  const Geo g = make_geo<DW>(na, nb);
+  const Geo g = make_geo<DW, TS>(na, nb);
   const int NB = (g.W + P - 1) / P;
   return (size_t)g.SA + g.SB + (size_t)nwaves * 1024 + (size_t)8 * g.W +
          (size_t)((2 * NB + 15) & ~15) + 128 + (DW == 8 ? bs_bytes(g) : 0);
@@ -553,12 +556,18 @@ __device__ __forceinline__ int strip_start_sum(const Lds& s, const Geo& g, int w
 
 // Strip w with offset 8-bit digits: its 64 limbs and carry word.  S0 is the
 // digit-sum term at the strip start; returns the one of strip w + 1.
+// TS = 32: acc is a quarter of a 32x32 result tile (registers 4q..4q+3:
+// column lane & 31, rows 4 (lane >> 5) + v of the quarter's eight).
+template <int TS = 16>
 __device__ __forceinline__ int strip_out8(v4i acc, int w, const Lds& s, const Geo& g,
                                           uint32_t* out, int S0) {
   const int lane = lane_id();
   int32_t* sc = s.wscr;
 #pragma unroll
-  for (int v = 0; v < 4; ++v) sc[16 * (4 * (lane >> 4) + v) + (lane & 15)] = acc[v];
+  for (int v = 0; v < 4; ++v) {
+    if constexpr (TS == 32) sc[32 * (4 * (lane >> 5) + v) + (lane & 31)] = acc[v];
+    else sc[16 * (4 * (lane >> 4) + v) + (lane & 15)] = acc[v];
+  }
   const int g0 = 64 * w;         // the strip's first limb (4-digit group)
   const int m1 = g0 + lane;      // this lane's limb; its digits k = 4 m1 + t
   // per-digit changes of S: alpha'_k - alpha'_{k-Nb} + beta'_k - beta'_{k-Na};
@@ -619,6 +628,144 @@ __device__ __forceinline__ int strip_out8(v4i acc, int w, const Lds& s, const Ge
   return S_next;
 }
 
+// ---- 32x32x32 tiles (v_mfma_i32_32x32x32_i8) ----------------------------------------
+// D[32x32] += A[32x32] B[32x32] with A_Z[r][s] = alpha[Z + 32r - s] and
+// B_Y[s][p] = beta[Y + s + p]: the 1024 outputs are c[Z+Y .. Z+Y+1024),
+// tile T = four consecutive strips.  With Y = 1024y + 32rho (32 phases) and
+// Z = 1024x - 32rho the tile is T = x + y, and a band of P/4 tiles walks y
+// with a ring of A tiles exactly as the 16x16 bands do.  Each instruction
+// does twice the 16x16x64 tile's multiply-accumulates for the same operand
+// bytes per lane.  Register layout (lane l, row r = l & 31, k-group
+// g = l >> 5, byte t: contraction index 16g + t): A lane holds
+// alpha[Z + 32r - 16g - t], one aligned ds_read_b128 of the reversed
+// digits; B lane holds beta[Y + p + 16g + t] with p = l & 31, five dwords
+// aligned with v_alignbyte.  Result register v holds column l & 31, row
+// (v & 3) + 8 (v >> 2) + 4 (l >> 5): registers 4q..4q+3 are strip 4T + q.
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ Range band_range32(const Geo& g, int T0, int P32, int rho) {
+  Range r;
+  // B tile covers beta[Y .. Y+62]; A tile covers alpha[Z-31 .. Z+992]
+  const int yb_lo = ceil_div(-62 - 32 * rho, 1024);
+  const int yb_hi = floor_div(g.Nb - 1 - 32 * rho, 1024);
+  r.xlo = ceil_div(32 * rho - 992, 1024);
+  r.xhi = floor_div(g.Na + 30 + 32 * rho, 1024);
+  r.lo = max(yb_lo, T0 - r.xhi);
+  r.hi = min(yb_hi, T0 + P32 - 1 - r.xlo);
+  return r;
+}
+
+__device__ __forceinline__ int band_cost32(const Geo& g, int band, int P) {
+  int c = 0;
+  for (int rho = 0; rho < 32; ++rho) {
+    const Range r = band_range32(g, band * (P / 4), P / 4, rho);
+    c += max(0, r.hi - r.lo + 1);
+  }
+  return c;
+}
+
+__device__ __forceinline__ v4i load_A32(const uint8_t* Abuf, const Geo& g, int x, int rho,
+                                        const Range& r) {
+  const int lane = lane_id();
+  const int Z = 1024 * x - 32 * rho;
+  const bool ok = x >= r.xlo && x <= r.xhi;  // wave-uniform
+  const int addr = ok ? g.QA - Z - 32 * (lane & 31) + 16 * (lane >> 5) : 0;
+  return *reinterpret_cast<const v4i*>(Abuf + addr);
+}
+
+__device__ __forceinline__ BRaw load_B_raw32(const uint8_t* Bbuf, int y, int rho) {
+  const int lane = lane_id();
+  const int p = lane & 31;
+  const int Y = 1024 * y + 32 * rho;
+  const uint32_t* src =
+      reinterpret_cast<const uint32_t*>(Bbuf + kPadB + Y + 16 * (lane >> 5) + 4 * (p >> 2));
+  BRaw b;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) b.d[i] = src[i];
+  return b;
+}
+
+// One phase of one band of P32 tiles: acc[i] += sum over the y range of
+// A(T0+i-y) B(y); the software pipeline and the ramp block of band_phase.
+template <int P32>
+__device__ __forceinline__ void band_phase32(v16i (&acc)[P32], const Lds& s, const Geo& g, int T0,
+                                             int rho) {
+  const Range r = band_range32(g, T0, P32, rho);
+  const int L = r.hi - r.lo + 1;
+  if (L <= 0) return;
+  const int xb = T0 - r.lo;
+  const bool ramp = L >= 2 * P32 && r.lo == T0 - r.xhi;
+  v4i ring[P32];
+#pragma unroll
+  for (int i = 0; i < P32; ++i) ring[i] = load_A32(s.A, g, xb + i, rho, r);
+  v4i Bc = align_B(load_B_raw32(s.B, r.lo, rho));
+  BRaw raw = load_B_raw32(s.B, min(r.lo + 1, r.hi), rho);
+  auto step_fn = [&](const int step, const int st, const bool rmp) __attribute__((always_inline)) {
+    auto mma = [&](int i) __attribute__((always_inline)) {
+      if (!rmp || i <= st)
+        acc[i] = __builtin_amdgcn_mfma_i32_32x32x32_i8(ring[(P32 + i - st) % P32], Bc, acc[i], 0, 0, 0);
+    };
+    mma(P32 - 1);
+    ring[(2 * P32 - 1 - st) % P32] = load_A32(s.A, g, xb - step - 1, rho, r);
+#pragma unroll
+    for (int i = P32 - 2; i >= P32 / 2; --i) mma(i);
+    __builtin_amdgcn_sched_barrier(0);
+    const v4i Bn = align_B(raw);
+    raw = load_B_raw32(s.B, min(r.lo + step + 2, r.hi), rho);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int i = P32 / 2 - 1; i >= 0; --i) mma(i);
+    __builtin_amdgcn_sched_barrier(0);
+    Bc = Bn;
+  };
+  const int nfull = L / P32;
+  int blk0 = 0;
+  if (ramp) {
+#pragma unroll
+    for (int st = 0; st < P32; ++st) step_fn(st, st, true);
+    blk0 = 1;
+  }
+#pragma unroll 1
+  for (int blk = blk0; blk < nfull; ++blk) {
+#pragma unroll
+    for (int st = 0; st < P32; ++st) step_fn(blk * P32 + st, st, false);
+  }
+  const int rem = L - nfull * P32;
+  if (rem > 0) {
+#pragma unroll
+    for (int st = 0; st < P32 - 1; ++st)
+      if (st < rem) step_fn(nfull * P32 + st, st, false);
+  }
+}
+
+// A band of P strips (P / 4 tiles of 32x32) with offset 8-bit digits.
+template <int P>
+__device__ __forceinline__ void run_band32(int band, const Lds& s, const Geo& g, uint32_t* out) {
+  constexpr int P32 = P / 4;
+  const int T0 = band * P32;
+  v16i acc[P32];
+#pragma unroll
+  for (int i = 0; i < P32; ++i) {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) acc[i][e] = 0;
+  }
+#pragma unroll 1
+  for (int rho = 0; rho < 32; ++rho) band_phase32<P32>(acc, s, g, T0, rho);
+  int S = 0;
+#pragma unroll
+  for (int i = 0; i < P32; ++i) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int w = 4 * (T0 + i) + q;
+      if (w < g.W) {
+        if (i == 0 && q == 0) S = strip_start_sum(s, g, w);
+        const v4i part = {acc[i][4 * q], acc[i][4 * q + 1], acc[i][4 * q + 2], acc[i][4 * q + 3]};
+        S = strip_out8<32>(part, w, s, g, out, S);
+      }
+    }
+  }
+}
+
 template <int DW, int P>
 __device__ __forceinline__ void run_band(int band, const Lds& s, const Geo& g, uint32_t* out, int32_t* coef) {
   const int w0 = band * P;
@@ -656,13 +803,14 @@ __host__ __device__ inline int high_band(int nlo, int P) {
 // one less, and the limbs below nlo are left as they were or wrong.  With
 // coef != nullptr (7-bit digits only, whole product) the raw coefficients
 // c_k (k < Na+Nb-1) are written instead.
-template <int DW, int P>
+template <int DW, int P, int TS = 16>
 __device__ __forceinline__ void wg_mul_mfma(uint32_t* out, int32_t* coef, const uint32_t* __restrict__ a, int na,
                             const uint32_t* __restrict__ b, int nb, char* smem, int nout = -1,
                             int nlo = 0) {
   static_assert(DW == 7 || DW == 8, "digit width");
+  static_assert(TS == 16 || (TS == 32 && DW == 8 && P % 4 == 0), "32x32 tiles: 8-bit digits, whole tiles per band");
   constexpr int kStripLimbs = strip_limbs<DW>();
-  const Geo g = make_geo<DW>(na, nb, coef ? -1 : nout);
+  const Geo g = make_geo<DW, TS>(na, nb, coef ? -1 : nout);
   const Lds s = carve(smem, g, P);
   const int NBall = (g.W + P - 1) / P;
   // bands [band_lo, NBall) are computed; strips from w_first up
@@ -679,7 +827,8 @@ __device__ __forceinline__ void wg_mul_mfma(uint32_t* out, int32_t* coef, const 
   }
   // band order: most expensive first (rank sort by cost; the costs sit in
   // the wave scratch area, which holds 256 ints per wave >= NB)
-  for (int t = threadIdx.x; t < NB; t += blockDim.x) s.scr[t] = band_cost(g, band_lo + t, P);
+  for (int t = threadIdx.x; t < NB; t += blockDim.x)
+    s.scr[t] = TS == 32 ? band_cost32(g, band_lo + t, P) : band_cost(g, band_lo + t, P);
   if (threadIdx.x == 0) s.misc[0] = 0;
   __syncthreads();
   for (int t = threadIdx.x; t < NB; t += blockDim.x) {
@@ -699,7 +848,8 @@ __device__ __forceinline__ void wg_mul_mfma(uint32_t* out, int32_t* coef, const 
     t = __builtin_amdgcn_readfirstlane(t);
     if ((int)t >= NB) break;
     const int band = band_lo + __builtin_amdgcn_readfirstlane((int)s.order[t]);
-    run_band<DW, P>(band, s, g, out, coef);
+    if constexpr (TS == 32) run_band32<P>(band, s, g, out);
+    else run_band<DW, P>(band, s, g, out, coef);
   }
   __syncthreads();
   if (coef == nullptr) {

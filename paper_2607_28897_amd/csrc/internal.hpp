@@ -7,10 +7,12 @@ namespace bi {
 
 // tile configuration of the MFMA multiply
 struct MfmaCfg {
-  int P;       // strips per wave band (4, 8, 16)
+  int P;       // strips per wave band (4, 8, 16; 8, 16, 32 with 32x32 tiles)
   int waves;   // waves per work-group (4, 8); 1: one wave per instance, 4 instances
                // per work-group (8-bit digits, na + nb <= 4096 limbs)
   int dw;      // digit width: 7 (plain 7-bit digits) or 8 (offset 8-bit digits)
+  int tile = 16;  // MFMA tile: 16 (v_mfma_i32_16x16x64_i8) or 32 (v_mfma_i32_32x32x32_i8;
+                  // 8-bit digits, P = 8 or 16 strips per band)
 };
 
 // index of a tile configuration in the ragged kernel's dispatch

@@ -290,13 +290,13 @@ int launch_mul_plain(uint32_t* out, const uint32_t* a, int64_t na, const uint32_
 // MFMA-split multiply: one work-group per instance
 // ============================================================================
 // out instance i = a_i * b_i mod B^nout (nout = na + nb: the whole product)
-template <int DW, int P>
+template <int DW, int P, int TS>
 __global__ __launch_bounds__(512) void k_mul_mfma(uint32_t* out, int32_t* coef, const uint32_t* a,
                                                   int na, const uint32_t* b, int nb, int nout) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
   const int64_t inst = blockIdx.x;
   const int K = mfma::ndigits(na) + mfma::ndigits(nb) - 1;
-  mfma::wg_mul_mfma<DW, P>(out ? out + inst * (int64_t)nout : nullptr,
+  mfma::wg_mul_mfma<DW, P, TS>(out ? out + inst * (int64_t)nout : nullptr,
                            coef ? coef + inst * (int64_t)K : nullptr, a + inst * (int64_t)na, na,
                            b + inst * (int64_t)nb, nb, smem, nout);
 }
@@ -305,19 +305,20 @@ __global__ __launch_bounds__(512) void k_mul_mfma(uint32_t* out, int32_t* coef, 
 // as its 4-wave fallback, which covers it)
 size_t mfma_lds(int na, int nb, MfmaCfg cfg) {
   if (cfg.waves == 1) cfg.waves = 4;
+  if (cfg.tile == 32) return mfma::lds_bytes<8, 32>(na, nb, cfg.waves, cfg.P);
   return cfg.dw == 8 ? mfma::lds_bytes<8>(na, nb, cfg.waves, cfg.P)
                      : mfma::lds_bytes<7>(na, nb, cfg.waves, cfg.P);
 }
 
-template <int DW, int P>
+template <int DW, int P, int TS = 16>
 static int launch_mfma_p(uint32_t* out, int32_t* coef, const uint32_t* a, int64_t na,
                          const uint32_t* b, int64_t nb, int64_t batch, int waves, int nout,
                          hipStream_t s) {
-  const size_t lds = mfma::lds_bytes<DW>((int)na, (int)nb, waves, P);
+  const size_t lds = mfma::lds_bytes<DW, TS>((int)na, (int)nb, waves, P);
   if (lds > 163840) return BIGINT_EUNSUPPORTED;
-  BI_HIP(hipFuncSetAttribute((const void*)k_mul_mfma<DW, P>,
+  BI_HIP(hipFuncSetAttribute((const void*)k_mul_mfma<DW, P, TS>,
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  hipLaunchKernelGGL((k_mul_mfma<DW, P>), dim3((unsigned)batch), dim3(64 * waves), lds, s, out,
+  hipLaunchKernelGGL((k_mul_mfma<DW, P, TS>), dim3((unsigned)batch), dim3(64 * waves), lds, s, out,
                      coef, a, (int)na, b, (int)nb, nout);
   BI_LAUNCH_CHECK();
   return BIGINT_OK;
@@ -327,6 +328,16 @@ template <int DW>
 static int launch_mfma_dw(uint32_t* out, int32_t* coef, const uint32_t* a, int64_t na,
                           const uint32_t* b, int64_t nb, int64_t batch, MfmaCfg cfg, int nout,
                           hipStream_t s) {
+  if constexpr (DW == 8) {
+    if (cfg.tile == 32) {
+      switch (cfg.P) {
+        case 8: return launch_mfma_p<8, 8, 32>(out, coef, a, na, b, nb, batch, cfg.waves, nout, s);
+        case 16: return launch_mfma_p<8, 16, 32>(out, coef, a, na, b, nb, batch, cfg.waves, nout, s);
+        case 32: return launch_mfma_p<8, 32, 32>(out, coef, a, na, b, nb, batch, cfg.waves, nout, s);
+        default: return BIGINT_EINVAL;
+      }
+    }
+  }
   switch (cfg.P) {
     case 4: return launch_mfma_p<DW, 4>(out, coef, a, na, b, nb, batch, cfg.waves, nout, s);
     case 8: return launch_mfma_p<DW, 8>(out, coef, a, na, b, nb, batch, cfg.waves, nout, s);
@@ -390,6 +401,7 @@ int launch_mul_mfma(uint32_t* out, int32_t* coef, const uint32_t* a, int64_t na,
   if (cfg.dw == 8 && coef == nullptr)
     return launch_mfma_dw<8>(out, nullptr, a, na, b, nb, batch, cfg, nout, s);
   if (cfg.dw != 7 && cfg.dw != 8) return BIGINT_EINVAL;
+  cfg.tile = 16;   // raw coefficients and 7-bit digits: 16x16 tiles
   return launch_mfma_dw<7>(out, coef, a, na, b, nb, batch, cfg, coef ? (int)(na + nb) : nout, s);
 }
 
@@ -804,8 +816,45 @@ int launch_mad_rate(uint64_t* out, int blocks, int iters, hipStream_t s) {
   return BIGINT_OK;
 }
 
+// The same probe on v_mfma_i32_32x32x32_i8 (32,768 multiply-accumulates per
+// instruction, twice the 16x16x64 tile's for the same 16 operand bytes per
+// lane): 4 independent 32x32 accumulators per wave, 32 MFMAs per loop
+// round (the same multiply-accumulates per round as the 16x16x64 probe).
+typedef int v16i __attribute__((ext_vector_type(16)));
+__global__ __launch_bounds__(256) void k_mfma_rate32(int32_t* out, int iters, int toggle) {
+  const int lane = lane_id();
+  v4i a = {lane, lane * 3, lane * 5, lane * 7};
+  v4i b = {lane * 11, lane * 13, lane, 1};
+  v16i acc[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) acc[j][e] = e == 0 ? j : 0;
+  }
+  const int flip = (toggle & 1) ? (int)0x9e3779b9 : 0;
+  for (int i = 0; i < iters; ++i) {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, acc[j], 0, 0, 0);
+      a ^= flip;
+      b ^= flip + r;
+    }
+  }
+  int32_t t = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) t += acc[j][e];
+  }
+  out[blockIdx.x * blockDim.x + threadIdx.x] = t;
+}
+
 int launch_mfma_rate(int32_t* out, int blocks, int iters, int toggle, hipStream_t s) {
-  hipLaunchKernelGGL(k_mfma_rate, dim3(blocks), dim3(256), 0, s, out, iters, toggle);
+  if (toggle & 2)
+    hipLaunchKernelGGL(k_mfma_rate32, dim3(blocks), dim3(256), 0, s, out, iters, toggle);
+  else
+    hipLaunchKernelGGL(k_mfma_rate, dim3(blocks), dim3(256), 0, s, out, iters, toggle);
   BI_LAUNCH_CHECK();
   return BIGINT_OK;
 }

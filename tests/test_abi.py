@@ -132,3 +132,32 @@ def test_tune_table_load_and_restore(bi, tmp_path):
     with pytest.raises(bi.BigIntError):
         bi.autotune_load(bad)
     assert bi.mfma_config(4096, 4096) == (8, 8, 8)
+
+
+def test_tune_table_tile_field(bi, tmp_path):
+    # host-side only: the optional "tile" field of a table entry picks the
+    # MFMA tile (absent: 16); 32x32 tiles with 7-bit digits or 4 strips per
+    # band fall back to 16; a 16x16 entry with 32 strips per band is refused
+    import json
+    path = str(tmp_path / "t32.json")
+    json.dump({"bins": [{"max_limbs": 2000, "strips_per_band": 8, "waves": 8, "digit_bits": 8},
+                        {"max_limbs": 18432, "strips_per_band": 32, "waves": 8, "digit_bits": 8,
+                         "tile": 32}]}, open(path, "w"))
+    bi.autotune_load(path)
+    try:
+        assert bi.mfma_tile(1000, 1000) == 16
+        assert bi.mfma_tile(16384, 16384) == 32
+        assert bi.mfma_config(16384, 16384) == (32, 8, 8)
+        bi.set_mfma_config(0, 0, 7)
+        try:
+            assert bi.mfma_tile(16384, 16384) == 16
+        finally:
+            bi.set_mfma_config(0, 0, 0)
+    finally:
+        bi.autotune_load(None)
+    assert bi.mfma_tile(16384, 16384) == 16
+    bad = str(tmp_path / "bad32.json")
+    json.dump({"bins": [{"max_limbs": 18432, "strips_per_band": 32, "waves": 8, "digit_bits": 8,
+                         "tile": 16}]}, open(bad, "w"))
+    with pytest.raises(bi.BigIntError):
+        bi.autotune_load(bad)

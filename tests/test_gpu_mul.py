@@ -15,20 +15,24 @@ def bi():
     m.lib()
     yield m
     m.set_mfma_config(0, 0, 0)
+    m.set_mfma_tile(0)
 
 
-# the plain kernel, and the MFMA-split kernel with 7-bit and offset 8-bit digits
-ALGOS = ["plain", "mfma7", "mfma8"]
+# the plain kernel, and the MFMA-split kernel with 7-bit and offset 8-bit
+# digits on 16x16x64 tiles, and with 8-bit digits on 32x32x32 tiles
+ALGOS = ["plain", "mfma7", "mfma8", "mfma8t32"]
 
 
 def _mul(bi, ta, tb, name):
     if name == "plain":
         return bi.mul(ta, tb, bi.MUL_PLAIN)
     bi.set_mfma_config(0, 0, 7 if name == "mfma7" else 8)
+    bi.set_mfma_tile(32 if name == "mfma8t32" else 16)
     try:
         return bi.mul(ta, tb, bi.MUL_MFMA)
     finally:
         bi.set_mfma_config(0, 0, 0)
+        bi.set_mfma_tile(0)
 
 
 # ---- the steps of the MFMA path ---------------------------------------------------
@@ -194,10 +198,14 @@ def test_autotune_table_roundtrip(bi, orc, tmp_path):
     t = json.load(open(path))
     assert t["op"] == "mul_mfma" and len(t["bins"]) == 8
     for e in t["bins"]:
-        assert e["strips_per_band"] in (4, 8, 16) and e["waves"] in (1, 4, 8)
-        assert e["digit_bits"] in (7, 8)
+        assert e["strips_per_band"] in (4, 8, 16, 32) and e["waves"] in (1, 4, 8)
+        assert e["digit_bits"] in (7, 8) and e["tile"] in (16, 32)
         if e["waves"] == 1:
-            assert e["digit_bits"] == 8 and e["strips_per_band"] in (4, 8)
+            assert e["digit_bits"] == 8 and e["strips_per_band"] in (4, 8) and e["tile"] == 16
+        if e["tile"] == 32:
+            assert e["digit_bits"] == 8 and e["strips_per_band"] in (8, 16, 32)
+        else:
+            assert e["strips_per_band"] != 32
     bi.autotune_load(path)
     try:
         g = np.random.default_rng(9)
@@ -412,3 +420,70 @@ def test_unaligned_buffers_take_the_scalar_paths(bi, orc):
     got = out[1:1 + B * n].cpu().numpy().view(np.uint32).reshape(B, n)
     want, wc = orc.sub(a, b)
     assert np.array_equal(got, want) and np.array_equal(cy.cpu().numpy().view(np.uint32), wc)
+
+
+@pytest.mark.parametrize("P,waves", [(8, 4), (8, 8), (16, 4), (16, 8)])
+@pytest.mark.parametrize("na,nb", [(1, 1), (3, 700), (64, 64), (257, 255), (1000, 1000), (4097, 4095),
+                                   (12000, 300), (16384, 16384), (18432, 18432)])
+def test_tile32_shapes(bi, orc, P, waves, na, nb):
+    """32x32x32 tiles (four strips per tile, 32 phases per band) on every
+    strips-per-band and wave count they take: ragged tails, unequal
+    operands and the largest size, against the oracle."""
+    g = np.random.default_rng(na * 31 + nb + P + waves)
+    B = 2 if na * nb > 10**7 else 3
+    a = rand_limbs(g, B, na)
+    b = rand_limbs(g, B, nb)
+    b[B - 1] = 0xFFFFFFFF
+    bi.set_mfma_config(P, waves, 8)
+    bi.set_mfma_tile(32)
+    try:
+        p = host(bi.mul(dev(a), dev(b), bi.MUL_MFMA))
+    finally:
+        bi.set_mfma_config(0, 0, 0)
+        bi.set_mfma_tile(0)
+    for i in range(B):
+        assert np.array_equal(p[i], orc.mul1(a[i], b[i])), i
+
+
+@pytest.mark.parametrize("pat", [0x00000000, 0xFFFFFFFF, 0x80808080, 0x7F7F7F7F])
+def test_tile32_offset_digit_extremes(bi, orc, pat):
+    """Every offset digit at -128, +127, 0 or -1: the largest MFMA sums."""
+    n = 16384
+    a = np.full((1, n), pat, np.uint32)
+    bi.set_mfma_tile(32)
+    try:
+        p = host(bi.mul(dev(a), dev(a), bi.MUL_MFMA))[0]
+    finally:
+        bi.set_mfma_tile(0)
+    assert np.array_equal(p, orc.mul1(a[0], a[0]))
+
+
+@pytest.mark.parametrize("n", [700, 4096, 16384])
+def test_tile32_mullo(bi, orc, n):
+    """Products mod B^n (only the strips below limb n) on 32x32 tiles."""
+    g = np.random.default_rng(n + 5)
+    a = rand_limbs(g, 2, n)
+    b = rand_limbs(g, 2, n)
+    bi.set_mfma_tile(32)
+    try:
+        p = host(bi.mullo(dev(a), dev(b)))
+    finally:
+        bi.set_mfma_tile(0)
+    for i in range(2):
+        assert np.array_equal(p[i], orc.mullo1(a[i], b[i])), i
+
+
+def test_tile_query_and_errors(bi):
+    assert bi.lib().bigint_set_mfma_tile(24) == bi.EINVAL
+    bi.set_mfma_tile(32)
+    try:
+        bi.set_mfma_config(16, 8, 8)
+        assert bi.mfma_tile(16384, 16384) == 32
+        bi.set_mfma_config(4, 8, 8)            # 4 strips per band: not a whole tile
+        assert bi.mfma_tile(16384, 16384) == 16
+        bi.set_mfma_config(16, 8, 7)           # 7-bit digits run 16x16 tiles
+        assert bi.mfma_tile(16384, 16384) == 16
+    finally:
+        bi.set_mfma_config(0, 0, 0)
+        bi.set_mfma_tile(0)
+
