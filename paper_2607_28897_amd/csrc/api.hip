@@ -446,8 +446,11 @@ static int plan_build_mul(bigint_plan_s* p) {
     p->lds = lds;
   } else {
     // Segments, one launch each.  A segment starts with the largest remaining
-    // instance; its core is the run of instances with the same tile
-    // configuration and the same LDS-bound work-groups per CU.  The core is
+    // instance; its core is the run of instances with the same digit width,
+    // waves and LDS-bound work-groups per CU and no more strips per band (the
+    // segment's kernel runs those with fewer strips inlined; one launch over
+    // them balances better than a launch per strips-per-band value: 4096
+    // ragged products 2.18 -> 2.12 ms).  The core is
     // list-scheduled largest first on the launch's resident work-groups (as
     // in-order dispatch will run it); then the following instances of the
     // same digit width and no more strips per band join the segment as long
@@ -482,10 +485,12 @@ static int plan_build_mul(bigint_plan_s* p) {
       const It& h = it[pos];
       RaggedClass k{ragged_cfg_id(h.c), h.c.waves, (int)pos, 0, 0};
       int64_t end = pos;
-      while (end < B && it[end].c.P == h.c.P && it[end].c.dw == h.c.dw &&
+      while (end < B && it[end].c.P <= h.c.P && it[end].c.dw == h.c.dw &&
              it[end].c.waves == h.c.waves && it[end].lpc == h.lpc) {
         const int64_t i = it[end].i;
-        k.lds = std::max(k.lds, mfma_lds((int)p->la[i], (int)p->lb[i], MfmaCfg{h.c.P, k.waves, h.c.dw}));
+        // (each instance's own strips per band: fewer strips, more bands)
+        k.lds = std::max(k.lds, mfma_lds((int)p->la[i], (int)p->lb[i],
+                                         MfmaCfg{it[end].c.P, k.waves, h.c.dw}));
         ++end;
       }
       const int slots = ragged_slots(k.cfg, k.waves, k.lds);
