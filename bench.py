@@ -333,13 +333,27 @@ def ragged_leg(torch, bi, inputs, args):
         N = (32 * int(n_) + 6) // 7 if dbits == 7 else 4 * int(n_)
         macs += float(N) * N * int((lens == n_).sum())
     info = plan.info()
+    # each segment's launch alone (direct, same buffers): its time, its
+    # executed int8 ops against the peak, and the plan's modelled busy
+    # fraction of its resident work-groups
+    segs = []
+    for k, sg in enumerate(plan.segments()):
+        t, _ = time_launches(lambda: plan.run_segment(k, ta, tao, tb, tbo, out, oo), steps, args.warmup,
+                             torch)
+        sms = t / steps
+        segs.append({"instances": sg["instances"], "digit_bits": sg["digit_bits"],
+                     "strips_per_band": sg["strips_per_band"], "waves": sg["waves"],
+                     "resident_work_groups": sg["slots"], "ms": round(sms, 4),
+                     "frac": round(2.0 * sg["digit_products"] / (sms * 1e-3) / 1e12 / INT8_PEAK_TOPS, 4),
+                     "modelled_busy": round(sg["modelled_busy"], 3)})
     plan.close()
     return {"workload": "4096 products, operand bits log-uniform in [2^15, 2^19] (seed 1003)",
             "value": round(4096 / (ms * 1e-3), 1), "unit": "muls/s", "ms_per_call": round(ms, 4),
             "steps": steps, "launches_per_call": info["launches_per_call"],
             "graph_replays": info["graph_replays"],
             "roofline": mfma_roofline(2.0 * macs, ms, f"sum over pairs of 2 x (digits)^2 int8 ops at the "
-                                                    f"tuned digit width, {2.0 * macs:.4g} per call")}
+                                                    f"tuned digit width, {2.0 * macs:.4g} per call"),
+            "segments": segs}
 
 
 def divmod_leg(torch, bi, inputs, args):
@@ -449,8 +463,9 @@ def peak_mode(torch, bi):
 
 
 def ragged_mode(torch, bi, inputs, args):
-    """4096 products, bit lengths log-uniform in [2^15, 2^19] (seed 1003), one
-    persistent launch replayed from a hipGraph; the plain kernel beside it."""
+    """4096 products, bit lengths log-uniform in [2^15, 2^19] (seed 1003), the
+    plan's segment launches replayed from a hipGraph and launched directly,
+    the plain kernel beside them, and every segment timed alone."""
     c = inputs.ragged_mul_2e15_2e19()
     lens = c["lens"]
     ta = torch.from_numpy(c["a"].view(np.int32)).cuda()
@@ -485,6 +500,7 @@ def ragged_mode(torch, bi, inputs, args):
         else:
             res[name]["equals_mfma_graph"] = bool(torch.equal(out, ref))
         plan.close()
+    res["segments"] = ragged_leg(torch, bi, inputs, args)["segments"]
     print(json.dumps(res))
 
 

@@ -239,6 +239,30 @@ int bigint_mul_ragged(uint32_t* out, const int64_t* out_off, const uint32_t* a,
                       const int64_t* b_off, int64_t batch, bigint_plan_t plan,
                       void* stream);
 
+/* The segments of a ragged multiply plan (diagnostic): *n_segments = the
+ * launches one bigint_mul_ragged call makes on the MFMA-split path (0 for a
+ * plain or division plan), and for segment k < max_segments the host int64
+ * row seg[8k .. 8k+8): [0] first queue position (queue = instances largest
+ * first), [1] instances, [2] digit bits, [3] strips per band of its leading
+ * configuration, [4] waves per work-group, [5] work-groups resident at once,
+ * [6] digit products its instances compute (sum of Na*Nb at its digit width),
+ * [7] modelled busy fraction in parts per million: the segment's cost (sum
+ * of la*lb) over resident work-groups times the span of the plan's largest-
+ * first list schedule.  The plan's load-balance figure per launch. */
+int bigint_plan_segments(bigint_plan_t plan, int64_t* seg, int max_segments,
+                         int* n_segments);
+
+/* One segment of a ragged multiply (same arguments as bigint_mul_ragged,
+ * segment < the count bigint_plan_segments reports): launches only that
+ * segment's kernel, directly (no graph), writing only the products of its
+ * instances.  Running every segment once, in any order, equals one
+ * bigint_mul_ragged call; lets a caller time or overlap segments. */
+int bigint_mul_ragged_segment(uint32_t* out, const int64_t* out_off,
+                              const uint32_t* a, const int64_t* a_off,
+                              const uint32_t* b, const int64_t* b_off,
+                              int64_t batch, bigint_plan_t plan, int segment,
+                              void* stream);
+
 /* Ragged division: instance i divides u[u_off[i]..) by v[v_off[i]..); q
  * instance i has the dividend's limb count and r the divisor's.  The
  * division launches (one or more, each at most eight times the work-groups

@@ -81,6 +81,8 @@ def lib() -> ctypes.CDLL:
             "bigint_plan_destroy": ([_vp], _int),
             "bigint_plan_info": ([_vp, _vp, _int], _int),
             "bigint_mul_ragged": ([_vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp], _int),
+            "bigint_plan_segments": ([_vp, _vp, _int, _vp], _int),
+            "bigint_mul_ragged_segment": ([_vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _int, _vp], _int),
             "bigint_divmod_ragged": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp], _int),
             "bigint_autotune": ([ctypes.c_char_p, _int], _int),
             "bigint_autotune_load": ([ctypes.c_char_p], _int),
@@ -395,6 +397,28 @@ class MulPlan(_Plan):
         _check(lib().bigint_mul_ragged(_p(out), _p(out_off), _p(a), _p(a_off), _p(b), _p(b_off),
                                        self.batch, self._h, _stream()), "bigint_mul_ragged")
         return out, out_off
+
+    def segments(self) -> list:
+        """The plan's launches on the MFMA-split path, one dict per segment:
+        first queue position, instances, digit bits, strips per band, waves,
+        resident work-groups, digit products, modelled busy fraction."""
+        import numpy as np
+        n = ctypes.c_int()
+        _check(lib().bigint_plan_segments(self._h, None, 0, ctypes.byref(n)), "bigint_plan_segments")
+        v = np.zeros((max(n.value, 1), 8), np.int64)
+        _check(lib().bigint_plan_segments(self._h, v.ctypes.data_as(ctypes.c_void_p), n.value,
+                                          ctypes.byref(n)), "bigint_plan_segments")
+        keys = ("first", "instances", "digit_bits", "strips_per_band", "waves", "slots",
+                "digit_products")
+        return [dict({k: int(x) for k, x in zip(keys, row[:7])}, modelled_busy=float(row[7]) / 1e6)
+                for row in v[:n.value]]
+
+    def run_segment(self, k, a, a_off, b, b_off, out, out_off):
+        """Launch only segment k (no graph) into out."""
+        _check(lib().bigint_mul_ragged_segment(_p(out), _p(out_off), _p(a), _p(a_off), _p(b), _p(b_off),
+                                               self.batch, self._h, int(k), _stream()),
+               "bigint_mul_ragged_segment")
+        return out
 
 
 class DivPlan(_Plan):

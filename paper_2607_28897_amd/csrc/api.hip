@@ -374,6 +374,11 @@ struct bigint_plan_s {
   // schedule: the queue (largest first; division: int32 instance indices)
   bi::QueueItem* d_queue = nullptr;
   std::vector<bi::RaggedClass> cls;  // MFMA multiply: one launch per segment
+  // per segment (bigint_plan_segments): digit products its instances compute,
+  // and its modelled busy fraction (sum of costs / (slots x list-schedule span))
+  std::vector<int64_t> seg_products;
+  std::vector<double> seg_busy;
+  std::vector<int> seg_slots;
   size_t lds = 0;                    // plain multiply
   bool plain = false;
   int grid = 0;               // division: work-groups (workspace slots) per launch
@@ -516,7 +521,20 @@ static int plan_build_mul(bigint_plan_s* p) {
         ++end;
       }
       k.count = (int)(end - pos);
-      for (int64_t t = pos; t < end; ++t) q[t] = QueueItem{(int32_t)it[t].i, it[t].c.P};
+      double work = 0.0, fspan = 0.0;
+      int64_t prod = 0;
+      for (int64_t t = pos; t < end; ++t) {
+        q[t] = QueueItem{(int32_t)it[t].i, it[t].c.P};
+        work += (double)cost(it[t].i);
+        const int64_t i = it[t].i;
+        const int64_t da = h.c.dw == 8 ? 4 * p->la[i] : (32 * p->la[i] + 6) / 7;
+        const int64_t db = h.c.dw == 8 ? 4 * p->lb[i] : (32 * p->lb[i] + 6) / 7;
+        prod += da * db;
+      }
+      while (!fin.empty()) { fspan = std::max(fspan, fin.top()); fin.pop(); }
+      p->seg_products.push_back(prod);
+      p->seg_busy.push_back(fspan > 0.0 ? work / ((double)slots * fspan) : 0.0);
+      p->seg_slots.push_back(slots);
       cls.push_back(k);
       pos = end;
     }
@@ -627,9 +645,29 @@ int bigint_plan_info(bigint_plan_t plan, int64_t* info, int n) {
   return BIGINT_OK;
 }
 
-int bigint_mul_ragged(uint32_t* out, const int64_t* out_off, const uint32_t* a,
-                      const int64_t* a_off, const uint32_t* b, const int64_t* b_off, int64_t batch,
-                      bigint_plan_t plan, void* stream) {
+int bigint_plan_segments(bigint_plan_t plan, int64_t* seg, int max_segments, int* n_segments) {
+  if (!plan || !n_segments || max_segments < 0 || (!seg && max_segments > 0)) return BIGINT_EINVAL;
+  const bool mfma = plan->op == BIGINT_OP_MUL && !plan->plain;
+  const int n = mfma ? (int)plan->cls.size() : 0;
+  *n_segments = n;
+  for (int k = 0; k < std::min(n, max_segments); ++k) {
+    const RaggedClass& c = plan->cls[k];
+    int64_t* o = seg + 8 * k;
+    o[0] = c.first;
+    o[1] = c.count;
+    o[2] = c.cfg >= 3 ? 8 : 7;
+    o[3] = 4 << (c.cfg % 3);
+    o[4] = c.waves;
+    o[5] = plan->seg_slots[k];
+    o[6] = plan->seg_products[k];
+    o[7] = (int64_t)std::llround(1e6 * plan->seg_busy[k]);
+  }
+  return BIGINT_OK;
+}
+
+static int ragged_mul_checks(uint32_t* out, const int64_t* out_off, const uint32_t* a,
+                             const int64_t* a_off, const uint32_t* b, const int64_t* b_off,
+                             int64_t batch, bigint_plan_t plan) {
   if (!plan || plan->op != BIGINT_OP_MUL || batch != plan->batch) return BIGINT_EINVAL;
   if (batch == 0) return BIGINT_OK;
   if (!out || !out_off || !a || !a_off || !b || !b_off) return BIGINT_EINVAL;
@@ -637,6 +675,24 @@ int bigint_mul_ragged(uint32_t* out, const int64_t* out_off, const uint32_t* a,
   for (int64_t i = 0; i < batch; ++i) { ta += plan->la[i]; tb += plan->lb[i]; }
   const size_t ob = (size_t)(ta + tb) * 4;
   if (overlap(out, ob, a, (size_t)ta * 4) || overlap(out, ob, b, (size_t)tb * 4)) return BIGINT_EINVAL;
+  return BIGINT_OK;
+}
+
+int bigint_mul_ragged_segment(uint32_t* out, const int64_t* out_off, const uint32_t* a,
+                              const int64_t* a_off, const uint32_t* b, const int64_t* b_off,
+                              int64_t batch, bigint_plan_t plan, int segment, void* stream) {
+  const int rc = ragged_mul_checks(out, out_off, a, a_off, b, b_off, batch, plan);
+  if (rc != BIGINT_OK) return rc;
+  if (plan->plain || segment < 0 || segment >= (int)plan->cls.size()) return BIGINT_EINVAL;
+  return launch_mul_ragged(out, out_off, a, a_off, b, b_off, plan->d_queue, plan->cls.data() + segment,
+                           1, (hipStream_t)stream);
+}
+
+int bigint_mul_ragged(uint32_t* out, const int64_t* out_off, const uint32_t* a,
+                      const int64_t* a_off, const uint32_t* b, const int64_t* b_off, int64_t batch,
+                      bigint_plan_t plan, void* stream) {
+  const int rc = ragged_mul_checks(out, out_off, a, a_off, b, b_off, batch, plan);
+  if (rc != BIGINT_OK || batch == 0) return rc;
   hipStream_t s = (hipStream_t)stream;
   auto launch = [&](hipStream_t ls) {
     if (plan->plain)

@@ -85,6 +85,9 @@ def test_plan_argument_checks(bi):
     n = ctypes.c_size_t()
     assert L.bigint_plan_workspace_size(None, ctypes.byref(n)) == bi.EINVAL
     assert L.bigint_mul_ragged(None, None, None, None, None, None, 0, None, None) == bi.EINVAL
+    k = ctypes.c_int()
+    assert L.bigint_plan_segments(None, None, 0, ctypes.byref(k)) == bi.EINVAL
+    assert L.bigint_mul_ragged_segment(None, None, None, None, None, None, 0, None, 0, None) == bi.EINVAL
 
 
 def test_binding_fails_loudly_without_library(monkeypatch):

@@ -115,6 +115,38 @@ def test_ragged_4096_direct_launch(bi, ragged_4096):
     plan.close()
 
 
+def test_ragged_4096_segments_one_by_one(bi, ragged_4096):
+    """The plan's segment table covers the queue once, in order; launching
+    every segment alone, last first, into a cleared buffer gives every
+    product; a segment index out of range is refused."""
+    import torch
+    c = ragged_4096
+    lens = c["lens"]
+    plan = bi.MulPlan(lens, lens)
+    segs = plan.segments()
+    assert len(segs) == plan.info()["launches_per_call"] >= 1
+    assert segs[0]["first"] == 0
+    for s0, s1 in zip(segs, segs[1:]):
+        assert s1["first"] == s0["first"] + s0["instances"]
+    assert sum(s["instances"] for s in segs) == lens.size
+    for s in segs:
+        assert s["digit_bits"] in (7, 8) and s["strips_per_band"] in (4, 8, 16)
+        assert s["slots"] >= 256 and 0.0 < s["modelled_busy"] <= 1.0
+    # at least (4n)^2 digit products per instance (8-bit digits; 7-bit ones have more)
+    assert sum(s["digit_products"] for s in segs) >= int(((4 * lens.astype(np.int64)) ** 2).sum())
+    ta, tao = dev(c["a"]), torch.from_numpy(c["a_off"]).cuda()
+    tb, tbo = dev(c["b"]), torch.from_numpy(c["b_off"]).cuda()
+    out = torch.full((int(2 * lens.sum()),), -1, dtype=torch.int32, device="cuda")
+    oo = torch.from_numpy(c["out_off"]).cuda()
+    for k in reversed(range(len(segs))):
+        plan.run_segment(k, ta, tao, tb, tbo, out, oo)
+    torch.cuda.synchronize()
+    assert _first_bad_instance(host(out), c) is None
+    with pytest.raises(bi.BigIntError):
+        plan.run_segment(len(segs), ta, tao, tb, tbo, out, oo)
+    plan.close()
+
+
 def test_plan_errors(bi):
     import ctypes
     L = bi.lib()
