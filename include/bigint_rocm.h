@@ -204,7 +204,9 @@ int bigint_divmod_noalloc(uint32_t* q, uint32_t* r, int32_t* status,
 /* ---- plans for ragged batches ------------------------------------------------------
  * A plan fixes the instance sizes of a ragged batch (host arrays len_a, len_b
  * of `batch` limb counts; for DIVMOD len_a are the dividend and len_b the
- * divisor lengths), bins instances by cost, orders them largest first and
+ * divisor lengths), bins instances by cost, orders them largest first (a
+ * division plan reverses every other row of the work-groups resident at the
+ * start, so that the largest divisions share their CUs with the smallest) and
  * picks a tuned tile configuration per bin (from the autotune cache if one
  * was loaded, else built-in defaults).  Creating a plan allocates a small
  * device schedule; the plan owns it until bigint_plan_destroy.

@@ -569,6 +569,18 @@ static int plan_build_div(bigint_plan_s* p) {
   std::stable_sort(idx.begin(), idx.end(), [&](int64_t x, int64_t y) { return cost(x) > cost(y); });
   std::vector<int32_t> q(B);
   for (int64_t t = 0; t < B; ++t) q[t] = (int32_t)idx[t];
+  // The work-groups resident at the start land one per CU in rows: work-
+  // group j and j + R (R CUs) share a CU.  Reversing every other row (a
+  // snake over the largest-first order) pairs each of the largest divisions
+  // with one of the smallest, so the divisions that set the call's time
+  // share their CU the least (512 divisions of 2^16..2^18 bits: 0.402 ->
+  // 0.380 ms; pairing neighbours in the order instead: 0.45 ms).
+  {
+    const int64_t R = num_cus();
+    const int64_t e = std::min<int64_t>(B, R * div_groups_per_cu(p->cap_u, p->cap_v));
+    for (int64_t row = 1; row * R < e; row += 2)
+      std::reverse(q.begin() + row * R, q.begin() + std::min(e, (row + 1) * R));
+  }
   p->grid = div_chunk(p->cap_u, p->cap_v, B);
   p->n_launches = B > 0 ? (B + p->grid - 1) / p->grid : 0;
   if (B > 0) {
