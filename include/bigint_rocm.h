@@ -134,6 +134,16 @@ int bigint_sub(uint32_t* out, uint32_t* borrow_out, const uint32_t* a,
  *     conclusion names more elaborate multiplication algorithms as a next
  *     step.  The call allocates 5n limbs of workspace per instance on
  *     `stream` (stream-ordered) and frees it the same way.
+ * With fewer instances than the device has CUs and no configuration forced
+ * by bigint_set_mfma_config or bigint_set_mfma_tile, MFMA full products of
+ * at least eight 4-strip bands are split: each product's bands run on
+ * several work-groups (contiguous runs of about equal cost, as many as fill
+ * the CUs once, at least four bands each, and only where that gives at
+ * least four work-groups per instance), whose strip carry words go to a
+ * workspace of 8 bytes per strip and instance allocated and freed on
+ * `stream` (stream-ordered); a second launch resolves each instance's strip
+ * carries.  Same bytes as one work-group per instance
+ * (bigint_mfma_split_parts reports the split).
  * a: batch*na limbs, b: batch*nb limbs, out: batch*(na+nb) limbs.
  * na, nb >= 1.  MFMA needs na, nb <= BIGINT_MFMA_MAX_LIMBS (else
  * BIGINT_EUNSUPPORTED); PLAIN needs na+nb <= 32768; AUTO picks MFMA when it
@@ -382,6 +392,12 @@ int bigint_mfma_tile(int64_t na, int64_t nb);
  * wave, and always for bigint_mullo), if the LDS allows.  A wave count set with bigint_set_mfma_config is used at every
  * batch.  BIGINT_EUNSUPPORTED if the MFMA multiply does not take that
  * size with it; BIGINT_EINVAL for null pointers or sizes < 1. */
+/* Work-groups per instance that bigint_mul's MFMA path gives a batch of
+ * `batch` full na x nb products on the current device (1: one work-group
+ * per instance; more: the bands split as described at bigint_mul), written
+ * to the host int.  BIGINT_EINVAL for null pointers or sizes < 1. */
+int bigint_mfma_split_parts(int64_t na, int64_t nb, int64_t batch, int* parts);
+
 int bigint_mfma_config(int64_t na, int64_t nb, int* strips_per_band, int* waves,
                        int* digit_bits);
 

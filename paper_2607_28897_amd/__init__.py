@@ -91,6 +91,7 @@ def lib() -> ctypes.CDLL:
             "bigint_shinv": ([_vp, _vp, _i64, _i64, _i64, _vp], _int),
             "bigint_set_mfma_config": ([_int, _int, _int], _int),
             "bigint_mfma_config": ([_i64, _i64, _pint, _pint, _pint], _int),
+            "bigint_mfma_split_parts": ([_i64, _i64, _i64, _pint], _int),
             "bigint_set_mfma_tile": ([_int], _int),
             "bigint_mfma_tile": ([_i64, _i64], _int),
             "bigint_mullo": ([_vp, _vp, _vp, _i64, _i64, _vp], _int),
@@ -315,6 +316,14 @@ def mfma_config(na: int, nb: int):
     _check(lib().bigint_mfma_config(na, nb, ctypes.byref(p), ctypes.byref(w), ctypes.byref(d)),
            "bigint_mfma_config")
     return p.value, w.value, d.value
+
+
+def mfma_split_parts(na: int, nb: int, batch: int) -> int:
+    """Work-groups per instance bigint_mul's MFMA path uses for this batch."""
+    import ctypes
+    k = ctypes.c_int()
+    _check(lib().bigint_mfma_split_parts(na, nb, batch, ctypes.byref(k)), "bigint_mfma_split_parts")
+    return k.value
 
 
 def autotune(cache_path: str | None = None, flags: int = 0):

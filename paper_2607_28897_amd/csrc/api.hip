@@ -262,11 +262,39 @@ int bigint_mul(uint32_t* out, const uint32_t* a, int64_t na, const uint32_t* b, 
   if (use == BIGINT_MUL_MFMA) {
     if (!mfma_fits(na, nb, cfg)) return BIGINT_EUNSUPPORTED;
     if (batch == 0) return BIGINT_OK;
+    // fewer instances than CUs and no configuration forced: each product's
+    // bands split over several work-groups
+    int wstride = 0;
+    const bool forced = t_cfg_P || t_cfg_waves || t_cfg_dw || t_cfg_tile;
+    const int parts = forced ? 1 : mul_mfma_split_parts((int)na, (int)nb, batch, cfg.dw, &wstride);
+    if (parts > 1) {
+      hipStream_t s = (hipStream_t)stream;
+      void* ws = nullptr;
+      hipError_t e = hipMallocAsync(&ws, (size_t)batch * wstride * 8, s);
+      if (e != hipSuccess) { set_hip_error(e); return BIGINT_ENOMEM; }
+      const int rc = launch_mul_mfma_split(out, a, na, b, nb, batch, cfg.dw, parts,
+                                           reinterpret_cast<uint64_t*>(ws), wstride, s);
+      e = hipFreeAsync(ws, s);
+      if (rc != BIGINT_OK) return rc;
+      if (e != hipSuccess) { set_hip_error(e); return BIGINT_EHIP; }
+      return BIGINT_OK;
+    }
     return launch_mul_mfma(out, nullptr, a, na, b, nb, batch, cfg, (hipStream_t)stream);
   }
   if (na + nb > 32768) return BIGINT_EUNSUPPORTED;
   if (batch == 0) return BIGINT_OK;
   return launch_mul_plain(out, a, na, b, nb, batch, (hipStream_t)stream);
+}
+
+int bigint_mfma_split_parts(int64_t na, int64_t nb, int64_t batch, int* parts) {
+  if (na <= 0 || nb <= 0 || batch < 1 || !parts) return BIGINT_EINVAL;
+  *parts = 1;
+  if (na > BIGINT_MFMA_MAX_LIMBS || nb > BIGINT_MFMA_MAX_LIMBS) return BIGINT_OK;
+  const MfmaCfg cfg = uniform_mfma_cfg((int)na, (int)nb, batch, false);
+  if (!mfma_fits(na, nb, cfg) || t_cfg_P || t_cfg_waves || t_cfg_dw || t_cfg_tile) return BIGINT_OK;
+  int wstride = 0;
+  *parts = mul_mfma_split_parts((int)na, (int)nb, batch, cfg.dw, &wstride);
+  return BIGINT_OK;
 }
 
 int bigint_mullo(uint32_t* out, const uint32_t* a, const uint32_t* b, int64_t n, int64_t batch,

@@ -787,6 +787,55 @@ __device__ __forceinline__ void run_band(int band, const Lds& s, const Geo& g, u
     }
 }
 
+// The closing strip carry scan of an instance (whole work-group): carry[w]
+// holds strip w's carry word (bits 0-62) and tail flag (bit 63), out its
+// limbs, strips from w_first up; scratch: >= 16 words of LDS.
+template <int DW>
+__device__ __forceinline__ void close_strips(uint32_t* out, const Geo& g, const uint64_t* carry, int w_first,
+                                             uint32_t* scratch) {
+  constexpr int kStripLimbs = strip_limbs<DW>();
+  // out += sum_w C_w B^(L(w+1)), L limbs per strip.  Strip w' receives C_{w'-1} (< 2^35) on its
+  // limbs 0 and 1; a carry out of limb 1 runs on only through a tail of
+  // all-ones limbs.  So an exclusive carry scan over strips, one strip per
+  // thread, resolves everything: strip w' generates when limbs 0..1 plus
+  // C_{w'-1} overflow and its tail is all ones, and propagates when limbs
+  // 0..1 plus C_{w'-1} are all ones and so is its tail.
+  const uint64_t kC = (1ull << 63) - 1;
+  uint32_t cy = 0u;
+  for (int base = w_first; base < g.W; base += blockDim.x) {
+    const int w = base + threadIdx.x;
+    const bool valid = w < g.W;
+    const int j0 = kStripLimbs * (valid ? w : 0);
+    const uint32_t l0 = (valid && j0 < g.nout) ? out[j0] : 0u;
+    const uint32_t l1 = (valid && j0 + 1 < g.nout) ? out[j0 + 1] : 0u;
+    const uint64_t d = (valid && w > w_first) ? (carry[w - 1] & kC) : 0ull;
+    const bool ones = valid && (carry[w] >> 63);
+    const uint64_t x0 = ((uint64_t)l1 << 32) | l0;
+    const uint64_t x = x0 + d;
+    const bool xh = x < x0;  // carry out of limb 1
+    const bool gen = valid && xh && ones;
+    const bool prop = valid && !xh && x == ~0ull && ones;
+    uint32_t cout;
+    const uint32_t c = wg_carry_scan(gen, prop, cy, scratch, &cout);
+    cy = cout;
+    if (valid) {
+      const uint64_t y = x + c;
+      const bool yh = xh || (y < x);
+      if (y != x0) {
+        if (j0 < g.nout) out[j0] = (uint32_t)y;
+        if (j0 + 1 < g.nout) out[j0 + 1] = (uint32_t)(y >> 32);
+      }
+      if (yh) {  // ripple into the tail (stops at its first limb that is not all ones)
+        for (int j = j0 + 2; j < min(j0 + kStripLimbs, g.nout); ++j) {
+          const uint32_t v = out[j];
+          out[j] = v + 1u;
+          if (v != 0xffffffffu) break;
+        }
+      }
+    }
+  }
+}
+
 // First band of a product whose limbs below nlo are not needed: the strips
 // of the bands before it lie entirely below limb nlo - 2.  (The part of the
 // product they hold is below 2^34 B^(first strip's limb) <= B^nlo, so leaving
@@ -803,15 +852,22 @@ __host__ __device__ inline int high_band(int nlo, int P) {
 // one less, and the limbs below nlo are left as they were or wrong.  With
 // coef != nullptr (7-bit digits only, whole product) the raw coefficients
 // c_k (k < Na+Nb-1) are written instead.
+// nparts > 1 (full products, coef == nullptr, nlo == 0): this work-group is
+// part `part` of nparts sharing the instance.  The bands are cut into nparts
+// contiguous runs of about equal cost (band t goes to the part its cost
+// midpoint falls in); this part computes only its run, writes its strips'
+// carry words to carry_ext[w] (global memory, one word per strip) instead of
+// LDS and leaves the closing strip carry scan to close_strips once every
+// part has finished (a later launch).
 template <int DW, int P, int TS = 16>
 __device__ __forceinline__ void wg_mul_mfma(uint32_t* out, int32_t* coef, const uint32_t* __restrict__ a, int na,
                             const uint32_t* __restrict__ b, int nb, char* smem, int nout = -1,
-                            int nlo = 0) {
+                            int nlo = 0, int part = 0, int nparts = 1, uint64_t* carry_ext = nullptr) {
   static_assert(DW == 7 || DW == 8, "digit width");
   static_assert(TS == 16 || (TS == 32 && DW == 8 && P % 4 == 0), "32x32 tiles: 8-bit digits, whole tiles per band");
-  constexpr int kStripLimbs = strip_limbs<DW>();
   const Geo g = make_geo<DW, TS>(na, nb, coef ? -1 : nout);
-  const Lds s = carve(smem, g, P);
+  Lds s = carve(smem, g, P);
+  if (nparts > 1) s.carry = carry_ext;
   const int NBall = (g.W + P - 1) / P;
   // bands [band_lo, NBall) are computed; strips from w_first up
   const int band_lo = coef ? 0 : min(high_band<DW>(nlo, P), NBall);
@@ -831,14 +887,37 @@ __device__ __forceinline__ void wg_mul_mfma(uint32_t* out, int32_t* coef, const 
     s.scr[t] = TS == 32 ? band_cost32(g, band_lo + t, P) : band_cost(g, band_lo + t, P);
   if (threadIdx.x == 0) s.misc[0] = 0;
   __syncthreads();
-  for (int t = threadIdx.x; t < NB; t += blockDim.x) {
-    const int c = s.scr[t];
+  // this part's bands [pb0, pb1) (all of them for a whole instance)
+  int pb0 = 0, pb1 = NB;
+  if (nparts > 1) {
+    if (threadIdx.x == 0) {
+      int64_t tot = 0;
+      for (int t = 0; t < NB; ++t) tot += s.scr[t];
+      int64_t acc = 0;
+      int b0 = NB, b1 = NB;
+      for (int t = 0; t < NB; ++t) {
+        const int64_t c2 = 2 * acc + s.scr[t];   // twice the cost midpoint
+        const int pt = tot > 0 ? (int)min<int64_t>(nparts - 1, c2 * nparts / (2 * tot)) : 0;
+        if (pt >= part && b0 == NB) b0 = t;
+        if (pt > part && b1 == NB) b1 = t;
+        acc += s.scr[t];
+      }
+      s.misc[1] = (uint32_t)b0;
+      s.misc[2] = (uint32_t)max(b0, b1);
+    }
+    __syncthreads();
+    pb0 = (int)s.misc[1];
+    pb1 = (int)s.misc[2];
+  }
+  const int PN = pb1 - pb0;
+  for (int t = threadIdx.x; t < PN; t += blockDim.x) {
+    const int c = s.scr[pb0 + t];
     int rank = 0;
-    for (int u2 = 0; u2 < NB; ++u2) {
-      const int cu = s.scr[u2];
+    for (int u2 = 0; u2 < PN; ++u2) {
+      const int cu = s.scr[pb0 + u2];
       rank += (cu > c) || (cu == c && u2 < t);
     }
-    s.order[rank] = (uint16_t)t;
+    s.order[rank] = (uint16_t)(pb0 + t);
   }
   __syncthreads();
 
@@ -846,54 +925,13 @@ __device__ __forceinline__ void wg_mul_mfma(uint32_t* out, int32_t* coef, const 
     uint32_t t = 0;
     if (lane_id() == 0) t = atomicAdd(&s.misc[0], 1u);
     t = __builtin_amdgcn_readfirstlane(t);
-    if ((int)t >= NB) break;
+    if ((int)t >= PN) break;
     const int band = band_lo + __builtin_amdgcn_readfirstlane((int)s.order[t]);
     if constexpr (TS == 32) run_band32<P>(band, s, g, out);
     else run_band<DW, P>(band, s, g, out, coef);
   }
   __syncthreads();
-  if (coef == nullptr) {
-    // out += sum_w C_w B^(L(w+1)), L limbs per strip.  Strip w' receives C_{w'-1} (< 2^35) on its
-    // limbs 0 and 1; a carry out of limb 1 runs on only through a tail of
-    // all-ones limbs.  So an exclusive carry scan over strips, one strip per
-    // thread, resolves everything: strip w' generates when limbs 0..1 plus
-    // C_{w'-1} overflow and its tail is all ones, and propagates when limbs
-    // 0..1 plus C_{w'-1} are all ones and so is its tail.
-    const uint64_t kC = (1ull << 63) - 1;
-    uint32_t carry = 0u;
-    for (int base = w_first; base < g.W; base += blockDim.x) {
-      const int w = base + threadIdx.x;
-      const bool valid = w < g.W;
-      const int j0 = kStripLimbs * (valid ? w : 0);
-      const uint32_t l0 = (valid && j0 < g.nout) ? out[j0] : 0u;
-      const uint32_t l1 = (valid && j0 + 1 < g.nout) ? out[j0 + 1] : 0u;
-      const uint64_t d = (valid && w > w_first) ? (s.carry[w - 1] & kC) : 0ull;
-      const bool ones = valid && (s.carry[w] >> 63);
-      const uint64_t x0 = ((uint64_t)l1 << 32) | l0;
-      const uint64_t x = x0 + d;
-      const bool xh = x < x0;  // carry out of limb 1
-      const bool gen = valid && xh && ones;
-      const bool prop = valid && !xh && x == ~0ull && ones;
-      uint32_t cout;
-      const uint32_t c = wg_carry_scan(gen, prop, carry, s.misc + 1, &cout);
-      carry = cout;
-      if (valid) {
-        const uint64_t y = x + c;
-        const bool yh = xh || (y < x);
-        if (y != x0) {
-          if (j0 < g.nout) out[j0] = (uint32_t)y;
-          if (j0 + 1 < g.nout) out[j0 + 1] = (uint32_t)(y >> 32);
-        }
-        if (yh) {  // ripple into the tail (stops at its first limb that is not all ones)
-          for (int j = j0 + 2; j < min(j0 + kStripLimbs, g.nout); ++j) {
-            const uint32_t v = out[j];
-            out[j] = v + 1u;
-            if (v != 0xffffffffu) break;
-          }
-        }
-      }
-    }
-  }
+  if (coef == nullptr && nparts == 1) close_strips<DW>(out, g, s.carry, w_first, s.misc + 1);
   __syncthreads();
 }
 
