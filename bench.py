@@ -262,6 +262,7 @@ def main():
     }
     line["mfma_7bit"] = seven_bit_leg(torch, bi, mul_call, out_m, batch, n, args)
     line["karatsuba"] = karatsuba_leg(torch, bi, mul_call, out_m, batch, args)
+    line["small_batches"] = small_batch_leg(torch, bi, a, b, out_m, n, args)
     line["ragged_4096"] = ragged_leg(torch, bi, inputs, args)
     line["divmod_512"] = divmod_leg(torch, bi, inputs, args)
     if not args.no_cpu:
@@ -309,6 +310,24 @@ def karatsuba_leg(torch, bi, mul_call, ref, batch, args):
             "steps": steps,
             "what": "one Karatsuba level (three 2^18-bit products per pair) over the same MFMA-split multiply",
             "equals_mfma": bool(torch.equal(out, ref))}
+
+
+def small_batch_leg(torch, bi, a, b, ref, n, args):
+    """The first 1 and 16 pairs of the same 2^19-bit batch alone: each
+    product's bands split over several work-groups (k_mul_mfma_part, then
+    k_mul_mfma_close); both equal the batch's products.  (One work-group per
+    product takes about 0.52 ms for either, the headline kernel's time.)"""
+    out = []
+    steps = max(10, args.steps // 2)
+    for k in (x for x in (1, 16) if x <= a.shape[0]):
+        ta, tb = a[:k].contiguous(), b[:k].contiguous()
+        p = bi.mul(ta, tb, bi.MUL_MFMA)
+        total, _ = time_launches(lambda: bi.mul(ta, tb, bi.MUL_MFMA), steps, 2, torch)
+        ms = total / steps
+        out.append({"products": k, "parts_per_product": bi.mfma_split_parts(n, n, k), "ms": round(ms, 4),
+                    "equal": bool(torch.equal(p, ref[:k]))})
+        print(f"# {k} products alone: {ms:.4f} ms (split)", file=sys.stderr, flush=True)
+    return out
 
 
 def ragged_leg(torch, bi, inputs, args):
