@@ -69,6 +69,10 @@ def test_host_side_argument_checks(bi):
     assert L.bigint_set_mfma_config(0, 0, 6) == EINVAL
     assert L.bigint_digits7(None, p, 4, 5, 1, None) == EINVAL
     assert L.bigint_diag_mfma_rate(None, 1, 1, 0, None) == EINVAL
+    k = ctypes.c_int()
+    assert L.bigint_mfma_split_parts(16384, 16384, 1, None) == EINVAL
+    assert L.bigint_mfma_split_parts(0, 16384, 1, ctypes.byref(k)) == EINVAL
+    assert L.bigint_mfma_split_parts(16384, 16384, 0, ctypes.byref(k)) == EINVAL
 
 
 def test_plan_argument_checks(bi):
