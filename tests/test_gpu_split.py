@@ -25,7 +25,8 @@ def bi():
 # (batch, na, nb): one 2^19-bit product, the largest operands, unequal
 # operands, ragged strip counts, and batches up to a quarter of the CU count
 CASES = [(1, 16384, 16384), (1, 18432, 18432), (2, 16384, 1000), (3, 5000, 5000), (7, 4096, 3001),
-         (17, 2048, 2048), (60, 3000, 2000), (64, 4096, 4096), (64, 16384, 16384)]
+         (17, 2048, 2048), (60, 3000, 2000), (64, 4096, 4096), (64, 16384, 16384),
+         (1, 16384, 1), (3, 2, 12000)]
 
 
 @pytest.mark.parametrize("batch,na,nb", CASES)
@@ -35,7 +36,7 @@ def test_split_every_instance(bi, orc, batch, na, nb):
     b = rand_limbs(g, batch, nb)
     a[0] = 0xFFFFFFFF                      # carries through whole strips
     b[0] = 0xFFFFFFFF
-    if batch > 1:
+    if batch > 1 and nb > 1:
         b[1, 1:] = 0                       # a * small: long all-ones and zero runs
         b[1, 0] = 3
     assert bi.mfma_split_parts(na, nb, batch) >= 4
