@@ -360,7 +360,8 @@ def ragged_leg(torch, bi, inputs, args):
         t, _ = time_launches(lambda: plan.run_segment(k, ta, tao, tb, tbo, out, oo), steps, args.warmup,
                              torch)
         sms = t / steps
-        segs.append({"instances": sg["instances"], "digit_bits": sg["digit_bits"],
+        segs.append({"instances": sg["instances"], "parts_per_instance": sg["parts"],
+                     "digit_bits": sg["digit_bits"],
                      "strips_per_band": sg["strips_per_band"], "waves": sg["waves"],
                      "resident_work_groups": sg["slots"], "ms": round(sms, 4),
                      "frac": round(2.0 * sg["digit_products"] / (sms * 1e-3) / 1e12 / INT8_PEAK_TOPS, 4),
@@ -417,7 +418,21 @@ def divmod_leg(torch, bi, inputs, args):
             "roofline": mfma_roofline(2.0 * macs, ms, f"2 int8 ops per digit product the division's MFMA "
                                                     f"products compute, {2.0 * macs:.4g} per call"),
             "newton_steps_histogram": hist(0), "negative_branch_steps_histogram": hist(1),
-            "quotient_corrections_histogram": hist(2)}
+            "quotient_corrections_histogram": hist(2),
+            "critical_path": critical_path(cnt[:, 3], ms)}
+
+
+def critical_path(div_macs, ms):
+    """The call's time is the latency of its largest division, which runs on
+    one work-group (one CU): that division's MFMA multiply-accumulates at one
+    CU's share of the int8 peak, against the call time."""
+    top = float(np.max(div_macs))
+    cu_macs_per_s = INT8_PEAK_TOPS * 1e12 / 2 / 256
+    us = top / cu_macs_per_s * 1e6
+    return {"largest_division_macs": top, "at_one_cu_peak_us": round(us, 1),
+            "frac_of_call": round(us / (ms * 1e3), 3),
+            "what": "one division per work-group: the batch cannot finish before its largest division, "
+                    "whose products run on one CU"}
 
 
 def copy_mode(torch):

@@ -221,8 +221,10 @@ int bigint_divmod_noalloc(uint32_t* q, uint32_t* r, int32_t* status,
  * was loaded, else built-in defaults).  Creating a plan allocates a small
  * device schedule; the plan owns it until bigint_plan_destroy.
  * Workspace: bigint_plan_workspace_size reports the device scratch a call
- * needs; pass a buffer of at least that size with bigint_plan_set_workspace,
- * otherwise the first call allocates one (owned by the plan).
+ * needs (a multiply plan needs some only when a segment is split: 8 bytes per
+ * strip of its instances); pass a buffer of at least that size with
+ * bigint_plan_set_workspace, otherwise the first call allocates one (owned
+ * by the plan).
  * A plan must not be used by two streams at once. */
 int bigint_plan_create(bigint_plan_t* plan, int op, const int64_t* len_a,
                        const int64_t* len_b, int64_t batch, int flags);
@@ -254,13 +256,16 @@ int bigint_mul_ragged(uint32_t* out, const int64_t* out_off, const uint32_t* a,
 /* The segments of a ragged multiply plan (diagnostic): *n_segments = the
  * launches one bigint_mul_ragged call makes on the MFMA-split path (0 for a
  * plain or division plan), and for segment k < max_segments the host int64
- * row seg[8k .. 8k+8): [0] first queue position (queue = instances largest
+ * row seg[9k .. 9k+9): [0] first queue position (queue = instances largest
  * first), [1] instances, [2] digit bits, [3] strips per band of its leading
  * configuration, [4] waves per work-group, [5] work-groups resident at once,
  * [6] digit products its instances compute (sum of Na*Nb at its digit width),
  * [7] modelled busy fraction in parts per million: the segment's cost (sum
  * of la*lb) over resident work-groups times the span of the plan's largest-
- * first list schedule.  The plan's load-balance figure per launch. */
+ * first list schedule, [8] work-groups per instance: 1, or the parts of a
+ * segment of few instances whose bands are split as bigint_mul splits a
+ * small batch (then 4 strips per band and 4 waves, and two launches).  The
+ * plan's load-balance figure per launch. */
 int bigint_plan_segments(bigint_plan_t plan, int64_t* seg, int max_segments,
                          int* n_segments);
 

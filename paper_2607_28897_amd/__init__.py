@@ -408,19 +408,20 @@ class MulPlan(_Plan):
         return out, out_off
 
     def segments(self) -> list:
-        """The plan's launches on the MFMA-split path, one dict per segment:
+        """The plan's segments on the MFMA-split path, one dict per segment:
         first queue position, instances, digit bits, strips per band, waves,
-        resident work-groups, digit products, modelled busy fraction."""
+        resident work-groups, digit products, modelled busy fraction, and
+        work-groups per instance (parts > 1: bands split, two launches)."""
         import numpy as np
         n = ctypes.c_int()
         _check(lib().bigint_plan_segments(self._h, None, 0, ctypes.byref(n)), "bigint_plan_segments")
-        v = np.zeros((max(n.value, 1), 8), np.int64)
+        v = np.zeros((max(n.value, 1), 9), np.int64)
         _check(lib().bigint_plan_segments(self._h, v.ctypes.data_as(ctypes.c_void_p), n.value,
                                           ctypes.byref(n)), "bigint_plan_segments")
         keys = ("first", "instances", "digit_bits", "strips_per_band", "waves", "slots",
                 "digit_products")
-        return [dict({k: int(x) for k, x in zip(keys, row[:7])}, modelled_busy=float(row[7]) / 1e6)
-                for row in v[:n.value]]
+        return [dict({k: int(x) for k, x in zip(keys, row[:7])}, modelled_busy=float(row[7]) / 1e6,
+                     parts=int(row[8])) for row in v[:n.value]]
 
     def run_segment(self, k, a, a_off, b, b_off, out, out_off):
         """Launch only segment k (no graph) into out."""

@@ -566,14 +566,46 @@ static int plan_build_mul(bigint_plan_s* p) {
       cls.push_back(k);
       pos = end;
     }
+    // A segment of few instances leaves most CUs idle however it is
+    // ordered: split every instance's bands over several work-groups, as a
+    // small uniform batch is (parts: enough to fill the CUs once, at most a
+    // quarter of the largest instance's 4-strip bands, at least four), with
+    // the strips' carry words in the plan's workspace.
+    const int R = num_cus();
+    int64_t ws_words = 0;
+    for (RaggedClass& k : cls) {
+      if ((int64_t)k.count * 4 > R) continue;
+      const int dw = k.cfg >= 3 ? 8 : 7;
+      int wmax = 0, w0 = 0;
+      size_t lmax = 0;
+      for (int t = k.first; t < k.first + k.count; ++t) {
+        const int64_t i = q[t].inst;
+        int w;
+        size_t l;
+        ragged_split_geo((int)p->la[i], (int)p->lb[i], dw, &w, &l);
+        if (t == k.first) w0 = w;   // the largest instance
+        wmax = std::max(wmax, w);
+        lmax = std::max(lmax, l);
+      }
+      const int parts = (int)std::min<int64_t>((R + k.count - 1) / k.count, ((w0 + 3) / 4) / 4);
+      if (parts < 4 || lmax > 163840) continue;
+      k.parts = parts;
+      k.wstride = wmax;
+      k.split_lds = lmax;
+      k.ws_off = ws_words;
+      ws_words += (int64_t)k.count * wmax;
+    }
     p->cls = cls;
+    p->ws_need = (size_t)ws_words * 8;
   }
-  p->n_launches = plain ? (B > 0 ? 1 : 0) : (int64_t)p->cls.size();
+  p->n_launches = 0;
+  if (plain) p->n_launches = B > 0 ? 1 : 0;
+  for (const RaggedClass& k : p->cls) p->n_launches += k.parts > 1 ? 2 : 1;
   if (B > 0) {
     BI_HIP(hipMalloc(&p->d_queue, sizeof(QueueItem) * B));
     BI_HIP(hipMemcpy(p->d_queue, q.data(), sizeof(QueueItem) * B, hipMemcpyHostToDevice));
   }
-  p->ws_need = 0;  // the multiply needs no workspace beyond LDS
+  if (plain || B == 0) p->ws_need = 0;  // otherwise set with the segments
   return BIGINT_OK;
 }
 
@@ -692,7 +724,7 @@ int bigint_plan_segments(bigint_plan_t plan, int64_t* seg, int max_segments, int
   *n_segments = n;
   for (int k = 0; k < std::min(n, max_segments); ++k) {
     const RaggedClass& c = plan->cls[k];
-    int64_t* o = seg + 8 * k;
+    int64_t* o = seg + 9 * k;
     o[0] = c.first;
     o[1] = c.count;
     o[2] = c.cfg >= 3 ? 8 : 7;
@@ -701,6 +733,7 @@ int bigint_plan_segments(bigint_plan_t plan, int64_t* seg, int max_segments, int
     o[5] = plan->seg_slots[k];
     o[6] = plan->seg_products[k];
     o[7] = (int64_t)std::llround(1e6 * plan->seg_busy[k]);
+    o[8] = c.parts;
   }
   return BIGINT_OK;
 }
@@ -718,32 +751,43 @@ static int ragged_mul_checks(uint32_t* out, const int64_t* out_off, const uint32
   return BIGINT_OK;
 }
 
+// the plan's workspace, allocated (and owned) on first use if none was set
+static int plan_ws(bigint_plan_t plan) {
+  if (plan->ws_need == 0 || plan->ws) return BIGINT_OK;
+  BI_HIP(hipMalloc(&plan->ws, plan->ws_need));
+  plan->ws_bytes = plan->ws_need;
+  plan->ws_owned = true;
+  return BIGINT_OK;
+}
+
 int bigint_mul_ragged_segment(uint32_t* out, const int64_t* out_off, const uint32_t* a,
                               const int64_t* a_off, const uint32_t* b, const int64_t* b_off,
                               int64_t batch, bigint_plan_t plan, int segment, void* stream) {
-  const int rc = ragged_mul_checks(out, out_off, a, a_off, b, b_off, batch, plan);
+  int rc = ragged_mul_checks(out, out_off, a, a_off, b, b_off, batch, plan);
   if (rc != BIGINT_OK) return rc;
   if (plan->plain || segment < 0 || segment >= (int)plan->cls.size()) return BIGINT_EINVAL;
+  if ((rc = plan_ws(plan)) != BIGINT_OK) return rc;
   return launch_mul_ragged(out, out_off, a, a_off, b, b_off, plan->d_queue, plan->cls.data() + segment,
-                           1, (hipStream_t)stream);
+                           1, plan->ws, (hipStream_t)stream);
 }
 
 int bigint_mul_ragged(uint32_t* out, const int64_t* out_off, const uint32_t* a,
                       const int64_t* a_off, const uint32_t* b, const int64_t* b_off, int64_t batch,
                       bigint_plan_t plan, void* stream) {
-  const int rc = ragged_mul_checks(out, out_off, a, a_off, b, b_off, batch, plan);
+  int rc = ragged_mul_checks(out, out_off, a, a_off, b, b_off, batch, plan);
   if (rc != BIGINT_OK || batch == 0) return rc;
+  if ((rc = plan_ws(plan)) != BIGINT_OK) return rc;
   hipStream_t s = (hipStream_t)stream;
   auto launch = [&](hipStream_t ls) {
     if (plan->plain)
       return launch_mul_plain_ragged(out, out_off, a, a_off, b, b_off, plan->d_queue, batch,
                                      plan->lds, ls);
     return launch_mul_ragged(out, out_off, a, a_off, b, b_off, plan->d_queue, plan->cls.data(),
-                             (int)plan->cls.size(), ls);
+                             (int)plan->cls.size(), plan->ws, ls);
   };
   if (plan->flags & BIGINT_PLAN_NO_GRAPH) return launch(s);
-  const void* key[6] = {out, out_off, a, a_off, b, b_off};
-  return plan_graph_call(plan, key, 6, launch, s);
+  const void* key[7] = {out, out_off, a, a_off, b, b_off, plan->ws};
+  return plan_graph_call(plan, key, 7, launch, s);
 }
 
 // ---- division ------------------------------------------------------------------

@@ -75,14 +75,24 @@ struct RaggedClass {
   int first;      // first queue entry of the segment
   int count;      // entries
   size_t lds;     // dynamic LDS bytes (largest instance of the segment)
+  // parts > 1: every instance's bands split over `parts` work-groups (few
+  // instances; the split configuration, 4 strips per band and 4 waves),
+  // carry words at workspace words [ws_off + t * wstride ..) for entry t
+  int parts = 1;
+  int64_t ws_off = 0;
+  int wstride = 0;
+  size_t split_lds = 0;
 };
+// strips and part-kernel LDS of one instance of a split ragged segment
+void ragged_split_geo(int na, int nb, int dw, int* strips, size_t* lds);
 
 // work-groups of the segment kernel resident on the device at once (0: the
 // configuration or LDS size is not supported)
 int ragged_slots(int cfg_id, int waves, size_t lds);
 int launch_mul_ragged(uint32_t* out, const int64_t* out_off, const uint32_t* a,
                       const int64_t* a_off, const uint32_t* b, const int64_t* b_off,
-                      const QueueItem* queue, const RaggedClass* cls, int ncls, hipStream_t s);
+                      const QueueItem* queue, const RaggedClass* cls, int ncls, void* ws,
+                      hipStream_t s);
 int launch_mul_plain_ragged(uint32_t* out, const int64_t* out_off, const uint32_t* a,
                             const int64_t* a_off, const uint32_t* b, const int64_t* b_off,
                             const QueueItem* queue, int64_t nitems, size_t lds, hipStream_t s);

@@ -398,6 +398,18 @@ int mul_mfma_split_parts(int na, int nb, int64_t batch, int dw, int* wstride) {
   return k >= 4 ? k : 1;
 }
 
+// The split configuration for one instance of a ragged segment: strips
+// (carry words) and the part kernel's LDS.
+void ragged_split_geo(int na, int nb, int dw, int* strips, size_t* lds) {
+  if (dw == 8) {
+    *strips = mfma::make_geo<8>(na, nb, na + nb).W;
+    *lds = mfma::lds_bytes<8>(na, nb, kSplitWaves, kSplitP);
+  } else {
+    *strips = mfma::make_geo<7>(na, nb, na + nb).W;
+    *lds = mfma::lds_bytes<7>(na, nb, kSplitWaves, kSplitP);
+  }
+}
+
 int launch_mul_mfma_split(uint32_t* out, const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb,
                           int64_t batch, int dw, int nparts, uint64_t* ws, int wstride,
                           hipStream_t s) {
@@ -801,6 +813,36 @@ __global__ __launch_bounds__(512) void k_mul_mfma_ragged(uint32_t* out, const in
   }
 }
 
+// A ragged segment of few instances split like a small uniform batch
+// (k_mul_mfma_part): part blockIdx.x of queue entry blockIdx.y, carry words
+// at ws[blockIdx.y * wstride + w]; then k_mul_mfma_close_ragged per entry.
+template <int DW>
+__global__ __launch_bounds__(64 * kSplitWaves) void k_mul_mfma_part_ragged(
+    uint32_t* out, const int64_t* out_off, const uint32_t* a, const int64_t* a_off, const uint32_t* b,
+    const int64_t* b_off, const QueueItem* queue, int nparts, uint64_t* ws, int wstride) {
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  const int t = blockIdx.y;
+  const int64_t i = __builtin_amdgcn_readfirstlane(queue[t].inst);
+  const int na = (int)(a_off[i + 1] - a_off[i]);
+  const int nb = (int)(b_off[i + 1] - b_off[i]);
+  mfma::wg_mul_mfma<DW, kSplitP>(out + out_off[i], nullptr, a + a_off[i], na, b + b_off[i], nb, smem, na + nb,
+                                 0, (int)blockIdx.x, nparts, ws + (int64_t)t * wstride);
+}
+
+template <int DW>
+__global__ __launch_bounds__(1024) void k_mul_mfma_close_ragged(uint32_t* out, const int64_t* out_off,
+                                                                const int64_t* a_off, const int64_t* b_off,
+                                                                const QueueItem* queue, const uint64_t* ws,
+                                                                int wstride) {
+  __shared__ uint32_t scratch[32];
+  const int t = blockIdx.x;
+  const int64_t i = __builtin_amdgcn_readfirstlane(queue[t].inst);
+  const int na = (int)(a_off[i + 1] - a_off[i]);
+  const int nb = (int)(b_off[i + 1] - b_off[i]);
+  const mfma::Geo g = mfma::make_geo<DW>(na, nb, na + nb);
+  mfma::close_strips<DW>(out + out_off[i], g, ws + (int64_t)t * wstride, 0, scratch);
+}
+
 __global__ __launch_bounds__(1024) void k_mul_plain_ragged(uint32_t* out, const int64_t* out_off,
                                                            const uint32_t* a, const int64_t* a_off,
                                                            const uint32_t* b, const int64_t* b_off,
@@ -977,11 +1019,37 @@ static void launch_ragged_class(const RaggedClass& c, uint32_t* out, const int64
                      out_off, a, a_off, b, b_off, queue + c.first, c.count);
 }
 
+template <int DW>
+static int launch_ragged_split(const RaggedClass& c, uint32_t* out, const int64_t* out_off, const uint32_t* a,
+                               const int64_t* a_off, const uint32_t* b, const int64_t* b_off,
+                               const QueueItem* queue, uint64_t* ws, hipStream_t s) {
+  BI_HIP(hipFuncSetAttribute((const void*)k_mul_mfma_part_ragged<DW>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)c.split_lds));
+  hipLaunchKernelGGL(k_mul_mfma_part_ragged<DW>, dim3((unsigned)c.parts, (unsigned)c.count),
+                     dim3(64 * kSplitWaves), c.split_lds, s, out, out_off, a, a_off, b, b_off,
+                     queue + c.first, c.parts, ws + c.ws_off, c.wstride);
+  BI_LAUNCH_CHECK();
+  const unsigned threads = (unsigned)std::min(1024, (c.wstride + 63) / 64 * 64);
+  hipLaunchKernelGGL(k_mul_mfma_close_ragged<DW>, dim3((unsigned)c.count), dim3(threads), 0, s, out,
+                     out_off, a_off, b_off, queue + c.first, ws + c.ws_off, c.wstride);
+  BI_LAUNCH_CHECK();
+  return BIGINT_OK;
+}
+
 int launch_mul_ragged(uint32_t* out, const int64_t* out_off, const uint32_t* a,
                       const int64_t* a_off, const uint32_t* b, const int64_t* b_off,
-                      const QueueItem* queue, const RaggedClass* cls, int ncls, hipStream_t s) {
+                      const QueueItem* queue, const RaggedClass* cls, int ncls, void* ws_v,
+                      hipStream_t s) {
+  uint64_t* ws = reinterpret_cast<uint64_t*>(ws_v);
   for (int k = 0; k < ncls; ++k) {
     const RaggedClass& c = cls[k];
+    if (c.parts > 1) {
+      if (!ws || c.split_lds > 163840) return BIGINT_EINVAL;
+      const int rc = c.cfg >= 3 ? launch_ragged_split<8>(c, out, out_off, a, a_off, b, b_off, queue, ws, s)
+                                : launch_ragged_split<7>(c, out, out_off, a, a_off, b, b_off, queue, ws, s);
+      if (rc != BIGINT_OK) return rc;
+      continue;
+    }
     const void* kern = ragged_kernel(c.cfg);
     if (!kern || c.lds > 163840) return BIGINT_EUNSUPPORTED;
     if (c.count < 1) continue;

@@ -124,7 +124,9 @@ def test_ragged_4096_segments_one_by_one(bi, ragged_4096):
     lens = c["lens"]
     plan = bi.MulPlan(lens, lens)
     segs = plan.segments()
+    assert all(s["parts"] == 1 for s in segs)               # many instances: none split
     assert len(segs) == plan.info()["launches_per_call"] >= 1
+    assert plan.workspace_size() == 0
     assert segs[0]["first"] == 0
     for s0, s1 in zip(segs, segs[1:]):
         assert s1["first"] == s0["first"] + s0["instances"]
@@ -144,6 +146,72 @@ def test_ragged_4096_segments_one_by_one(bi, ragged_4096):
     assert _first_bad_instance(host(out), c) is None
     with pytest.raises(bi.BigIntError):
         plan.run_segment(len(segs), ta, tao, tb, tbo, out, oo)
+    plan.close()
+
+
+def _few_large(g):
+    # a few large products (some far from square) among small ones
+    la = np.array([16384, 16000, 12000, 9000, 18432, 3000, 500, 7, 1, 2048, 14000, 6000], np.int64)
+    lb = np.array([16384, 15000, 11000, 9500, 1, 3333, 40, 7000, 1, 2048, 200, 6000], np.int64)
+    a, a_off = _ragged(g, la)
+    b, b_off = _ragged(g, lb)
+    a[a_off[0]:a_off[1]] = 0xFFFFFFFF      # carries through whole strips
+    b[b_off[0]:b_off[1]] = 0xFFFFFFFF
+    return la, lb, a, a_off, b, b_off
+
+
+@pytest.mark.parametrize("flags", [0, 2])   # graph, direct launch
+def test_ragged_few_large_instances_split(bi, orc, flags):
+    """A plan whose largest segment holds a few instances splits their bands
+    over work-groups (parts > 1, two launches, the plan's workspace): every
+    product against the oracle, on the first call and on replays into a
+    cleared buffer, and each segment launched alone."""
+    import torch
+    g = np.random.default_rng(123 + flags)
+    la, lb, a, a_off, b, b_off = _few_large(g)
+    plan = bi.MulPlan(la, lb, flags)
+    segs = plan.segments()
+    assert any(s["parts"] >= 4 for s in segs), segs
+    assert plan.info()["launches_per_call"] == sum(2 if s["parts"] > 1 else 1 for s in segs)
+    assert plan.workspace_size() > 0
+    want = oracle_map(lambda i: orc.mul1(a[a_off[i]:a_off[i + 1]], b[b_off[i]:b_off[i + 1]]),
+                      range(la.size))
+    ta, tao = dev(a), torch.from_numpy(a_off).cuda()
+    tb, tbo = dev(b), torch.from_numpy(b_off).cuda()
+    out_off = np.zeros(la.size + 1, np.int64)
+    np.cumsum(la + lb, out=out_off[1:])
+    oo = torch.from_numpy(out_off).cuda()
+    out = torch.empty(int(out_off[-1]), dtype=torch.int32, device="cuda")
+    for rep in range(3):
+        out.fill_(-1)
+        plan(ta, tao, tb, tbo, out=out, out_off=oo)
+        res = host(out)
+        for i in range(la.size):
+            assert np.array_equal(res[out_off[i]:out_off[i + 1]], want[i]), (rep, i)
+    out.fill_(-1)
+    for k in reversed(range(len(segs))):
+        plan.run_segment(k, ta, tao, tb, tbo, out, oo)
+    res = host(out)
+    for i in range(la.size):
+        assert np.array_equal(res[out_off[i]:out_off[i + 1]], want[i]), ("segments", i)
+    plan.close()
+
+
+def test_ragged_split_with_caller_workspace(bi, orc):
+    """The same plan with a workspace the caller provides (too small: refused)."""
+    import torch
+    g = np.random.default_rng(321)
+    la, lb, a, a_off, b, b_off = _few_large(g)
+    plan = bi.MulPlan(la, lb)
+    need = plan.workspace_size()
+    with pytest.raises(bi.BigIntError):
+        plan.set_workspace(torch.empty(need // 4 - 1, dtype=torch.int32, device="cuda"))
+    plan.set_workspace(torch.zeros(need // 4 + 16, dtype=torch.int32, device="cuda"))
+    out, oo = plan(dev(a), torch.from_numpy(a_off).cuda(), dev(b), torch.from_numpy(b_off).cuda())
+    res = host(out)
+    off = oo.cpu().numpy()
+    for i in range(la.size):
+        assert np.array_equal(res[off[i]:off[i + 1]], orc.mul1(a[a_off[i]:a_off[i + 1]], b[b_off[i]:b_off[i + 1]])), i
     plan.close()
 
 
