@@ -792,8 +792,9 @@ def cpu_oracle_mode(inputs, args):
 
 def kernel_sha():
     """Hash of the sources of the uniform MFMA multiply kernel k_mul_mfma (its
-    device headers and its own definition and launcher in kernels.hip), to
-    know whether counters taken earlier still describe the current kernel."""
+    device headers, and its definition and launchers in kernels.hip up to the
+    split-product code that follows them), to know whether counters taken
+    earlier still describe the current kernel."""
     import hashlib
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2607_28897_amd", "csrc")
@@ -803,7 +804,7 @@ def kernel_sha():
     with open(os.path.join(d, "kernels.hip"), "r") as fh:
         src = fh.read()
     i = src.index("__global__ __launch_bounds__(512) void k_mul_mfma(")
-    j = src.index("// coef != nullptr (raw coefficients)", i)
+    j = src.index("// ---- fewer products than CUs", i)
     h.update(src[i:j].encode())
     return h.hexdigest()[:16]
 
