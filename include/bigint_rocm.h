@@ -136,7 +136,7 @@ int bigint_sub(uint32_t* out, uint32_t* borrow_out, const uint32_t* a,
  *     `stream` (stream-ordered) and frees it the same way.
  * With fewer instances than the device has CUs and no configuration forced
  * by bigint_set_mfma_config or bigint_set_mfma_tile, MFMA full products of
- * at least eight 4-strip bands are split: each product's bands run on
+ * at least 32 4-strip bands (128 strips) are split: each product's bands run on
  * several work-groups (contiguous runs of about equal cost, as many as fill
  * the CUs once, at least four bands each, and only where that gives at
  * least four work-groups per instance), whose strip carry words go to a
@@ -155,6 +155,8 @@ int bigint_mul(uint32_t* out, const uint32_t* a, int64_t na, const uint32_t* b,
  * bigint_mullo: out[i] = a[i] * b[i] mod B^n (B = 2^32), the paper's
  *   multiplication, whose quadratic formula keeps only digits k < n
  *   (Section 5.2).  MFMA-split, computing only the strips below limb n.
+ *   Small batches split each product's bands over work-groups as
+ *   bigint_mul's do (same condition, workspace and bytes).
  *   a, b, out: batch*n limbs; 1 <= n <= BIGINT_MFMA_MAX_LIMBS; out must not
  *   overlap a or b.
  * bigint_add6: the 6-Add benchmark (Table tab-add): six dependent additions

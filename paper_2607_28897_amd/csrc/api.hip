@@ -227,6 +227,24 @@ static bool mfma_fits(int64_t na, int64_t nb, MfmaCfg cfg) {
          mfma_lds((int)na, (int)nb, cfg) <= 163840;
 }
 
+// a configuration forced on this thread keeps one work-group per instance
+static bool split_forced() { return t_cfg_P || t_cfg_waves || t_cfg_dw || t_cfg_tile; }
+
+// products of a small batch with each product's bands split over `parts`
+// work-groups: carry words in a stream-ordered workspace, two launches
+static int mul_split(uint32_t* out, const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb, int nout,
+                     int64_t batch, int dw, int parts, int wstride, hipStream_t s) {
+  void* ws = nullptr;
+  hipError_t e = hipMallocAsync(&ws, (size_t)batch * wstride * 8, s);
+  if (e != hipSuccess) { set_hip_error(e); return BIGINT_ENOMEM; }
+  const int rc = launch_mul_mfma_split(out, a, na, b, nb, nout, batch, dw, parts,
+                                       reinterpret_cast<uint64_t*>(ws), wstride, s);
+  e = hipFreeAsync(ws, s);
+  if (rc != BIGINT_OK) return rc;
+  if (e != hipSuccess) { set_hip_error(e); return BIGINT_EHIP; }
+  return BIGINT_OK;
+}
+
 int bigint_mul(uint32_t* out, const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb,
                int64_t batch, int algo, void* stream) {
   if (!out || !a || !b || na <= 0 || nb <= 0 || batch < 0) return BIGINT_EINVAL;
@@ -265,20 +283,10 @@ int bigint_mul(uint32_t* out, const uint32_t* a, int64_t na, const uint32_t* b, 
     // fewer instances than CUs and no configuration forced: each product's
     // bands split over several work-groups
     int wstride = 0;
-    const bool forced = t_cfg_P || t_cfg_waves || t_cfg_dw || t_cfg_tile;
-    const int parts = forced ? 1 : mul_mfma_split_parts((int)na, (int)nb, batch, cfg.dw, &wstride);
-    if (parts > 1) {
-      hipStream_t s = (hipStream_t)stream;
-      void* ws = nullptr;
-      hipError_t e = hipMallocAsync(&ws, (size_t)batch * wstride * 8, s);
-      if (e != hipSuccess) { set_hip_error(e); return BIGINT_ENOMEM; }
-      const int rc = launch_mul_mfma_split(out, a, na, b, nb, batch, cfg.dw, parts,
-                                           reinterpret_cast<uint64_t*>(ws), wstride, s);
-      e = hipFreeAsync(ws, s);
-      if (rc != BIGINT_OK) return rc;
-      if (e != hipSuccess) { set_hip_error(e); return BIGINT_EHIP; }
-      return BIGINT_OK;
-    }
+    const int nout = (int)(na + nb);
+    const int parts = split_forced() ? 1 : mul_mfma_split_parts((int)na, (int)nb, nout, batch, cfg.dw, &wstride);
+    if (parts > 1)
+      return mul_split(out, a, na, b, nb, nout, batch, cfg.dw, parts, wstride, (hipStream_t)stream);
     return launch_mul_mfma(out, nullptr, a, na, b, nb, batch, cfg, (hipStream_t)stream);
   }
   if (na + nb > 32768) return BIGINT_EUNSUPPORTED;
@@ -291,9 +299,9 @@ int bigint_mfma_split_parts(int64_t na, int64_t nb, int64_t batch, int* parts) {
   *parts = 1;
   if (na > BIGINT_MFMA_MAX_LIMBS || nb > BIGINT_MFMA_MAX_LIMBS) return BIGINT_OK;
   const MfmaCfg cfg = uniform_mfma_cfg((int)na, (int)nb, batch, false);
-  if (!mfma_fits(na, nb, cfg) || t_cfg_P || t_cfg_waves || t_cfg_dw || t_cfg_tile) return BIGINT_OK;
+  if (!mfma_fits(na, nb, cfg) || split_forced()) return BIGINT_OK;
   int wstride = 0;
-  *parts = mul_mfma_split_parts((int)na, (int)nb, batch, cfg.dw, &wstride);
+  *parts = mul_mfma_split_parts((int)na, (int)nb, (int)(na + nb), batch, cfg.dw, &wstride);
   return BIGINT_OK;
 }
 
@@ -306,6 +314,9 @@ int bigint_mullo(uint32_t* out, const uint32_t* a, const uint32_t* b, int64_t n,
   const MfmaCfg cfg = uniform_mfma_cfg((int)n, (int)n, batch, true);
   if (!mfma_fits(n, n, cfg)) return BIGINT_EUNSUPPORTED;
   if (batch == 0) return BIGINT_OK;
+  int wstride = 0;
+  const int parts = split_forced() ? 1 : mul_mfma_split_parts((int)n, (int)n, (int)n, batch, cfg.dw, &wstride);
+  if (parts > 1) return mul_split(out, a, n, b, n, (int)n, batch, cfg.dw, parts, wstride, (hipStream_t)stream);
   return launch_mul_mfma(out, nullptr, a, n, b, n, batch, cfg, (hipStream_t)stream, (int)n);
 }
 
@@ -587,8 +598,9 @@ static int plan_build_mul(bigint_plan_s* p) {
         wmax = std::max(wmax, w);
         lmax = std::max(lmax, l);
       }
-      const int parts = (int)std::min<int64_t>((R + k.count - 1) / k.count, ((w0 + 3) / 4) / 4);
-      if (parts < 4 || lmax > 163840) continue;
+      const int nb0 = (w0 + 3) / 4;   // 4-strip bands of the largest instance
+      const int parts = (int)std::min<int64_t>((R + k.count - 1) / k.count, nb0 / 4);
+      if (nb0 < 32 || parts < 4 || lmax > 163840) continue;
       k.parts = parts;
       k.wstride = wmax;
       k.split_lds = lmax;

@@ -28,10 +28,10 @@ int launch_addsub(bool sub, uint32_t* out, uint32_t* cout, const uint32_t* a, co
                   int64_t n, int64_t batch, hipStream_t s);
 int launch_mul_plain(uint32_t* out, const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb,
                      int64_t batch, hipStream_t s);
-// full products of fewer instances than CUs, bands split over work-groups
-int mul_mfma_split_parts(int na, int nb, int64_t batch, int dw, int* wstride);
+// products (mod B^nout) of fewer instances than CUs, bands split over work-groups
+int mul_mfma_split_parts(int na, int nb, int nout, int64_t batch, int dw, int* wstride);
 int launch_mul_mfma_split(uint32_t* out, const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb,
-                          int64_t batch, int dw, int nparts, uint64_t* ws, int wstride,
+                          int nout, int64_t batch, int dw, int nparts, uint64_t* ws, int wstride,
                           hipStream_t s);
 int launch_mul_mfma(uint32_t* out, int32_t* coef, const uint32_t* a, int64_t na,
                     const uint32_t* b, int64_t nb, int64_t batch, MfmaCfg cfg, hipStream_t s,

@@ -357,36 +357,36 @@ constexpr int kSplitP = 4, kSplitWaves = 4;
 template <int DW>
 __global__ __launch_bounds__(64 * kSplitWaves) void k_mul_mfma_part(uint32_t* out, const uint32_t* a,
                                                                    int na, const uint32_t* b, int nb,
-                                                                   uint64_t* ws, int wstride,
+                                                                   int nout, uint64_t* ws, int wstride,
                                                                    int nparts) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
   const int64_t inst = blockIdx.y;
-  const int nout = na + nb;
   mfma::wg_mul_mfma<DW, kSplitP>(out + inst * (int64_t)nout, nullptr, a + inst * (int64_t)na, na,
                                  b + inst * (int64_t)nb, nb, smem, nout, 0, (int)blockIdx.x, nparts,
                                  ws + inst * (int64_t)wstride);
 }
 
 template <int DW>
-__global__ __launch_bounds__(1024) void k_mul_mfma_close(uint32_t* out, int na, int nb,
+__global__ __launch_bounds__(1024) void k_mul_mfma_close(uint32_t* out, int na, int nb, int nout,
                                                          const uint64_t* ws, int wstride) {
   __shared__ uint32_t scratch[32];
   const int64_t inst = blockIdx.x;
-  const int nout = na + nb;
   const mfma::Geo g = mfma::make_geo<DW>(na, nb, nout);
   mfma::close_strips<DW>(out + inst * (int64_t)nout, g, ws + inst * (int64_t)wstride, 0, scratch);
 }
 
-// Parts per instance for a full na x nb product over `batch` instances (1:
+// Parts per instance for an na x nb product (mod B^nout) over `batch` instances (1:
 // no split): enough work-groups for every CU once, at least four bands per
-// part, and at least four parts (with two, the parts' 4-strip bands on 4
-// waves lose more than the second CU gains: 128 products of 2^19 bits
-// 0.54 -> 0.70 ms, 64 of 2^15 bits 17 -> 31 us; with four or more,
-// 2^19 bits: 1 or 4 products 0.52 -> 0.127 ms, 16 products 0.52 -> 0.19,
-// 64 products 0.53 -> 0.39; 2^17 bits, 1 or 16 products 0.053 -> 0.041);
+// part, at least four parts and at least 32 bands (128 strips): with two
+// parts, or four thin ones, the parts' 4-strip bands on 4 waves lose more
+// than the extra CUs gain (128 products of 2^19 bits 0.54 -> 0.70 ms, 64 of
+// 2^15 bits 17 -> 31 us, one 4096-limb product mod B^n 36 -> 37 us); with
+// four or more, 2^19 bits: 1 or 4 products 0.52 -> 0.127 ms, 16 products
+// 0.52 -> 0.19, 64 products 0.53 -> 0.39; 2^17 bits, 1 or 16 products
+// 0.053 -> 0.041; products mod B^n of 2^19 bits, 1 or 16: 0.29 -> 0.115);
 // *wstride = strips per instance (carry words of workspace each).
-int mul_mfma_split_parts(int na, int nb, int64_t batch, int dw, int* wstride) {
-  const int W = dw == 8 ? mfma::make_geo<8>(na, nb, na + nb).W : mfma::make_geo<7>(na, nb, na + nb).W;
+int mul_mfma_split_parts(int na, int nb, int nout, int64_t batch, int dw, int* wstride) {
+  const int W = dw == 8 ? mfma::make_geo<8>(na, nb, nout).W : mfma::make_geo<7>(na, nb, nout).W;
   *wstride = W;
   const int R = num_cus();
   if (batch <= 0 || batch >= R) return 1;
@@ -394,6 +394,7 @@ int mul_mfma_split_parts(int na, int nb, int64_t batch, int dw, int* wstride) {
                              : mfma::lds_bytes<7>(na, nb, kSplitWaves, kSplitP);
   if (lds > 163840) return 1;
   const int NB = (W + kSplitP - 1) / kSplitP;
+  if (NB < 32) return 1;
   const int k = (int)std::min<int64_t>((R + batch - 1) / batch, NB / 4);
   return k >= 4 ? k : 1;
 }
@@ -411,7 +412,7 @@ void ragged_split_geo(int na, int nb, int dw, int* strips, size_t* lds) {
 }
 
 int launch_mul_mfma_split(uint32_t* out, const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb,
-                          int64_t batch, int dw, int nparts, uint64_t* ws, int wstride,
+                          int nout, int64_t batch, int dw, int nparts, uint64_t* ws, int wstride,
                           hipStream_t s) {
   const int W = wstride;
   const unsigned close_threads = (unsigned)std::min(1024, (W + 63) / 64 * 64);
@@ -421,19 +422,19 @@ int launch_mul_mfma_split(uint32_t* out, const uint32_t* a, int64_t na, const ui
     BI_HIP(hipFuncSetAttribute((const void*)k_mul_mfma_part<8>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)lds));
     hipLaunchKernelGGL(k_mul_mfma_part<8>, gp, dim3(64 * kSplitWaves), lds, s, out, a, (int)na, b,
-                       (int)nb, ws, wstride, nparts);
+                       (int)nb, nout, ws, wstride, nparts);
     BI_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_mul_mfma_close<8>, dim3((unsigned)batch), dim3(close_threads), 0, s, out,
-                       (int)na, (int)nb, ws, wstride);
+                       (int)na, (int)nb, nout, ws, wstride);
   } else {
     const size_t lds = mfma::lds_bytes<7>((int)na, (int)nb, kSplitWaves, kSplitP);
     BI_HIP(hipFuncSetAttribute((const void*)k_mul_mfma_part<7>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)lds));
     hipLaunchKernelGGL(k_mul_mfma_part<7>, gp, dim3(64 * kSplitWaves), lds, s, out, a, (int)na, b,
-                       (int)nb, ws, wstride, nparts);
+                       (int)nb, nout, ws, wstride, nparts);
     BI_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_mul_mfma_close<7>, dim3((unsigned)batch), dim3(close_threads), 0, s, out,
-                       (int)na, (int)nb, ws, wstride);
+                       (int)na, (int)nb, nout, ws, wstride);
   }
   BI_LAUNCH_CHECK();
   return BIGINT_OK;

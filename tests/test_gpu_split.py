@@ -24,8 +24,8 @@ def bi():
 
 # (batch, na, nb): one 2^19-bit product, the largest operands, unequal
 # operands, ragged strip counts, and batches up to a quarter of the CU count
-CASES = [(1, 16384, 16384), (1, 18432, 18432), (2, 16384, 1000), (3, 5000, 5000), (7, 4096, 3001),
-         (17, 2048, 2048), (60, 3000, 2000), (64, 4096, 4096), (64, 16384, 16384),
+CASES = [(1, 16384, 16384), (1, 18432, 18432), (2, 16384, 1000), (3, 5000, 5000), (7, 4096, 4100),
+         (17, 4096, 4096), (60, 5000, 3500), (64, 4096, 4096), (64, 16384, 16384),
          (1, 16384, 1), (3, 2, 12000)]
 
 
@@ -82,7 +82,7 @@ def test_split_seven_bit_digits_from_table(bi, orc, tmp_path):
     bi.autotune_load(path)
     try:
         g = np.random.default_rng(77)
-        for batch, n in ((1, 16000), (5, 3333)):
+        for batch, n in ((1, 16000), (5, 5000)):
             a = rand_limbs(g, batch, n)
             b = rand_limbs(g, batch, n)
             assert bi.mfma_config(n, n)[2] == 7 and bi.mfma_split_parts(n, n, batch) >= 4
@@ -102,8 +102,31 @@ def test_split_parts_query(bi):
     assert bi.mfma_split_parts(16384, 16384, 64) == 4     # the CUs once
     assert bi.mfma_split_parts(16384, 16384, 128) == 1    # two parts: not split
     assert bi.mfma_split_parts(1024, 1024, 64) == 1
+    assert bi.mfma_split_parts(2048, 2048, 1) == 1         # 64 strips: too few bands
     bi.set_mfma_config(0, 4, 0)
     try:
         assert bi.mfma_split_parts(16384, 16384, 1) == 1
     finally:
         bi.set_mfma_config(0, 0, 0)
+
+
+@pytest.mark.parametrize("batch,n", [(1, 16384), (1, 18432), (3, 9000), (16, 8192), (64, 16384)])
+def test_split_products_mod_b_n(bi, orc, batch, n):
+    """bigint_mullo (a b mod B^n) on the split path: only the strips below
+    limb n, every instance against the oracle and against the bytes of one
+    work-group per instance (configuration forced)."""
+    g = np.random.default_rng(batch + n)
+    a = rand_limbs(g, batch, n)
+    b = rand_limbs(g, batch, n)
+    a[0] = 0xFFFFFFFF
+    b[0] = 0xFFFFFFFF                    # (B^n - 1)^2 mod B^n = 1
+    p = host(bi.mullo(dev(a), dev(b)))
+    want = oracle_map(lambda i: orc.mullo1(a[i], b[i]), range(batch))
+    assert all(np.array_equal(p[i], want[i]) for i in range(batch))
+    P, w, d = bi.mfma_config(n, n)
+    bi.set_mfma_config(P, 0, 0)
+    try:
+        forced = host(bi.mullo(dev(a), dev(b)))
+    finally:
+        bi.set_mfma_config(0, 0, 0)
+    assert np.array_equal(p, forced)
