@@ -961,9 +961,11 @@ int bigint_autotune(const char* cache_path, int flags) {
   int rc = BIGINT_OK;
   for (size_t bi_ = 0; bi_ < sizeof(kBins) / sizeof(kBins[0]) && rc == BIGINT_OK; ++bi_) {
     const int n = kBins[bi_];
-    // enough instances to fill every CU several times at the small sizes
+    // enough instances to fill every CU several times: at least four per CU
+    // (with fewer, configurations that fit two work-groups per CU leave
+    // slots empty and lose to one-per-CU ones they beat on full batches)
     const double r = 16384.0 / n;
-    const int nb = num_cus() * std::max(1, (int)(r * r / 8));
+    const int nb = num_cus() * std::max(4, (int)(r * r / 8));
     const size_t in_bytes = (size_t)nb * n * 4, out_bytes = (size_t)nb * 2 * n * 4;
     uint32_t *a = nullptr, *b = nullptr, *out = nullptr;
     if (hipMalloc(&a, in_bytes) != hipSuccess || hipMalloc(&b, in_bytes) != hipSuccess ||
