@@ -26,9 +26,13 @@ struct TuneEntry {
   int tile = 16;  // MFMA tile (16 or 32)
 };
 static std::mutex g_tune_mu;
-// (waves 1: one wave per instance, four instances per work-group)
+// (waves 1: one wave per instance, four instances per work-group).  8
+// strips on 8 waves run up to 8,676 limbs, the largest size whose LDS fits
+// two such work-groups on a CU; above it, with one work-group per CU either
+// way, 16 strips win (1024 products of 9,000 / 10,000 limbs: 0.599 / 0.615
+// of the int8 peak against 0.583 / 0.600).
 static const std::vector<TuneEntry> kBuiltinTune = {
-    {512, 4, 1, 8}, {1448, 8, 1, 8}, {2896, 8, 4, 8}, {5792, 8, 8, 8}, {11585, 8, 8, 8},
+    {512, 4, 1, 8}, {1448, 8, 1, 8}, {2896, 8, 4, 8}, {5792, 8, 8, 8}, {8676, 8, 8, 8},
     {BIGINT_MFMA_MAX_LIMBS, 16, 8, 8}};
 static std::vector<TuneEntry> g_tune = kBuiltinTune;
 
