@@ -113,12 +113,13 @@ __host__ __device__ inline Geo make_geo(int na, int nb, int nout = -1) {
 __host__ __device__ inline int bs_bytes(const Geo& g) { return (4 * (g.NBa + g.NBb + 2) + 15) & ~15; }
 
 // LDS layout: [Abuf SA][Bbuf SB][per-wave scratch 1 KiB each][strip carries
-// 8W][band order 2*NB][misc 128][block prefix sums (8-bit digits)]
+// 8W][with lead (8-bit digits): every strip's limbs 0-1, 8W][band order
+// 2*NB][misc 128][block prefix sums (8-bit digits)]
 template <int DW, int TS = 16>
-__host__ __device__ inline size_t lds_bytes(int na, int nb, int nwaves, int P) {
+__host__ __device__ inline size_t lds_bytes(int na, int nb, int nwaves, int P, bool lead = false) {
   const Geo g = make_geo<DW, TS>(na, nb);
   const int NB = (g.W + P - 1) / P;
-  return (size_t)g.SA + g.SB + (size_t)nwaves * 1024 + (size_t)8 * g.W +
+  return (size_t)g.SA + g.SB + (size_t)nwaves * 1024 + (size_t)((DW == 8 && lead) ? 16 : 8) * g.W +
          (size_t)((2 * NB + 15) & ~15) + 128 + (DW == 8 ? bs_bytes(g) : 0);
 }
 
@@ -128,13 +129,18 @@ struct Lds {
   int32_t* wscr;     // this wave's 256 ints
   int32_t* scr;      // all waves' scratch (256 ints per wave)
   uint64_t* carry;   // W words
+  uint64_t* lead = nullptr;  // nullable, W words: limbs 0-1 of every strip as its output wrote
+                             // them, so the closing scan need not read them back from out
   uint16_t* order;   // NB entries
   uint32_t* misc;    // [0] band counter, [1..16] scan scratch (32 words)
   int32_t* bsa;      // 8-bit digits: bsa[b] = sum of alpha'_i, i < 256 b (b <= NBa)
   int32_t* bsb;      // the same for beta' (b <= NBb)
 };
 
-__device__ __forceinline__ Lds carve(char* smem, const Geo& g, int P) {
+// lead: carve the strips' limbs 0-1 area (8-bit digits; the LDS must have
+// been sized by lds_bytes with lead)
+template <int DW>
+__device__ __forceinline__ Lds carve(char* smem, const Geo& g, int P, bool lead) {
   Lds s;
   const int NB = (g.W + P - 1) / P;
   char* p = smem;
@@ -143,6 +149,10 @@ __device__ __forceinline__ Lds carve(char* smem, const Geo& g, int P) {
   s.scr = reinterpret_cast<int32_t*>(p);
   s.wscr = s.scr + wave_id() * 256; p += num_waves() * 1024;
   s.carry = reinterpret_cast<uint64_t*>(p); p += 8 * g.W;
+  if (DW == 8 && lead) {
+    s.lead = reinterpret_cast<uint64_t*>(p);
+    p += 8 * g.W;
+  }
   s.order = reinterpret_cast<uint16_t*>(p); p += (2 * NB + 15) & ~15;
   s.misc = reinterpret_cast<uint32_t*>(p); p += 128;
   s.bsa = reinterpret_cast<int32_t*>(p);
@@ -621,6 +631,7 @@ __device__ __forceinline__ int strip_out8(v4i acc, int w, const Lds& s, const Ge
   const uint64_t tail = ~3ull;   // limbs 2..63
   const uint64_t ones = __ballot(jg >= g.nout || limb == 0xffffffffu);
   if (jg < g.nout) out[jg] = limb;
+  if (s.lead && lane < 2) reinterpret_cast<uint32_t*>(s.lead)[2 * w + lane] = jg < g.nout ? limb : 0u;
   if (lane == 63) {
     const uint32_t cout = (uint32_t)gb | ((uint32_t)pb & cin);
     s.carry[w] = (uint64_t)(H + cout) | ((uint64_t)((ones & tail) == tail) << 63);
@@ -789,10 +800,12 @@ __device__ __forceinline__ void run_band(int band, const Lds& s, const Geo& g, u
 
 // The closing strip carry scan of an instance (whole work-group): carry[w]
 // holds strip w's carry word (bits 0-62) and tail flag (bit 63), out its
-// limbs, strips from w_first up; scratch: >= 16 words of LDS.
+// limbs, strips from w_first up; scratch: >= 16 words of LDS.  lead
+// (nullable, LDS): lead[w] = strip w's limbs 0-1 as written to out, read
+// there instead of from out.
 template <int DW>
 __device__ __forceinline__ void close_strips(uint32_t* out, const Geo& g, const uint64_t* carry, int w_first,
-                                             uint32_t* scratch) {
+                                             uint32_t* scratch, const uint64_t* lead = nullptr) {
   constexpr int kStripLimbs = strip_limbs<DW>();
   // out += sum_w C_w B^(L(w+1)), L limbs per strip.  Strip w' receives C_{w'-1} (< 2^35) on its
   // limbs 0 and 1; a carry out of limb 1 runs on only through a tail of
@@ -806,11 +819,16 @@ __device__ __forceinline__ void close_strips(uint32_t* out, const Geo& g, const 
     const int w = base + threadIdx.x;
     const bool valid = w < g.W;
     const int j0 = kStripLimbs * (valid ? w : 0);
-    const uint32_t l0 = (valid && j0 < g.nout) ? out[j0] : 0u;
-    const uint32_t l1 = (valid && j0 + 1 < g.nout) ? out[j0 + 1] : 0u;
+    uint64_t x0;
+    if (lead) {
+      x0 = valid ? lead[w] : 0ull;
+    } else {
+      const uint32_t l0 = (valid && j0 < g.nout) ? out[j0] : 0u;
+      const uint32_t l1 = (valid && j0 + 1 < g.nout) ? out[j0 + 1] : 0u;
+      x0 = ((uint64_t)l1 << 32) | l0;
+    }
     const uint64_t d = (valid && w > w_first) ? (carry[w - 1] & kC) : 0ull;
     const bool ones = valid && (carry[w] >> 63);
-    const uint64_t x0 = ((uint64_t)l1 << 32) | l0;
     const uint64_t x = x0 + d;
     const bool xh = x < x0;  // carry out of limb 1
     const bool gen = valid && xh && ones;
@@ -859,14 +877,18 @@ __host__ __device__ inline int high_band(int nlo, int P) {
 // carry words to carry_ext[w] (global memory, one word per strip) instead of
 // LDS and leaves the closing strip carry scan to close_strips once every
 // part has finished (a later launch).
+// lead (8-bit digits, whole instance; smem sized by lds_bytes with lead):
+// every strip's limbs 0-1 are also kept in LDS, where the closing scan reads
+// them instead of reading them back from out.
 template <int DW, int P, int TS = 16>
 __device__ __forceinline__ void wg_mul_mfma(uint32_t* out, int32_t* coef, const uint32_t* __restrict__ a, int na,
                             const uint32_t* __restrict__ b, int nb, char* smem, int nout = -1,
-                            int nlo = 0, int part = 0, int nparts = 1, uint64_t* carry_ext = nullptr) {
+                            int nlo = 0, int part = 0, int nparts = 1, uint64_t* carry_ext = nullptr,
+                            bool lead = false) {
   static_assert(DW == 7 || DW == 8, "digit width");
   static_assert(TS == 16 || (TS == 32 && DW == 8 && P % 4 == 0), "32x32 tiles: 8-bit digits, whole tiles per band");
   const Geo g = make_geo<DW, TS>(na, nb, coef ? -1 : nout);
-  Lds s = carve(smem, g, P);
+  Lds s = carve<DW>(smem, g, P, lead && coef == nullptr && nparts == 1);
   if (nparts > 1) s.carry = carry_ext;
   const int NBall = (g.W + P - 1) / P;
   // bands [band_lo, NBall) are computed; strips from w_first up
@@ -931,7 +953,7 @@ __device__ __forceinline__ void wg_mul_mfma(uint32_t* out, int32_t* coef, const 
     else run_band<DW, P>(band, s, g, out, coef);
   }
   __syncthreads();
-  if (coef == nullptr && nparts == 1) close_strips<DW>(out, g, s.carry, w_first, s.misc + 1);
+  if (coef == nullptr && nparts == 1) close_strips<DW>(out, g, s.carry, w_first, s.misc + 1, s.lead);
   __syncthreads();
 }
 

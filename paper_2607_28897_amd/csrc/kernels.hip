@@ -289,16 +289,17 @@ int launch_mul_plain(uint32_t* out, const uint32_t* a, int64_t na, const uint32_
 // ============================================================================
 // MFMA-split multiply: one work-group per instance
 // ============================================================================
-// out instance i = a_i * b_i mod B^nout (nout = na + nb: the whole product)
+// out instance i = a_i * b_i mod B^nout (nout = na + nb: the whole product);
+// lead != 0: the LDS holds every strip's limbs 0-1 (see wg_mul_mfma)
 template <int DW, int P, int TS>
 __global__ __launch_bounds__(512) void k_mul_mfma(uint32_t* out, int32_t* coef, const uint32_t* a,
-                                                  int na, const uint32_t* b, int nb, int nout) {
+                                                  int na, const uint32_t* b, int nb, int nout, int lead) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
   const int64_t inst = blockIdx.x;
   const int K = mfma::ndigits(na) + mfma::ndigits(nb) - 1;
   mfma::wg_mul_mfma<DW, P, TS>(out ? out + inst * (int64_t)nout : nullptr,
                            coef ? coef + inst * (int64_t)K : nullptr, a + inst * (int64_t)na, na,
-                           b + inst * (int64_t)nb, nb, smem, nout);
+                           b + inst * (int64_t)nb, nb, smem, nout, 0, 0, 1, nullptr, lead != 0);
 }
 
 // LDS of the work-group kernel (waves == 1, one wave per instance, is sized
@@ -314,12 +315,18 @@ template <int DW, int P, int TS = 16>
 static int launch_mfma_p(uint32_t* out, int32_t* coef, const uint32_t* a, int64_t na,
                          const uint32_t* b, int64_t nb, int64_t batch, int waves, int nout,
                          hipStream_t s) {
-  const size_t lds = mfma::lds_bytes<DW, TS>((int)na, (int)nb, waves, P);
+  size_t lds = mfma::lds_bytes<DW, TS>((int)na, (int)nb, waves, P);
   if (lds > 163840) return BIGINT_EUNSUPPORTED;
+  // keep the strips' limbs 0-1 in LDS for the closing scan (no read-back from
+  // global memory) where the extra 8 bytes per strip fit without costing a
+  // resident work-group per CU
+  const size_t lds_lead = mfma::lds_bytes<DW, TS>((int)na, (int)nb, waves, P, true);
+  const int lead = DW == 8 && coef == nullptr && lds_lead <= 163840 && 163840 / lds_lead == 163840 / lds;
+  if (lead) lds = lds_lead;
   BI_HIP(hipFuncSetAttribute((const void*)k_mul_mfma<DW, P, TS>,
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   hipLaunchKernelGGL((k_mul_mfma<DW, P, TS>), dim3((unsigned)batch), dim3(64 * waves), lds, s, out,
-                     coef, a, (int)na, b, (int)nb, nout);
+                     coef, a, (int)na, b, (int)nb, nout, lead);
   BI_LAUNCH_CHECK();
   return BIGINT_OK;
 }

@@ -235,6 +235,40 @@ def test_products_with_long_all_ones_runs(bi, orc, algo, n, m):
         assert np.array_equal(p[i], orc.mul1(a[i], b[i])), i
 
 
+def test_closing_scan_limbs_from_lds_or_global(bi, orc):
+    """The closing strip carry scan takes every strip's limbs 0-1 from LDS in
+    the uniform kernel where they fit (2^19 bits) and from global memory in a
+    ragged plan's split segment: the same bytes, with carries that run through
+    whole strips (all-ones operands, (B^n - 1) * small) included."""
+    import torch
+    n = 16384
+    g = np.random.default_rng(1921)
+    a = rand_limbs(g, 4, n)
+    b = rand_limbs(g, 4, n)
+    a[0] = 0xFFFFFFFF
+    b[0] = 0xFFFFFFFF
+    a[1] = 0xFFFFFFFF
+    b[1, 1:] = 0
+    b[1, 0] = 7
+    a[2, : n // 2] = 0xFFFFFFFF
+    bi.set_mfma_config(0, 0, 8)   # a forced configuration: the uniform kernel, not split
+    try:
+        uni = host(bi.mul(dev(a), dev(b), bi.MUL_MFMA))
+    finally:
+        bi.set_mfma_config(0, 0, 0)
+    lens = np.full(4, n, np.int64)
+    off = np.arange(5, dtype=np.int64) * n
+    plan = bi.MulPlan(lens, lens)
+    assert plan.segments()[0]["parts"] > 1
+    out, oo = plan(dev(a.reshape(-1)), torch.from_numpy(off).cuda(), dev(b.reshape(-1)),
+                   torch.from_numpy(off).cuda())
+    rag = host(out).reshape(4, 2 * n)
+    plan.close()
+    assert np.array_equal(uni, rag)
+    want = oracle_map(lambda i: orc.mul1(a[i], b[i]), range(4))
+    assert all(np.array_equal(uni[i], want[i]) for i in range(4))
+
+
 @pytest.mark.parametrize("dw,n", [(7, 16397), (8, 18432), (0, 18432)])
 def test_largest_supported_size(bi, orc, dw, n):
     # 16,397 limbs: the largest 7-bit-digit operands whose digits fit the LDS
