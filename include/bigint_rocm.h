@@ -301,7 +301,11 @@ int bigint_divmod_ragged(uint32_t* q, const int64_t* q_off, uint32_t* r,
  * writes the table as JSON to `cache_path` (host path; NULL = do not write).
  * Later plans use the table.  bigint_autotune_load reads such a file (a
  * NULL path restores the built-in table).  All candidates produce identical
- * bytes; the table only affects speed. */
+ * bytes; the table only affects speed.
+ * Environment: BIGINT_TUNE_CACHE=<path> loads such a table once, before the
+ * library's first table lookup (a later bigint_autotune or
+ * bigint_autotune_load replaces it); a file that does not parse leaves the
+ * built-in table (bigint_autotune_load on the same path reports why). */
 int bigint_autotune(const char* cache_path, int flags);
 int bigint_autotune_load(const char* cache_path);
 

@@ -1,6 +1,7 @@
 // api.hip -- the C-ABI entry points: argument checks, dispatch, plans.
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <numeric>
@@ -36,10 +37,24 @@ static const std::vector<TuneEntry> kBuiltinTune = {
     {BIGINT_MFMA_MAX_LIMBS, 16, 8, 8}};
 static std::vector<TuneEntry> g_tune = kBuiltinTune;
 
+static int load_tune_file(const char* path);
+
+// A table named by the environment variable BIGINT_TUNE_CACHE is loaded once,
+// before the first lookup and before any table a caller loads or tunes (so
+// those replace it); a file that does not parse leaves the built-in table.
+static void tune_env_once() {
+  static std::once_flag once;
+  std::call_once(once, [] {
+    const char* path = std::getenv("BIGINT_TUNE_CACHE");
+    if (path && *path) (void)load_tune_file(path);
+  });
+}
+
 // The tuned configuration for this size; when its LDS does not fit (7-bit
 // digits near the top of the range) the same tiles with 8-bit digits, which
 // need 8/7 fewer bytes per operand.
 MfmaCfg default_mfma_cfg(int na, int nb) {
+  tune_env_once();
   const int n = std::max(na, nb);
   MfmaCfg c{16, 8, 8};
   {
@@ -951,6 +966,7 @@ int bigint_diag_mad_rate(uint64_t* scratch, int64_t blocks, int64_t iters, void*
 
 int bigint_autotune(const char* cache_path, int flags) {
   (void)flags;
+  tune_env_once();
   static const int kBins[] = {128, 256, 512, 1024, 2048, 4096, 8192, 16384};
   static const int kP[] = {4, 8, 16, 32};
   static const int kW[] = {1, 4, 8};
@@ -1086,11 +1102,20 @@ int bigint_autotune(const char* cache_path, int flags) {
 // Reads a table written by bigint_autotune (the fields are read in order);
 // a null path restores the built-in table.
 int bigint_autotune_load(const char* cache_path) {
+  tune_env_once();
   if (!cache_path) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune = kBuiltinTune;
     return BIGINT_OK;
   }
+  return load_tune_file(cache_path);
+}
+
+}  // extern "C"
+
+namespace bi {
+
+static int load_tune_file(const char* cache_path) {
   FILE* f = fopen(cache_path, "r");
   if (!f) return BIGINT_EINVAL;
   std::string txt;
@@ -1134,4 +1159,4 @@ int bigint_autotune_load(const char* cache_path) {
   return BIGINT_OK;
 }
 
-}  // extern "C"
+}  // namespace bi

@@ -168,3 +168,27 @@ def test_tune_table_tile_field(bi, tmp_path):
                          "tile": 16}]}, open(bad, "w"))
     with pytest.raises(bi.BigIntError):
         bi.autotune_load(bad)
+
+
+def test_tune_table_from_environment(tmp_path):
+    # host-side only, in a fresh process: BIGINT_TUNE_CACHE names a table
+    # loaded before the first lookup; bigint_autotune_load(NULL) still
+    # restores the built-in one, and a file that does not parse leaves it
+    import json
+    import subprocess
+    import sys
+    if not os.path.exists(os.path.join(ROOT, "paper_2607_28897_amd", "_lib", "libbigint_rocm.so")):
+        pytest.skip("library not built")
+    good = str(tmp_path / "env.json")
+    json.dump({"bins": [{"max_limbs": 18432, "strips_per_band": 8, "waves": 4, "digit_bits": 7}]},
+              open(good, "w"))
+    bad = str(tmp_path / "bad.json")
+    open(bad, "w").write("{\"bins\": []}")
+    code = ("import sys; sys.path.insert(0, %r); import paper_2607_28897_amd as m; m.lib(); "
+            "a = m.mfma_config(4096, 4096); m.autotune_load(None); print(a, m.mfma_config(4096, 4096))" % ROOT)
+    for path, first in ((good, "(8, 4, 7)"), (bad, "(8, 8, 8)")):
+        env = dict(os.environ, BIGINT_TUNE_CACHE=path)
+        r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                           timeout=300)
+        assert r.returncode == 0, r.stderr[-2000:]
+        assert r.stdout.split("\n")[-2] == f"{first} (8, 8, 8)", r.stdout
