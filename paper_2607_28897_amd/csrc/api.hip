@@ -1,5 +1,6 @@
 // api.hip -- the C-ABI entry points: argument checks, dispatch, plans.
 #include <algorithm>
+#include <climits>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -1130,7 +1131,11 @@ static int load_tune_file(const char* cache_path) {
     if (q == std::string::npos) return false;
     const size_t c = txt.find(':', q);
     if (c == std::string::npos) return false;
-    *v = atoi(txt.c_str() + c + 1);
+    // a decimal integer of int range (strtol saturates instead of overflowing)
+    char* end = nullptr;
+    const long x = std::strtol(txt.c_str() + c + 1, &end, 10);
+    if (end == txt.c_str() + c + 1 || x < INT_MIN || x > INT_MAX) return false;
+    *v = (int)x;
     pos = c + 1;
     return true;
   };
