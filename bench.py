@@ -219,6 +219,7 @@ def main():
         "vs_baseline": None,
         "dtype": "int8",
         "data": "synthetic",
+        "source_sha": source_sha(),
         "config": {
             "workload": f"{batch} pairs of 2^19-bit integers ({n} u32 limbs), uniform random limbs "
                         f"(seed 1002), full 2^20-bit products, MFMA-split multiply",
@@ -806,6 +807,21 @@ def kernel_sha():
     i = src.index("__global__ __launch_bounds__(512) void k_mul_mfma(")
     j = src.index("// ---- fewer products than CUs", i)
     h.update(src[i:j].encode())
+    return h.hexdigest()[:16]
+
+
+def source_sha():
+    """Hash of every library source and of the C-ABI header: names the build a
+    bench line was measured on (the GPU-side copy of the tree has no git)."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2607_28897_amd", "csrc")
+    for f in sorted(os.listdir(d)) + [os.path.join("..", "..", "include", "bigint_rocm.h")]:
+        path = os.path.join(d, f)
+        if os.path.isfile(path):
+            h.update(f.encode())
+            with open(path, "rb") as fh:
+                h.update(fh.read())
     return h.hexdigest()[:16]
 
 

@@ -55,3 +55,10 @@ def test_traffic_json_fields():
             t["write_size_kib_per_dispatch"] * t["write_scale_from_copy"]) * 1024
     assert abs(t["bytes_per_launch"] - want) <= 1024
     assert all(c.startswith("rocprofv3 --pmc ") for c in t["commands"])
+
+
+def test_source_sha_names_the_sources():
+    b = _bench()
+    h = b.source_sha()
+    assert len(h) == 16 and all(c in "0123456789abcdef" for c in h)
+    assert h == b.source_sha()
