@@ -572,7 +572,7 @@ def divmod_mode(torch, bi, inputs, args):
     g = torch.Generator(device="cuda")
     g.manual_seed(1007)
     rows = []
-    for bits in (2**13, 2**14, 2**15, 2**16, 2**17, 2**18):
+    for bits in (2**13, 2**14, 2**15, 2**16, 2**17, 2**18, 2**19):
         n, insts = bits // 32, 2**32 // bits
         u = _rand_dev(torch, g, insts, n)
         v = _rand_dev(torch, g, insts, n // 2)
