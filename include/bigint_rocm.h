@@ -305,7 +305,11 @@ int bigint_divmod_ragged(uint32_t* q, const int64_t* q_off, uint32_t* r,
  * Environment: BIGINT_TUNE_CACHE=<path> loads such a table once, before the
  * library's first table lookup (a later bigint_autotune or
  * bigint_autotune_load replaces it); a file that does not parse leaves the
- * built-in table (bigint_autotune_load on the same path reports why). */
+ * built-in table (bigint_autotune_load on the same path reports why).
+ * BIGINT_DEBUG=1 prints one line on stderr per configuration the library
+ * picks: each MFMA-split, plain or Karatsuba multiply call (digit width,
+ * tile, strips per band, waves, work-groups per product), each segment of a
+ * ragged multiply plan and each division plan. */
 int bigint_autotune(const char* cache_path, int flags);
 int bigint_autotune_load(const char* cache_path);
 

@@ -19,6 +19,20 @@ void set_hip_error(hipError_t e) { t_last_hip = (int)e; }
 
 static thread_local int t_cfg_P = 0, t_cfg_waves = 0, t_cfg_dw = 0, t_cfg_tile = 0;
 
+// BIGINT_DEBUG (set, and not "0"): one line on stderr per configuration the
+// library picks (multiply calls, plan segments, division launches)
+static bool debug_on() {
+  static const bool on = [] {
+    const char* e = std::getenv("BIGINT_DEBUG");
+    return e && *e && std::strcmp(e, "0") != 0;
+  }();
+  return on;
+}
+#define BI_DEBUG(...)                                  \
+  do {                                                 \
+    if (debug_on()) std::fprintf(stderr, __VA_ARGS__); \
+  } while (0)
+
 // Tile choice per size bin.  The built-in table is what bigint_autotune
 // picked on an MI355X; a table loaded with bigint_autotune_load (or produced
 // by bigint_autotune) replaces it.
@@ -283,6 +297,9 @@ int bigint_mul(uint32_t* out, const uint32_t* a, int64_t na, const uint32_t* b, 
     hc.tile = 16;                      // on 16x16 tiles
     if (!mfma_fits(h, h, hc)) return BIGINT_EUNSUPPORTED;
     if (batch == 0) return BIGINT_OK;
+    BI_DEBUG("bigint: mul %lld x (%lld x %lld limbs): one Karatsuba level, half products of %d limbs "
+             "with %d-bit digits, %d strips per band, %d waves\n",
+             (long long)batch, (long long)na, (long long)nb, h, hc.dw, hc.P, hc.waves);
     hipStream_t s = (hipStream_t)stream;
     void* ws = nullptr;
     hipError_t e = hipMallocAsync(&ws, kara_ws_bytes((int)na, batch), s);
@@ -305,12 +322,18 @@ int bigint_mul(uint32_t* out, const uint32_t* a, int64_t na, const uint32_t* b, 
     int wstride = 0;
     const int nout = (int)(na + nb);
     const int parts = split_forced() ? 1 : mul_mfma_split_parts((int)na, (int)nb, nout, batch, cfg.dw, &wstride);
+    BI_DEBUG("bigint: mul %lld x (%lld x %lld limbs): MFMA-split, %d-bit digits, %dx%d tiles, %d strips "
+             "per band, %d waves, %d work-group(s) per product\n",
+             (long long)batch, (long long)na, (long long)nb, cfg.dw, cfg.tile, cfg.tile,
+             parts > 1 ? 4 : cfg.P, parts > 1 ? 4 : cfg.waves, parts);
     if (parts > 1)
       return mul_split(out, a, na, b, nb, nout, batch, cfg.dw, parts, wstride, (hipStream_t)stream);
     return launch_mul_mfma(out, nullptr, a, na, b, nb, batch, cfg, (hipStream_t)stream);
   }
   if (na + nb > 32768) return BIGINT_EUNSUPPORTED;
   if (batch == 0) return BIGINT_OK;
+  BI_DEBUG("bigint: mul %lld x (%lld x %lld limbs): plain u64 kernel\n", (long long)batch, (long long)na,
+           (long long)nb);
   return launch_mul_plain(out, a, na, b, nb, batch, (hipStream_t)stream);
 }
 
@@ -594,6 +617,9 @@ static int plan_build_mul(bigint_plan_s* p) {
       p->seg_products.push_back(prod);
       p->seg_busy.push_back(fspan > 0.0 ? work / ((double)slots * fspan) : 0.0);
       p->seg_slots.push_back(slots);
+      BI_DEBUG("bigint: plan segment %zu: %d products from queue position %d, %d-bit digits, %d strips "
+               "per band, %d waves, %zu bytes of LDS, %d resident work-groups, modelled busy %.3f\n",
+               cls.size(), k.count, k.first, h.c.dw, h.c.P, k.waves, k.lds, slots, p->seg_busy.back());
       cls.push_back(k);
       pos = end;
     }
@@ -622,6 +648,8 @@ static int plan_build_mul(bigint_plan_s* p) {
       const int parts = (int)std::min<int64_t>((R + k.count - 1) / k.count, nb0 / 4);
       if (nb0 < 32 || parts < 4 || lmax > 163840) continue;
       k.parts = parts;
+      BI_DEBUG("bigint: plan segment of %d products from queue position %d split: %d work-groups per "
+               "product\n", k.count, k.first, parts);
       k.wstride = wmax;
       k.split_lds = lmax;
       k.ws_off = ws_words;
@@ -675,6 +703,10 @@ static int plan_build_div(bigint_plan_s* p) {
   }
   p->grid = div_chunk(p->cap_u, p->cap_v, B);
   p->n_launches = B > 0 ? (B + p->grid - 1) / p->grid : 0;
+  BI_DEBUG("bigint: plan of %lld divisions: dividends up to %d limbs, divisors up to %d, %d threads per "
+           "division, %d per CU, %d per launch\n",
+           (long long)B, p->cap_u, p->cap_v, div_threads(p->cap_u), div_groups_per_cu(p->cap_u, p->cap_v),
+           p->grid);
   if (B > 0) {
     BI_HIP(hipMalloc(&p->d_queue, sizeof(int32_t) * B));
     BI_HIP(hipMemcpy(p->d_queue, q.data(), sizeof(int32_t) * B, hipMemcpyHostToDevice));

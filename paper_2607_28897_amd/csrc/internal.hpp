@@ -109,6 +109,7 @@ int launch_mad_rate(uint64_t* out, int blocks, int iters, hipStream_t s);
 size_t div_ws_bytes(int cap_u, int cap_v, int slots);
 size_t div_lds_bytes(int cap_u, int cap_v);
 int div_groups_per_cu(int cap_u, int cap_v);
+int div_threads(int cap_u);   // threads per division work-group
 int div_chunk(int cap_u, int cap_v, int64_t batch);
 // The allocation-free division's device workspace on the current device:
 // its address (from hipGetSymbolAddress, once per device) and size.

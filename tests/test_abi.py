@@ -192,3 +192,31 @@ def test_tune_table_from_environment(tmp_path):
                            timeout=300)
         assert r.returncode == 0, r.stderr[-2000:]
         assert r.stdout.split("\n")[-2] == f"{first} (8, 8, 8)", r.stdout
+
+
+def test_debug_lines_from_environment():
+    # host-side only, in fresh processes: BIGINT_DEBUG prints one line per
+    # configuration a plan picks (here before the device allocation that a
+    # machine without a GPU then refuses); without it nothing is printed
+    import subprocess
+    import sys
+    if not os.path.exists(os.path.join(ROOT, "paper_2607_28897_amd", "_lib", "libbigint_rocm.so")):
+        pytest.skip("library not built")
+    code = ("import sys; sys.path.insert(0, %r); import numpy as np; import paper_2607_28897_amd as m\n"
+            "m.lib(); la = np.array([1024, 4096, 16384, 3000], np.int64)\n"
+            "for mk in (lambda: m.MulPlan(la, la), lambda: m.DivPlan(la, la // 2)):\n"
+            "    try:\n        mk()\n    except m.BigIntError:\n        pass\n" % ROOT)
+    for flag, want in (("1", True), ("0", False), (None, False)):
+        env = dict(os.environ)
+        env.pop("BIGINT_DEBUG", None)
+        if flag is not None:
+            env["BIGINT_DEBUG"] = flag
+        r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                           timeout=300)
+        assert r.returncode == 0, r.stderr[-2000:]
+        lines = [ln for ln in r.stderr.splitlines() if ln.startswith("bigint: ")]
+        if want:
+            assert any(ln.startswith("bigint: plan segment 0:") for ln in lines), r.stderr[-2000:]
+            assert any(ln.startswith("bigint: plan of 4 divisions:") for ln in lines), r.stderr[-2000:]
+        else:
+            assert not lines, lines
