@@ -199,12 +199,7 @@ def main():
     achieved = ops / (kernel_ms * 1e-3) / 1e12      # TOP/s
     N7 = (32 * n + 6) // 7
     seven = 2.0 * batch * N7 * N7 / (kernel_ms * 1e-3) / 1e12
-    traffic = None
-    if os.path.exists(args.traffic_json):
-        with open(args.traffic_json) as f:
-            t = json.load(f)
-        if t.get("kernel_sha") == kernel_sha():
-            traffic = t.get("bytes_per_launch")
+    traffic = stored_traffic(args.traffic_json, kernel_sha())
 
     line = {
         "metric": METRIC,
@@ -789,6 +784,17 @@ def cpu_oracle_mode(inputs, args):
                     "sample": f"{m} of {batch} (all cores), {k} (one core)"})
         print(json.dumps(out[-1]), flush=True)
     return out
+
+
+def stored_traffic(path, sha):
+    """HBM bytes per launch from counters stored at `path`, or None when there
+    are none or they were taken on other kernel sources than those hashing to
+    `sha`."""
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    return t.get("bytes_per_launch") if t.get("kernel_sha") == sha else None
 
 
 def kernel_sha():

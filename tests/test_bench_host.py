@@ -62,3 +62,14 @@ def test_source_sha_names_the_sources():
     h = b.source_sha()
     assert len(h) == 16 and all(c in "0123456789abcdef" for c in h)
     assert h == b.source_sha()
+
+
+def test_traffic_only_for_the_kernel_it_was_taken_on(tmp_path):
+    # the stored counters hold for the current kernel sources; a record taken
+    # on other sources, or none at all, gives null traffic
+    b = _bench()
+    path = os.path.join(ROOT, "profiles", "mfma_mul_2e19_traffic.json")
+    t = json.load(open(path))
+    assert b.stored_traffic(path, b.kernel_sha()) == t["bytes_per_launch"]
+    assert b.stored_traffic(path, "0" * 16) is None
+    assert b.stored_traffic(str(tmp_path / "none.json"), b.kernel_sha()) is None
